@@ -1,0 +1,196 @@
+"""Oracle global model: assembly, Newton state solve, adjoint solve and sensitivities.
+Test infrastructure only (see oracle/__init__.py).
+
+Constraint convention.  With the free dofs f and the constrained dofs c (values
+s_bar), the constrained system is
+    R~_f(s) = R_f(s),        R~_c(s) = s_c - s_bar_c,
+and its Jacobian is taken with the constrained columns eliminated,
+    J~ = [[J_ff, 0], [0, I]].
+Newton corrections are then zero on c, and the adjoint J~^T lambda = df/ds (with the
+right-hand side zeroed on c) gives lambda_c = 0 and lambda_f = J_ff^-T df/ds_f, the
+adjoint of the problem restricted to the free dofs (Sec. 5.1, adjoint sensitivity
+analysis of eq. optprob).
+"""
+
+import time
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .problem import Mesh, default_constraints, patch_flux, NFIELD, FIELD_P, FIELD_T
+from .material import cone_filter_matrix, ramp_k, ramp_kappa
+from .element import element_residual
+
+CSTEP = 1.0e-30     # complex-step size: derivative exact to round-off
+
+
+class Model:
+    def __init__(self, prm, x, constraints=None, flux=None, src_P=None, src_T=None, gamma=None):
+        """prm: Params; x: raw design per element (E,) in [0, 1].  The filtered density
+        gamma = F x feeds RAMP (if `gamma` is given it is used as is, without a filter)."""
+        self.prm = prm
+        self.mesh = Mesh(prm)
+        self.F = cone_filter_matrix(self.mesh, prm.filter_radius)
+        self.x = np.asarray(x, dtype=float)
+        self.gamma = np.asarray(gamma, dtype=float) if gamma is not None else self.F @ self.x
+        self.k = ramp_k(self.gamma, prm.k_f, prm.k_s, prm.q_c)
+        self.kap = ramp_kappa(self.gamma, prm.kappa_f, prm.kappa_s, prm.q_p)
+        if constraints is None:
+            constraints = default_constraints(self.mesh)
+        self.mask, self.sbar = constraints
+        self.flux = patch_flux(self.mesh, prm) if flux is None else np.asarray(flux, dtype=float)
+        self.src_P, self.src_T = src_P, src_T
+        m = self.mesh
+        self.ndof = m.n_nodes * NFIELD
+        # global dof of local dof (a, f): node * 5 + f, local index a * 5 + f
+        self.ldof = (m.conn[:, :, None] * NFIELD + np.arange(NFIELD)[None, None, :]).reshape(m.n_elems, 8 * NFIELD)
+        self.x0 = m.elem_ijk * m.h
+        self.timing = {}
+
+    # ---------------------------------------------------------------- residual
+    def _elem_rows(self, se, k=None, kap=None):
+        """se: (E, 40) local dofs -> (E, 40) element residual rows (complex-safe)."""
+        v = se.reshape(se.shape[0], 8, NFIELD)
+        k = self.k if k is None else k
+        kap = self.kap if kap is None else kap
+        RP, RT, RU = element_residual(v[:, :, FIELD_P], v[:, :, FIELD_T], v[:, :, 0:3], k, kap, self.prm,
+                                      self.src_P, self.src_T, self.x0)
+        out = np.empty(v.shape, dtype=np.result_type(se, k, kap))
+        out[:, :, 0:3] = RU
+        out[:, :, FIELD_P] = RP
+        out[:, :, FIELD_T] = RT
+        return out.reshape(se.shape[0], 8 * NFIELD)
+
+    def residual_unconstrained(self, s):
+        """R(s) = M(s) s - f of eq. finalsyseq for every row, as (N, 5)."""
+        s = np.asarray(s, dtype=float).reshape(-1)
+        re = self._elem_rows(s[self.ldof])
+        R = np.zeros(self.ndof)
+        np.add.at(R, self.ldof.ravel(), re.ravel())
+        R = R.reshape(-1, NFIELD)
+        R[:, FIELD_T] -= self.flux
+        return R
+
+    def residual(self, s):
+        s = np.asarray(s, dtype=float).reshape(-1, NFIELD)
+        R = self.residual_unconstrained(s)
+        R[self.mask] = s[self.mask] - self.sbar[self.mask]
+        return R
+
+    # ---------------------------------------------------------------- Jacobian
+    def element_jacobians(self, s):
+        """Complex-step element Jacobians Je (E, 40, 40), Je[e, i, j] = d R_e,i / d s_e,j."""
+        s = np.asarray(s, dtype=float).reshape(-1)
+        se = s[self.ldof]
+        E = se.shape[0]
+        Je = np.empty((E, 8 * NFIELD, 8 * NFIELD))
+        for j in range(8 * NFIELD):
+            pert = se.astype(complex)
+            pert[:, j] += 1j * CSTEP
+            Je[:, :, j] = self._elem_rows(pert).imag / CSTEP
+        return Je
+
+    def jacobian(self, s):
+        """Assembled constrained Jacobian J~ (CSR)."""
+        Je = self.element_jacobians(s)
+        nz = np.any(Je != 0.0, axis=0)                      # structural pattern of the element block
+        li, lj = np.nonzero(nz)
+        rows = self.ldof[:, li].ravel()
+        cols = self.ldof[:, lj].ravel()
+        vals = Je[:, li, lj].ravel()
+        J = sp.csr_matrix((vals, (rows, cols)), shape=(self.ndof, self.ndof))
+        free = (~self.mask).reshape(-1).astype(float)
+        Df = sp.diags(free)
+        return (Df @ J @ Df + sp.diags(1.0 - free)).tocsr()
+
+    def jac_apply(self, s, v):
+        return (self.jacobian(s) @ np.asarray(v, dtype=float).reshape(-1)).reshape(-1, NFIELD)
+
+    def jacT_apply(self, s, w):
+        return (self.jacobian(s).T @ np.asarray(w, dtype=float).reshape(-1)).reshape(-1, NFIELD)
+
+    # ---------------------------------------------------------------- Newton
+    def solve_state(self, s0=None, step_rtol=1e-12, maxit=50, verbose=False):
+        """Damped Newton (Sec. 5.4): full step unless it increases ||R~||_2, then halve.
+
+        Stops after a full step whose every field-block is below step_rtol relative to
+        that field of the iterate (quadratic convergence makes the following error
+        round-off).  Returns s (N, 5) and a history dict.
+        """
+        s = np.zeros((self.mesh.n_nodes, NFIELD)) if s0 is None else np.array(s0, dtype=float).reshape(-1, NFIELD)
+        s[self.mask] = self.sbar[self.mask]
+        R = self.residual(s)
+        hist = {"res": [np.linalg.norm(R)], "lam": [], "step": []}
+        t_asm = t_fac = t_sol = 0.0
+        for it in range(maxit):
+            t0 = time.perf_counter()
+            J = self.jacobian(s)
+            t1 = time.perf_counter()
+            lu = spla.splu(J.tocsc())
+            t2 = time.perf_counter()
+            d = lu.solve(-R.reshape(-1)).reshape(-1, NFIELD)
+            t3 = time.perf_counter()
+            t_asm, t_fac, t_sol = t_asm + t1 - t0, t_fac + t2 - t1, t_sol + t3 - t2
+            nrm = np.linalg.norm(R)
+            lam = 1.0
+            while True:
+                st = s + lam * d
+                Rt = self.residual(st)
+                if np.linalg.norm(Rt) <= nrm or lam < 1.0 / 64:
+                    break
+                lam *= 0.5
+            s, R = st, Rt
+            rel = [np.linalg.norm(d[:, f]) / max(np.linalg.norm(s[:, f]), 1e-300) for f in range(NFIELD)]
+            hist["res"].append(np.linalg.norm(R))
+            hist["lam"].append(lam)
+            hist["step"].append(max(rel))
+            if verbose:
+                print(f"newton {it}: |R|={hist['res'][-1]:.3e} lam={lam} step={max(rel):.3e}")
+            if lam == 1.0 and max(rel) <= step_rtol:
+                break
+        hist["its"] = it + 1
+        self.timing.update(state_assembly=t_asm, state_factor=t_fac, state_solve=t_sol)
+        return s, hist
+
+    # ---------------------------------------------------------------- objective / adjoint
+    def objective(self, s):
+        """Thermal compliance with the boundary-flux load: f = f_qh^T t (Sec. 5.1
+        eq. objdiscr with the flux vector in place of f_tQ)."""
+        return float(self.flux @ np.asarray(s).reshape(-1, NFIELD)[:, FIELD_T])
+
+    def dfds(self):
+        g = np.zeros((self.mesh.n_nodes, NFIELD))
+        g[:, FIELD_T] = self.flux
+        g[self.mask] = 0.0
+        return g
+
+    def solve_adjoint(self, s, rhs):
+        """Solve J~^T lambda = rhs (rhs zeroed on constrained dofs) with SuperLU."""
+        t0 = time.perf_counter()
+        J = self.jacobian(s)
+        t1 = time.perf_counter()
+        lu = spla.splu(J.tocsc())
+        t2 = time.perf_counter()
+        b = np.array(rhs, dtype=float).reshape(-1, NFIELD)
+        b[self.mask] = 0.0
+        lam = lu.solve(b.reshape(-1), trans="T").reshape(-1, NFIELD)
+        t3 = time.perf_counter()
+        self.timing.update(adjoint_assembly=t1 - t0, adjoint_factor=t2 - t1, adjoint_solve=t3 - t2)
+        return lam
+
+    def elem_dR_dgamma(self, s):
+        """d R_e / d gamma_e for every element by the complex step through RAMP, (E, 40)."""
+        s = np.asarray(s, dtype=float).reshape(-1)
+        g = self.gamma.astype(complex) + 1j * CSTEP
+        p = self.prm
+        k = ramp_k(g, p.k_f, p.k_s, p.q_c)
+        kap = ramp_kappa(g, p.kappa_f, p.kappa_s, p.q_p)
+        return self._elem_rows(s[self.ldof].astype(complex), k, kap).imag / CSTEP
+
+    def sensitivity(self, s, lam):
+        """Returns (dfdgamma, dfdx): -lambda_e^T dR_e/dgamma_e per element, and its image
+        under the filter transpose (the design chain gamma = F x)."""
+        lam = np.asarray(lam, dtype=float).reshape(-1)
+        dR = self.elem_dR_dgamma(s)
+        dfdg = -np.einsum("ej,ej->e", lam[self.ldof], dR)
+        return dfdg, self.F.T @ dfdg
