@@ -1,0 +1,157 @@
+/*
+ * nc.h -- C ABI of the MI355X (gfx950) natural-convection state / adjoint solver.
+ *
+ * The library solves the stabilised trilinear-hexahedron discretisation of the
+ * Darcy / Boussinesq / convection-diffusion model of Pollini, Sigmund, Andreasen and
+ * Alexandersen (arXiv 1904.00182): the Darcy velocity of Sec. 2.1 (eq. finaldarcy)
+ * inserted into incompressibility and the energy equation (Sec. 2.2, eq. goveq), in
+ * the weak form of App. A (eq. weakstable) with the Tezduyar SUPG weight, posed as
+ * R(s) = M(s) s - f = 0 (eq. finalsyseq).  Conductivity and permeability are RAMP
+ * interpolated (Sec. 5.2, eqs. condRAMP, permRAMP) from a filtered density.  The
+ * state is solved by damped Newton (Sec. 5.4) with matrix-free Jacobian applies,
+ * flexible GMRES and a geometric-multigrid preconditioner; design sensitivities
+ * follow from the adjoint (Sec. 5.1, eq. optprob and the adjoint analysis).
+ *
+ * Unknowns: five per node, node-interleaved (u, v, w, P, T).  The P and T rows are
+ * the paper's two-field system; the u, v, w rows are the lumped L2 projection of the
+ * Darcy velocity, which does not feed back into the P and T rows.
+ *
+ * Grid numbering (all arrays):
+ *   node    n = i + (nx+1) * (j + (ny+1) * k)      state arrays are [n][5] float64
+ *   element e = i + nx * (j + ny * k)              design arrays are [e] float64
+ *   z is vertical, gravity (0, 0, -g0).
+ * Boundary conditions of the cavity (Sec. 6.1): T = 0 on x = 0, x = Lx, y = 0,
+ * y = Ly and z = Lz; the bottom is insulated except for a heat flux q_h entering
+ * through a rectangular patch; u.n = 0 on all walls (natural); the pressure level
+ * is fixed by P = 0 at node (0, 0, nz).
+ *
+ * Memory ownership: every pointer whose name ends in _dev is a device pointer owned
+ * by the caller.  The library never allocates device memory: all of its persistent
+ * device buffers live in the single caller-provided workspace sized by
+ * nc_workspace_bytes().  A context is bound to one HIP stream (passed as void*),
+ * is not thread-safe, and is independent of every other context.
+ *
+ * Errors: every int-returning function returns NC_OK (0) on success, a positive
+ * value for a non-fatal outcome (NC_NOT_CONVERGED: the best iterate is left in the
+ * output and the info struct is filled) and a negative value on error.  Functions
+ * that return host-visible values synchronise the context's stream; the others only
+ * enqueue work.  No C++ exception crosses this interface.
+ */
+#ifndef NC_H
+#define NC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NC_OK               0
+#define NC_NOT_CONVERGED    1
+#define NC_EINVAL         (-1)
+#define NC_ENOMEM         (-2)
+#define NC_EHIP           (-3)
+#define NC_ENAN           (-4)
+
+#define NC_FP64   0   /* everything in float64                                          */
+#define NC_MIXED  1   /* float32 inner Krylov / multigrid / operator, float64 outer loop */
+
+typedef struct nc_problem {
+  int    nx, ny, nz;          /* elements per axis                                       */
+  double h;                   /* element edge; <= 0 means 1/nx                           */
+  double rho0, mu, cp, g0;    /* reference density, viscosity, heat capacity, gravity    */
+  double alpha;               /* thermal expansion coefficient (= Gr with unit constants)*/
+  double k_f, k_s;            /* fluid / solid conductivity                              */
+  double kappa_f, kappa_s;    /* fluid / solid permeability                              */
+  double q_c, q_p;            /* RAMP penalties of k and kappa                           */
+  double q_h;                 /* heat flux through the bottom patch                      */
+  double patch_x0, patch_x1, patch_y0, patch_y1; /* patch: bottom faces with centre inside */
+  double Q;                   /* uniform volumetric heat source                          */
+  double filter_radius;       /* cone density filter radius in element lengths; 0 = none */
+  int    precision;           /* NC_FP64 or NC_MIXED                                     */
+  int    levels;              /* multigrid levels; 0 = choose automatically              */
+  double newton_step_rtol;    /* stop after a full step with |ds_f| <= rtol |s_f| per field */
+  double krylov_rtol;         /* relative tolerance of each inner linear solve           */
+  double adjoint_rtol;        /* relative residual of the adjoint solve                  */
+  int    newton_maxit, krylov_restart, krylov_maxit;
+  int    smooth_pre, smooth_post; /* damped block-Jacobi sweeps                          */
+  double smooth_omega;        /* block-Jacobi damping                                    */
+} nc_problem;
+
+typedef struct nc_info {
+  int    newton_its;          /* Newton steps taken                                      */
+  int    krylov_its;          /* total FGMRES iterations (state or adjoint)              */
+  int    refine_its;          /* outer refinement sweeps (adjoint; mixed mode)           */
+  int    levels;              /* multigrid levels used                                   */
+  double res[5];              /* final residual 2-norm per field (u, v, w, P, T)         */
+  double rel_res;             /* final relative residual of the last linear solve        */
+  double t_total;             /* seconds, host wall clock of the call                    */
+} nc_info;
+
+typedef struct nc_ctx nc_ctx;
+
+/* Fill *p with the defaults of the paper's unit-constant cavity (Sec. 3 and Sec. 6.1:
+ * rho0 = mu = c_p = g0 = 1, k_f = 1, k_s = 100) for an nx*ny*nz grid; alpha 1e3 with
+ * the Table tab:2 permeability 0.00513, kappa_s 1e-4, q_c = q_p = 8, unit flux on the
+ * centred patch [0.375, 0.625] x [0.125, 0.375]. */
+void   nc_problem_default(nc_problem* p, int nx, int ny, int nz);
+
+/* Bytes of device workspace a context for *p needs (also the admission footprint).
+ * Returns 0 for an invalid problem. */
+size_t nc_workspace_bytes(const nc_problem* p);
+
+/* Create a context.  workspace_dev: caller-owned device buffer of >= bytes
+ * (nc_workspace_bytes), 256-byte aligned; stream: hipStream_t or NULL for the
+ * default stream.  NC_EINVAL for bad sizes, NC_ENOMEM if bytes is too small. */
+int    nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stream, nc_ctx** out);
+int    nc_destroy(nc_ctx* ctx);
+const char* nc_status_string(int status);
+
+/* Design chain (row a1): gamma = F_R x (cone filter, identity if radius 0), then the
+ * RAMP coefficients k(gamma), kappa(gamma) and their derivatives on every level.
+ * x_dev: [E] float64 in [0, 1].  Enqueue only. */
+int    nc_set_design(nc_ctx* ctx, const double* x_dev);
+/* Copy the filtered density gamma [E] into gamma_dev. */
+int    nc_get_gamma(nc_ctx* ctx, double* gamma_dev);
+
+/* Nonlinear residual R~(s) of the constrained system (row a2), [N][5] -> [N][5].
+ * Constrained rows hold s - s_bar (s_bar = 0). */
+int    nc_residual(nc_ctx* ctx, const double* s_dev, double* r_dev);
+
+/* Store the linearisation state (P, T of s) used by the Jacobian applies. */
+int    nc_linearize(nc_ctx* ctx, const double* s_dev);
+/* y = J~ v and y = J~^T w at the stored linearisation (rows a4, a5); J~ is the exact
+ * Newton Jacobian with constrained rows and columns replaced by the identity.
+ * Float64 and float32 variants ([N][5] each). */
+int    nc_jac_apply(nc_ctx* ctx, const double* v_dev, double* y_dev);
+int    nc_jacT_apply(nc_ctx* ctx, const double* w_dev, double* y_dev);
+int    nc_jac_apply_f32(nc_ctx* ctx, const float* v_dev, float* y_dev);
+int    nc_jacT_apply_f32(nc_ctx* ctx, const float* w_dev, float* y_dev);
+
+/* Newton state solve (rows a2-a4, a6-a9).  s_dev [N][5]: in = initial guess (zeros
+ * for a cold start; constrained entries are overwritten), out = solution.
+ * Synchronises; fills *info if non-NULL.  NC_NOT_CONVERGED leaves the last iterate. */
+int    nc_solve_state(nc_ctx* ctx, double* s_dev, nc_info* info);
+
+/* Objective f = f_qh^T t (the flux-weighted patch temperature; Sec. 5.1 eq. objdiscr
+ * with the boundary-flux load), to *f_host.  Synchronises. */
+int    nc_objective(nc_ctx* ctx, const double* s_dev, double* f_host);
+/* d f / d s, [N][5] (f_qh on the T entries of the patch nodes, 0 elsewhere). */
+int    nc_objective_grad(nc_ctx* ctx, double* g_dev);
+
+/* Adjoint solve J~^T lambda = rhs at the state s (rows a10, a11).  rhs_dev, lam_dev
+ * [N][5]; the rhs is zeroed on constrained dofs, so lambda is 0 there.  Synchronises. */
+int    nc_solve_adjoint(nc_ctx* ctx, const double* s_dev, const double* rhs_dev, double* lam_dev, nc_info* info);
+
+/* Sensitivities (row a12): dfdgamma_e = -lambda_e^T dR_e/dgamma_e through RAMP, then
+ * dfdx = F_R^T dfdgamma.  dfdx_dev [E] (required), dfdgamma_dev [E] (may be NULL). */
+int    nc_sensitivity(nc_ctx* ctx, const double* s_dev, const double* lam_dev, double* dfdx_dev, double* dfdgamma_dev);
+
+/* Stand-alone cone filter on an nx*ny*nz element grid (y = F_R x, or F_R^T x when
+ * transpose != 0); used to build filtered designs.  Enqueued on stream. */
+int    nc_cone_filter(int nx, int ny, int nz, double radius, const double* x_dev, double* y_dev, int transpose, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NC_H */
