@@ -427,6 +427,52 @@ NC_HD T elem_sensitivity(const Lin<T>& L, const T lP[8], const T lT[8], const T 
   return -c.W * (dk * rk + dkap * rkap);
 }
 
+// Velocity rows' coupling to the (P, T) columns alone: yU_a = -sum_q W N_a du_q with
+// du_q = -(kappa/mu)(grad p_q - beta t_q e_z).  State independent (only kappa enters).
+template <typename T>
+NC_HD void elem_uproj(const T p[8], const T t[8], T kap, const ElemConst<T>& c, T yU[3][8]) {
+  T mp[8], mt[8];
+  hadamard_fwd(p, mp);
+  hadamard_fwd(t, mt);
+  T gpx[4], gpy[4], gpz[4], gpc[3], tq[8], tc;
+  grad_from_modal(mp, c, gpx, gpy, gpz, gpc);
+  val_from_modal(mt, tq, tc);
+  const T cm = kap * c.inv_mu;
+  T sx[8], sy[8], sz[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    sx[q] = cm * gpx[jx_of(q)];
+    sy[q] = cm * gpy[jy_of(q)];
+    sz[q] = cm * (gpz[jz_of(q)] - c.beta * tq[q]);
+  }
+  project<T>(sx, nullptr, nullptr, nullptr, c, c.W, yU[0]);
+  project<T>(sy, nullptr, nullptr, nullptr, c, c.W, yU[1]);
+  project<T>(sz, nullptr, nullptr, nullptr, c, c.W, yU[2]);
+}
+
+// Transpose of elem_uproj: contributions of velocity-row weights zu to the P and T columns.
+template <typename T>
+NC_HD void elem_uprojT(const T zu[3][8], T kap, const ElemConst<T>& c, T yP[8], T yT[8]) {
+  T zq[3][8];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T m[8], vc;
+    hadamard_fwd(zu[d], m);
+    val_from_modal(m, zq[d], vc);
+  }
+  const T cmw = kap * c.inv_mu * c.W;
+  T Fx[8], Fy[8], Fz[8], s[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    Fx[q] = cmw * zq[0][q];
+    Fy[q] = cmw * zq[1][q];
+    Fz[q] = cmw * zq[2][q];
+    s[q] = -cmw * c.beta * zq[2][q];
+  }
+  project<T>(nullptr, Fx, Fy, Fz, c, (T)1, yP);
+  project<T>(s, nullptr, nullptr, nullptr, c, (T)1, yT);
+}
+
 // RAMP interpolation (Sec. 5.2, eqs. condRAMP and permRAMP) and derivatives.
 template <typename T>
 NC_HD void ramp(T gam, T k_f, T k_s, T q_c, T kap_f, T kap_s, T q_p, T& k, T& kap, T& dk, T& dkap) {

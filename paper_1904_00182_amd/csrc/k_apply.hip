@@ -1,0 +1,472 @@
+// Operator kernels: residual, Jacobian, transposed Jacobian, multigrid smoother and the
+// velocity-coupling pieces of the preconditioner.
+//
+// Work decomposition ("z-march").  A workgroup of TX x TY threads covers a tile of TX x
+// TY element columns and marches up in z through KZ + 1 element layers.  Thread (tx, ty)
+// computes element (I0 - 1 + tx, J0 - 1 + ty, k) of every layer in registers and owns
+// node column (I0 - 1 + tx, J0 - 1 + ty) for tx, ty >= 1 -- the lower-left node of its
+// own element.  Each node gathers the contributions of its four elements per layer
+// through LDS (the three neighbours' corners) and the contribution of the layer below
+// from a register accumulator, always in the same order, so results are bitwise
+// reproducible and no atomics are needed.  Elements on the tile's lower x / y edge and
+// the layer below the z chunk are recomputed by the neighbouring workgroup.
+#include "kernels.hpp"
+
+namespace nc {
+
+template <class Op, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void zmarch_kernel(const Op op, const int KZ) {
+  using T = typename Op::real;
+  constexpr int NI = Op::NIN, NO = Op::NOUT, NT = TX * TY;
+  __shared__ T xch[6 * NO * NT];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+  const int nx = op.g.nx, ny = op.g.ny, nz = op.g.nz;
+  const int i = (int)blockIdx.x * (TX - 1) - 1 + tx;
+  const int j = (int)blockIdx.y * (TY - 1) - 1 + ty;
+  const int K0 = (int)blockIdx.z * KZ;
+  const bool colok = i >= 0 && i < nx && j >= 0 && j < ny;
+  const bool owner = tx >= 1 && ty >= 1 && i <= nx && j <= ny;
+  const int kbeg = K0 > 0 ? K0 - 1 : 0;
+  const int kend = min(K0 + KZ - 1, nz);
+  T acc[NO];
+#pragma unroll
+  for (int f = 0; f < NO; ++f) acc[f] = (T)0;
+  T nd[8][NI];
+  bool have_lo = false;
+  for (int kl = kbeg; kl <= kend; ++kl) {
+    T out[8][NO];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int f = 0; f < NO; ++f) out[a][f] = (T)0;
+    if (colok && kl < nz) {
+      if (!have_lo) {
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) op.load(i + (cc & 1), j + (cc >> 1), kl, nd[cc]);
+      }
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) op.load(i + (cc & 1), j + (cc >> 1), kl + 1, nd[4 + cc]);
+      op.element(i, j, kl, nd, out);
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+        for (int f = 0; f < NI; ++f) nd[cc][f] = nd[4 + cc][f];
+      have_lo = true;
+    }
+#pragma unroll
+    for (int ka = 0; ka < 2; ++ka)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+        for (int f = 0; f < NO; ++f) xch[((ka * 3 + cc) * NO + f) * NT + tid] = out[cc + 1 + 4 * ka][f];
+    __syncthreads();
+    if (owner) {
+      const int tl = tid - 1, td = tid - TX, tld = tid - TX - 1;
+      T v[NO];
+#pragma unroll
+      for (int f = 0; f < NO; ++f)
+        v[f] = acc[f] + out[0][f] + xch[(0 * NO + f) * NT + tl] + xch[(1 * NO + f) * NT + td] +
+               xch[(2 * NO + f) * NT + tld];
+      if (kl >= K0) op.finish(i, j, kl, v);
+#pragma unroll
+      for (int f = 0; f < NO; ++f)
+        acc[f] = out[4][f] + xch[(3 * NO + f) * NT + tl] + xch[(4 * NO + f) * NT + td] + xch[(5 * NO + f) * NT + tld];
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int TILE_X = 16, TILE_Y = 16;
+
+template <class Op>
+static void run_zmarch(hipStream_t st, const Op& op) {
+  const Grid& g = op.g;
+  const int tiles_x = ceil_div(g.nx + 1, TILE_X - 1);
+  const int tiles_y = ceil_div(g.ny + 1, TILE_Y - 1);
+  // enough z chunks for ~4 workgroups per CU, but at least 4 planes per chunk
+  const int want = std::max(1, 1024 / std::max(1, tiles_x * tiles_y));
+  int KZ = std::max(4, ceil_div(g.nz + 1, want));
+  const int chunks = ceil_div(g.nz + 1, KZ);
+  dim3 grid(tiles_x, tiles_y, chunks), block(TILE_X, TILE_Y, 1);
+  hipLaunchKernelGGL((zmarch_kernel<Op, TILE_X, TILE_Y>), grid, block, 0, st, op, KZ);
+}
+
+// ------------------------------------------------------------------ residual (float64)
+struct ResidualOp {
+  using real = double;
+  static constexpr int NIN = 2, NOUT = 5;
+  Grid g;
+  ElemConst<double> c;
+  Patch patch;
+  const double* coef;
+  const double* s;
+  double* r;
+  __device__ void load(int i, int j, int k, double in[NIN]) const {
+    const long n = g.node(i, j, k);
+    in[0] = s[5 * n + 3];
+    in[1] = s[5 * n + 4];
+  }
+  __device__ void element(int i, int j, int k, const double nd[8][NIN], double out[8][NOUT]) const {
+    double P[8], Tn[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) { P[a] = nd[a][0]; Tn[a] = nd[a][1]; }
+    const long e = g.elem(i, j, k);
+    Lin<double> L;
+    linearize(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    double rP[8] = {0}, rT[8] = {0}, rU[3][8] = {{0}};
+    elem_residual<double, true>(L, c, rP, rT, rU);
+    if (k == 0 && patch.has(i, j)) {
+      const double fl = patch.q_h * patch.h * patch.h * 0.25;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) rT[a] -= fl;
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      out[a][0] = rU[0][a]; out[a][1] = rU[1][a]; out[a][2] = rU[2][a];
+      out[a][3] = rP[a]; out[a][4] = rT[a];
+    }
+  }
+  __device__ void finish(int i, int j, int k, const double v[NOUT]) const {
+    const long n = g.node(i, j, k);
+    const double M = c.W * g.valence(i, j, k);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) r[5 * n + d] = v[d] + M * s[5 * n + d];
+    r[5 * n + 3] = g.pfix(i, j, k) ? s[5 * n + 3] : v[3];
+    r[5 * n + 4] = g.tfix(i, j, k) ? s[5 * n + 4] : v[4];
+  }
+};
+
+void launch_residual(hipStream_t st, const Grid& g, const ElemConst<double>& c, const Patch& patch,
+                     const double* coef, const double* s, double* r) {
+  ResidualOp op{g, c, patch, coef, s, r};
+  run_zmarch(st, op);
+}
+
+// ------------------------------------------------------------------ Jacobian applies
+// NF: fields per node of the direction/output arrays (5 on the fine level, 2 in the
+// (P, T) multigrid hierarchy).
+template <typename T, int NF, int MODE>
+struct JvOp {
+  using real = T;
+  static constexpr int NIN = 4, NOUT = NF;
+  Grid g;
+  ElemConst<T> c;
+  const T* coef;
+  const T* st;
+  const T* x;
+  const T* b;
+  const T* dinv;
+  T* y;
+  T omega;
+  Scale5<T> rs;   // output row scales (five-field mode)
+  __device__ void load(int i, int j, int k, T in[NIN]) const {
+    const long n = g.node(i, j, k);
+    in[0] = st[2 * n];
+    in[1] = st[2 * n + 1];
+    T p = x[NF * n + NF - 2], t = x[NF * n + NF - 1];
+    if (g.pfix(i, j, k)) p = (T)0;
+    if (g.tfix(i, j, k)) t = (T)0;
+    in[2] = p;
+    in[3] = t;
+  }
+  __device__ void element(int i, int j, int k, const T nd[8][NIN], T out[8][NOUT]) const {
+    T P[8], Tn[8], p[8], t[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) { P[a] = nd[a][0]; Tn[a] = nd[a][1]; p[a] = nd[a][2]; t[a] = nd[a][3]; }
+    const long e = g.elem(i, j, k);
+    Lin<T> L;
+    linearize(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    T yP[8] = {0}, yT[8] = {0}, yU[3][8] = {{0}};
+    elem_jv<T, NF == 5>(L, p, t, c, yP, yT, yU);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (NF == 5) { out[a][0] = yU[0][a]; out[a][1] = yU[1][a]; out[a][2] = yU[2][a]; }
+      out[a][NF - 2] = yP[a];
+      out[a][NF - 1] = yT[a];
+    }
+  }
+  __device__ void finish(int i, int j, int k, const T v[NOUT]) const {
+    const long n = g.node(i, j, k);
+    const bool pf = g.pfix(i, j, k), tf = g.tfix(i, j, k);
+    const T ap = pf ? x[NF * n + NF - 2] : v[NF - 2];
+    const T at = tf ? x[NF * n + NF - 1] : v[NF - 1];
+    if (NF == 5) {
+      const T M = c.W * (T)g.valence(i, j, k);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) y[5 * n + d] = rs.s[d] * (v[d] + M * x[5 * n + d]);
+    }
+    if (MODE == MODE_STORE) {
+      y[NF * n + NF - 2] = NF == 5 ? rs.s[3] * ap : ap;
+      y[NF * n + NF - 1] = NF == 5 ? rs.s[4] * at : at;
+    } else {
+      const T rp = b[2 * n] - ap, rt = b[2 * n + 1] - at;
+      if (MODE == MODE_RESID) {
+        y[2 * n] = rp;
+        y[2 * n + 1] = rt;
+      } else {
+        const T* D = dinv + 4 * n;
+        y[2 * n] = x[2 * n] + omega * (D[0] * rp + D[1] * rt);
+        y[2 * n + 1] = x[2 * n + 1] + omega * (D[2] * rp + D[3] * rt);
+      }
+    }
+  }
+};
+
+template <typename T, int NF, int MODE>
+struct JtwOp {
+  using real = T;
+  static constexpr int NIN = NF == 5 ? 7 : 4, NOUT = 2;
+  Grid g;
+  ElemConst<T> c;
+  const T* coef;
+  const T* st;
+  const T* x;     // weights w
+  const T* b;
+  const T* dinv;
+  T* y;
+  T omega;
+  Scale5<T> rs;   // output row scales (five-field mode)
+  __device__ void load(int i, int j, int k, T in[NIN]) const {
+    const long n = g.node(i, j, k);
+    in[0] = st[2 * n];
+    in[1] = st[2 * n + 1];
+    T p = x[NF * n + NF - 2], t = x[NF * n + NF - 1];
+    if (g.pfix(i, j, k)) p = (T)0;
+    if (g.tfix(i, j, k)) t = (T)0;
+    in[2] = p;
+    in[3] = t;
+    if (NF == 5) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) in[4 + d] = x[5 * n + d];
+    }
+  }
+  __device__ void element(int i, int j, int k, const T nd[8][NIN], T out[8][NOUT]) const {
+    T P[8], Tn[8], wP[8], wT[8], wU[3][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      P[a] = nd[a][0]; Tn[a] = nd[a][1]; wP[a] = nd[a][2]; wT[a] = nd[a][3];
+      if (NF == 5) { wU[0][a] = nd[a][4 % NIN]; wU[1][a] = nd[a][5 % NIN]; wU[2][a] = nd[a][6 % NIN]; }
+    }
+    const long e = g.elem(i, j, k);
+    Lin<T> L;
+    linearize(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    T yP[8] = {0}, yT[8] = {0};
+    elem_jtw<T, NF == 5>(L, wP, wT, wU, c, yP, yT);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) { out[a][0] = yP[a]; out[a][1] = yT[a]; }
+  }
+  __device__ void finish(int i, int j, int k, const T v[NOUT]) const {
+    const long n = g.node(i, j, k);
+    const bool pf = g.pfix(i, j, k), tf = g.tfix(i, j, k);
+    const T ap = pf ? x[NF * n + NF - 2] : v[0];
+    const T at = tf ? x[NF * n + NF - 1] : v[1];
+    if (NF == 5) {
+      const T M = c.W * (T)g.valence(i, j, k);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) y[5 * n + d] = rs.s[d] * M * x[5 * n + d];
+    }
+    if (MODE == MODE_STORE) {
+      y[NF * n + NF - 2] = NF == 5 ? rs.s[3] * ap : ap;
+      y[NF * n + NF - 1] = NF == 5 ? rs.s[4] * at : at;
+    } else {
+      const T rp = b[2 * n] - ap, rt = b[2 * n + 1] - at;
+      if (MODE == MODE_RESID) {
+        y[2 * n] = rp;
+        y[2 * n + 1] = rt;
+      } else {
+        const T* D = dinv + 4 * n;     // (D^-1)^T
+        y[2 * n] = x[2 * n] + omega * (D[0] * rp + D[2] * rt);
+        y[2 * n + 1] = x[2 * n + 1] + omega * (D[1] * rp + D[3] * rt);
+      }
+    }
+  }
+};
+
+template <typename T>
+static Scale5<T> ones_or(const Scale5<T>* s) {
+  return s ? *s : Scale5<T>{{(T)1, (T)1, (T)1, (T)1, (T)1}};
+}
+
+template <typename T>
+void launch_jv5(hipStream_t st, const LevelView<T>& L, const T* x, T* y, const Scale5<T>* rows) {
+  JvOp<T, 5, MODE_STORE> op{L.g, L.c, L.coef, L.st, x, nullptr, nullptr, y, (T)0, ones_or(rows)};
+  run_zmarch(st, op);
+}
+template <typename T>
+void launch_jtw5(hipStream_t st, const LevelView<T>& L, const T* w, T* y, const Scale5<T>* rows) {
+  JtwOp<T, 5, MODE_STORE> op{L.g, L.c, L.coef, L.st, w, nullptr, nullptr, y, (T)0, ones_or(rows)};
+  run_zmarch(st, op);
+}
+
+template <typename T>
+void launch_pt_apply(hipStream_t st, const LevelView<T>& L, bool transpose, int mode, const T* x, const T* b, T* y,
+                     T omega) {
+#define NC_PT(OP, M)                                                              \
+  {                                                                             \
+    OP<T, 2, M> op{L.g, L.c, L.coef, L.st, x, b, L.dinv, y, omega, ones_or<T>(nullptr)}; \
+    run_zmarch(st, op);                                                         \
+  }
+  if (!transpose) {
+    if (mode == MODE_STORE) NC_PT(JvOp, MODE_STORE)
+    else if (mode == MODE_RESID) NC_PT(JvOp, MODE_RESID)
+    else NC_PT(JvOp, MODE_SMOOTH)
+  } else {
+    if (mode == MODE_STORE) NC_PT(JtwOp, MODE_STORE)
+    else if (mode == MODE_RESID) NC_PT(JtwOp, MODE_RESID)
+    else NC_PT(JtwOp, MODE_SMOOTH)
+  }
+#undef NC_PT
+}
+
+// ------------------------------------------------------------------ block diagonal
+template <typename T>
+struct DiagOp {
+  using real = T;
+  static constexpr int NIN = 2, NOUT = 4;
+  Grid g;
+  ElemConst<T> c;
+  const T* coef;
+  const T* st;
+  T* dinv;
+  __device__ void load(int i, int j, int k, T in[NIN]) const {
+    const long n = g.node(i, j, k);
+    in[0] = st[2 * n];
+    in[1] = st[2 * n + 1];
+  }
+  __device__ void element(int i, int j, int k, const T nd[8][NIN], T out[8][NOUT]) const {
+    T P[8], Tn[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) { P[a] = nd[a][0]; Tn[a] = nd[a][1]; }
+    const long e = g.elem(i, j, k);
+    Lin<T> L;
+    linearize(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    for (int a = 0; a < 8; ++a) {
+      for (int fld = 0; fld < 2; ++fld) {
+        T p[8] = {0}, t[8] = {0}, yP[8] = {0}, yT[8] = {0}, yU[3][8];
+        if (fld == 0) p[a] = (T)1; else t[a] = (T)1;
+        elem_jv<T, false>(L, p, t, c, yP, yT, yU);
+        // row-major block [dRP/dP, dRP/dT; dRT/dP, dRT/dT]
+        out[a][fld] = yP[a];
+        out[a][2 + fld] = yT[a];
+      }
+    }
+  }
+  __device__ void finish(int i, int j, int k, const T v[NOUT]) const {
+    T pp = v[0], pt = v[1], tp = v[2], tt = v[3];
+    if (g.tfix(i, j, k)) { tp = (T)0; tt = (T)1; pt = (T)0; }
+    if (g.pfix(i, j, k)) { pp = (T)1; pt = (T)0; tp = (T)0; }
+    const T idet = (T)1 / (pp * tt - pt * tp);
+    T* D = dinv + 4 * g.node(i, j, k);
+    D[0] = tt * idet;
+    D[1] = -pt * idet;
+    D[2] = -tp * idet;
+    D[3] = pp * idet;
+  }
+};
+
+template <typename T>
+void launch_diag_inverse(hipStream_t st, const LevelView<T>& L, T* dinv) {
+  DiagOp<T> op{L.g, L.c, L.coef, L.st, dinv};
+  run_zmarch(st, op);
+}
+
+// ------------------------------------------------------------------ velocity coupling
+template <typename T>
+struct UprojOp {
+  using real = T;
+  static constexpr int NIN = 2, NOUT = 3;
+  Grid g;
+  ElemConst<T> c;
+  const T* coef;
+  const T* xpt;
+  const T* r5;
+  T* z5;
+  Scale5<T> inv;   // 1 / row scale of r5
+  __device__ void load(int i, int j, int k, T in[NIN]) const {
+    const long n = g.node(i, j, k);
+    in[0] = g.pfix(i, j, k) ? (T)0 : xpt[2 * n];
+    in[1] = g.tfix(i, j, k) ? (T)0 : xpt[2 * n + 1];
+  }
+  __device__ void element(int i, int j, int k, const T nd[8][NIN], T out[8][NOUT]) const {
+    T p[8], t[8], yU[3][8] = {{0}};
+#pragma unroll
+    for (int a = 0; a < 8; ++a) { p[a] = nd[a][0]; t[a] = nd[a][1]; }
+    elem_uproj<T>(p, t, coef[2 * g.elem(i, j, k) + 1], c, yU);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) { out[a][0] = yU[0][a]; out[a][1] = yU[1][a]; out[a][2] = yU[2][a]; }
+  }
+  __device__ void finish(int i, int j, int k, const T v[NOUT]) const {
+    const long n = g.node(i, j, k);
+    const T iM = (T)1 / (c.W * (T)g.valence(i, j, k));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) z5[5 * n + d] = (inv.s[d] * r5[5 * n + d] - v[d]) * iM;
+    z5[5 * n + 3] = g.pfix(i, j, k) ? inv.s[3] * r5[5 * n + 3] : xpt[2 * n];
+    z5[5 * n + 4] = g.tfix(i, j, k) ? inv.s[4] * r5[5 * n + 4] : xpt[2 * n + 1];
+  }
+};
+
+template <typename T>
+struct UprojTOp {
+  using real = T;
+  static constexpr int NIN = 3, NOUT = 2;
+  Grid g;
+  ElemConst<T> c;
+  const T* coef;
+  const T* r5;
+  T* bpt;
+  T* z5;
+  Scale5<T> inv;   // 1 / row scale of r5
+  __device__ void load(int i, int j, int k, T in[NIN]) const {
+    const long n = g.node(i, j, k);
+    const T iM = (T)1 / (c.W * (T)g.valence(i, j, k));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) in[d] = inv.s[d] * r5[5 * n + d] * iM;
+  }
+  __device__ void element(int i, int j, int k, const T nd[8][NIN], T out[8][NOUT]) const {
+    T zu[3][8], yP[8] = {0}, yT[8] = {0};
+#pragma unroll
+    for (int a = 0; a < 8; ++a) { zu[0][a] = nd[a][0]; zu[1][a] = nd[a][1]; zu[2][a] = nd[a][2]; }
+    elem_uprojT<T>(zu, coef[2 * g.elem(i, j, k) + 1], c, yP, yT);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) { out[a][0] = yP[a]; out[a][1] = yT[a]; }
+  }
+  __device__ void finish(int i, int j, int k, const T v[NOUT]) const {
+    const long n = g.node(i, j, k);
+    const T iM = (T)1 / (c.W * (T)g.valence(i, j, k));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) z5[5 * n + d] = inv.s[d] * r5[5 * n + d] * iM;
+    bpt[2 * n] = g.pfix(i, j, k) ? (T)0 : inv.s[3] * r5[5 * n + 3] - v[0];
+    bpt[2 * n + 1] = g.tfix(i, j, k) ? (T)0 : inv.s[4] * r5[5 * n + 4] - v[1];
+  }
+};
+
+template <typename T>
+static Scale5<T> inverse_or_ones(const Scale5<T>* s) {
+  Scale5<T> r = ones_or<T>(nullptr);
+  if (s)
+    for (int f = 0; f < 5; ++f) r.s[f] = (T)1 / s->s[f];
+  return r;
+}
+template <typename T>
+void launch_uproj(hipStream_t st, const LevelView<T>& L, const T* x_pt, const T* r5, T* z5, const Scale5<T>* rows) {
+  UprojOp<T> op{L.g, L.c, L.coef, x_pt, r5, z5, inverse_or_ones(rows)};
+  run_zmarch(st, op);
+}
+template <typename T>
+void launch_uprojT(hipStream_t st, const LevelView<T>& L, const T* r5, T* b_pt, T* z5, const Scale5<T>* rows) {
+  UprojTOp<T> op{L.g, L.c, L.coef, r5, b_pt, z5, inverse_or_ones(rows)};
+  run_zmarch(st, op);
+}
+
+#define NC_INST(T)                                                                                  \
+  template void launch_jv5<T>(hipStream_t, const LevelView<T>&, const T*, T*, const Scale5<T>*);    \
+  template void launch_jtw5<T>(hipStream_t, const LevelView<T>&, const T*, T*, const Scale5<T>*);   \
+  template void launch_pt_apply<T>(hipStream_t, const LevelView<T>&, bool, int, const T*, const T*, T*, T); \
+  template void launch_diag_inverse<T>(hipStream_t, const LevelView<T>&, T*);                       \
+  template void launch_uproj<T>(hipStream_t, const LevelView<T>&, const T*, const T*, T*, const Scale5<T>*); \
+  template void launch_uprojT<T>(hipStream_t, const LevelView<T>&, const T*, T*, T*, const Scale5<T>*);
+NC_INST(double)
+NC_INST(float)
+#undef NC_INST
+
+}  // namespace nc

@@ -1,0 +1,760 @@
+// Multigrid transfers and setup, dense coarse solve, vector kernels, deterministic
+// reductions, design chain (cone filter, RAMP), sensitivities and the objective.
+#include "kernels.hpp"
+
+namespace nc {
+
+constexpr int BS = 256;
+
+static inline int blocks_for(long n, int bs = BS) {
+  long b = (n + bs - 1) / bs;
+  return (int)std::max<long>(1, std::min<long>(b, 65535L * 32));
+}
+
+// ------------------------------------------------------------------ transfers
+// Restriction by the transpose of trilinear prolongation (full weighting with weights
+// 1, 1/2, 1/4, 1/8), constrained coarse dofs set to zero.  One thread per coarse node.
+template <typename T>
+__global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf, T* __restrict__ bc) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= coarse.nodes()) return;
+  const int I = (int)(n % (coarse.nx + 1));
+  const int J = (int)((n / (coarse.nx + 1)) % (coarse.ny + 1));
+  const int K = (int)(n / ((long)(coarse.nx + 1) * (coarse.ny + 1)));
+  double sp = 0.0, stt = 0.0;
+  for (int dk = -1; dk <= 1; ++dk) {
+    const int k = 2 * K + dk;
+    if (k < 0 || k > fine.nz) continue;
+    const double wk = dk == 0 ? 1.0 : 0.5;
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int j = 2 * J + dj;
+      if (j < 0 || j > fine.ny) continue;
+      const double wj = wk * (dj == 0 ? 1.0 : 0.5);
+      for (int di = -1; di <= 1; ++di) {
+        const int i = 2 * I + di;
+        if (i < 0 || i > fine.nx) continue;
+        const double w = wj * (di == 0 ? 1.0 : 0.5);
+        const long m = fine.node(i, j, k);
+        sp += w * (double)rf[2 * m];
+        stt += w * (double)rf[2 * m + 1];
+      }
+    }
+  }
+  bc[2 * n] = coarse.pfix(I, J, K) ? (T)0 : (T)sp;
+  bc[2 * n + 1] = coarse.tfix(I, J, K) ? (T)0 : (T)stt;
+}
+
+// Trilinear prolongation added to the fine iterate; one thread per fine node.
+template <typename T>
+__global__ void prolong_kernel(Grid fine, Grid coarse, const T* __restrict__ xc, T* __restrict__ xf) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= fine.nodes()) return;
+  const int i = (int)(n % (fine.nx + 1));
+  const int j = (int)((n / (fine.nx + 1)) % (fine.ny + 1));
+  const int k = (int)(n / ((long)(fine.nx + 1) * (fine.ny + 1)));
+  const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
+  const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0, wk = (k & 1) ? 0.5 : 1.0;
+  double sp = 0.0, stt = 0.0;
+  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
+  for (int c = 0; c < nk; ++c)
+    for (int b = 0; b < nj; ++b)
+      for (int a = 0; a < ni; ++a) {
+        const long m = coarse.node(a ? i1 : i0, b ? j1 : j0, c ? k1 : k0);
+        const double w = wi * wj * wk;
+        sp += w * (double)xc[2 * m];
+        stt += w * (double)xc[2 * m + 1];
+      }
+  if (!fine.pfix(i, j, k)) xf[2 * n] += (T)sp;
+  if (!fine.tfix(i, j, k)) xf[2 * n + 1] += (T)stt;
+}
+
+template <typename T>
+__global__ void inject_kernel(Grid fine, Grid coarse, const T* __restrict__ sf, T* __restrict__ sc) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= coarse.nodes()) return;
+  const int I = (int)(n % (coarse.nx + 1));
+  const int J = (int)((n / (coarse.nx + 1)) % (coarse.ny + 1));
+  const int K = (int)(n / ((long)(coarse.nx + 1) * (coarse.ny + 1)));
+  const long m = fine.node(2 * I, 2 * J, 2 * K);
+  sc[2 * n] = sf[2 * m];
+  sc[2 * n + 1] = sf[2 * m + 1];
+}
+
+template <typename T>
+__global__ void average_coef_kernel(Grid fine, Grid coarse, const T* __restrict__ cf, T* __restrict__ cc) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= coarse.elems()) return;
+  const int I = (int)(e % coarse.nx);
+  const int J = (int)((e / coarse.nx) % coarse.ny);
+  const int K = (int)(e / ((long)coarse.nx * coarse.ny));
+  double k = 0.0, kap = 0.0;
+  for (int c = 0; c < 8; ++c) {
+    const long f = fine.elem(2 * I + (c & 1), 2 * J + ((c >> 1) & 1), 2 * K + ((c >> 2) & 1));
+    k += (double)cf[2 * f];
+    kap += (double)cf[2 * f + 1];
+  }
+  cc[2 * e] = (T)(0.125 * k);
+  cc[2 * e + 1] = (T)(0.125 * kap);
+}
+
+template <typename T>
+void launch_restrict(hipStream_t st, const Grid& fine, const Grid& coarse, const T* rf, T* bc) {
+  hipLaunchKernelGGL(restrict_kernel<T>, dim3(blocks_for(coarse.nodes())), dim3(BS), 0, st, fine, coarse, rf, bc);
+}
+template <typename T>
+void launch_prolong_add(hipStream_t st, const Grid& fine, const Grid& coarse, const T* xc, T* xf) {
+  hipLaunchKernelGGL(prolong_kernel<T>, dim3(blocks_for(fine.nodes())), dim3(BS), 0, st, fine, coarse, xc, xf);
+}
+template <typename T>
+void launch_inject_state(hipStream_t st, const Grid& fine, const Grid& coarse, const T* sf, T* sc) {
+  hipLaunchKernelGGL(inject_kernel<T>, dim3(blocks_for(coarse.nodes())), dim3(BS), 0, st, fine, coarse, sf, sc);
+}
+template <typename T>
+void launch_average_coef(hipStream_t st, const Grid& fine, const Grid& coarse, const T* cf, T* cc) {
+  hipLaunchKernelGGL(average_coef_kernel<T>, dim3(blocks_for(coarse.elems())), dim3(BS), 0, st, fine, coarse, cf, cc);
+}
+
+// ------------------------------------------------------------------ coarsest level
+// Element Jacobian columns of the (P, T) operator: mats[e][col][row], 16 x 16, local dof
+// index 2 a + field.
+template <typename T>
+__global__ void elem_matrix_kernel(LevelView<T> L, double* __restrict__ mats) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long E = L.g.elems();
+  if (t >= E * 16) return;
+  const long e = t / 16;
+  const int col = (int)(t % 16);
+  const int i = (int)(e % L.g.nx), j = (int)((e / L.g.nx) % L.g.ny), k = (int)(e / ((long)L.g.nx * L.g.ny));
+  T P[8], Tn[8], p[8], tt[8];
+  for (int a = 0; a < 8; ++a) {
+    const long n = L.g.node(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+    P[a] = L.st[2 * n];
+    Tn[a] = L.st[2 * n + 1];
+    p[a] = (T)0;
+    tt[a] = (T)0;
+  }
+  if (col & 1) tt[col >> 1] = (T)1; else p[col >> 1] = (T)1;
+  Lin<T> lin;
+  linearize(P, Tn, L.coef[2 * e], L.coef[2 * e + 1], L.c, lin);
+  T yP[8] = {0}, yT[8] = {0}, yU[3][8];
+  elem_jv<T, false>(lin, p, tt, L.c, yP, yT, yU);
+  double* m = mats + (e * 16 + col) * 16;
+  for (int a = 0; a < 8; ++a) {
+    m[2 * a] = (double)yP[a];
+    m[2 * a + 1] = (double)yT[a];
+  }
+}
+
+// Dense assembly, one thread per entry A[r][c] (row-major), constrained rows and
+// columns replaced by the identity.
+__global__ void dense_assemble_kernel(Grid g, const double* __restrict__ mats, double* __restrict__ A) {
+  const long n = 2 * g.nodes();
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const long r = t / n, c = t % n;
+  const long nr = r / 2, nc_ = c / 2;
+  const int fr = (int)(r % 2), fc = (int)(c % 2);
+  const int ir = (int)(nr % (g.nx + 1)), jr = (int)((nr / (g.nx + 1)) % (g.ny + 1)), kr = (int)(nr / ((long)(g.nx + 1) * (g.ny + 1)));
+  const int ic = (int)(nc_ % (g.nx + 1)), jc = (int)((nc_ / (g.nx + 1)) % (g.ny + 1)), kc = (int)(nc_ / ((long)(g.nx + 1) * (g.ny + 1)));
+  const bool rfix = fr == 0 ? g.pfix(ir, jr, kr) : g.tfix(ir, jr, kr);
+  const bool cfix = fc == 0 ? g.pfix(ic, jc, kc) : g.tfix(ic, jc, kc);
+  if (rfix || cfix) {
+    A[t] = (r == c) ? 1.0 : 0.0;
+    return;
+  }
+  double s = 0.0;
+  // elements containing node r: lower corner (ir - ar, jr - br, kr - cr)
+  for (int cr = 0; cr < 2; ++cr)
+    for (int br = 0; br < 2; ++br)
+      for (int ar = 0; ar < 2; ++ar) {
+        const int ei = ir - ar, ej = jr - br, ek = kr - cr;
+        if (ei < 0 || ej < 0 || ek < 0 || ei >= g.nx || ej >= g.ny || ek >= g.nz) continue;
+        const int ac = ic - ei, bc = jc - ej, ccz = kc - ek;
+        if (ac < 0 || ac > 1 || bc < 0 || bc > 1 || ccz < 0 || ccz > 1) continue;
+        const long e = g.elem(ei, ej, ek);
+        const int la_r = ar + 2 * br + 4 * cr, la_c = ac + 2 * bc + 4 * ccz;
+        s += mats[(e * 16 + 2 * la_c + fc) * 16 + 2 * la_r + fr];
+      }
+  A[t] = s;
+}
+
+template <typename T>
+void launch_coarse_assemble(hipStream_t st, const LevelView<T>& L, double* elem_mats, double* A) {
+  const long E = L.g.elems();
+  hipLaunchKernelGGL(elem_matrix_kernel<T>, dim3(blocks_for(E * 16)), dim3(BS), 0, st, L, elem_mats);
+  const long n = 2 * L.g.nodes();
+  hipLaunchKernelGGL(dense_assemble_kernel, dim3(blocks_for(n * n)), dim3(BS), 0, st, L.g, elem_mats, A);
+}
+
+// In-place Gauss-Jordan inversion with partial pivoting in one workgroup.
+constexpr int GJ_THREADS = 1024;
+__global__ __launch_bounds__(GJ_THREADS) void gauss_jordan_kernel(double* __restrict__ A, int n, int* __restrict__ perm) {
+  __shared__ double sval[GJ_THREADS / 64];
+  __shared__ int sidx[GJ_THREADS / 64];
+  __shared__ int piv;
+  extern __shared__ double fcol[];   // n entries
+  const int tid = threadIdx.x;
+  for (int k = 0; k < n; ++k) {
+    // pivot search in column k, rows k..n-1
+    double best = -1.0;
+    int bi = k;
+    for (int r = k + tid; r < n; r += GJ_THREADS) {
+      const double v = fabs(A[(long)r * n + k]);
+      if (v > best) { best = v; bi = r; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_down(best, off, 64);
+      const int oi = __shfl_down(bi, off, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if ((tid & 63) == 0) { sval[tid >> 6] = best; sidx[tid >> 6] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = sval[0];
+      int id = sidx[0];
+      for (int w = 1; w < GJ_THREADS / 64; ++w)
+        if (sval[w] > b || (sval[w] == b && sidx[w] < id)) { b = sval[w]; id = sidx[w]; }
+      piv = id;
+      perm[k] = id;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != k) {
+      for (int c = tid; c < n; c += GJ_THREADS) {
+        const double a = A[(long)k * n + c];
+        A[(long)k * n + c] = A[(long)p * n + c];
+        A[(long)p * n + c] = a;
+      }
+    }
+    __syncthreads();
+    const double pv = A[(long)k * n + k];
+    __syncthreads();
+    const double ipv = 1.0 / pv;
+    for (int c = tid; c < n; c += GJ_THREADS) {
+      A[(long)k * n + c] = (c == k ? 1.0 : A[(long)k * n + c]) * ipv;
+    }
+    for (int r = tid; r < n; r += GJ_THREADS) fcol[r] = (r == k) ? 0.0 : A[(long)r * n + k];
+    __syncthreads();
+    const long nn = (long)n * n;
+    for (long t = tid; t < nn; t += GJ_THREADS) {
+      const int r = (int)(t / n), c = (int)(t % n);
+      if (r == k) continue;
+      const double base = (c == k) ? 0.0 : A[t];
+      A[t] = base - fcol[r] * A[(long)k * n + c];
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, in reverse order
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k) {
+      for (int r = tid; r < n; r += GJ_THREADS) {
+        const double a = A[(long)r * n + k];
+        A[(long)r * n + k] = A[(long)r * n + p];
+        A[(long)r * n + p] = a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void launch_gauss_jordan(hipStream_t st, double* A, int n, int* perm) {
+  hipLaunchKernelGGL(gauss_jordan_kernel, dim3(1), dim3(GJ_THREADS), sizeof(double) * n, st, A, n, perm);
+}
+
+// x = Ainv b (one wave per row) or x = Ainv^T b (one thread per column)
+template <typename T>
+__global__ void dense_apply_kernel(const double* __restrict__ Ainv, int n, int transpose, const T* __restrict__ b,
+                                   T* __restrict__ x) {
+  if (!transpose) {
+    const int row = (int)((blockIdx.x * (long)blockDim.x + threadIdx.x) / 64);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    double s = 0.0;
+    for (int c = lane; c < n; c += 64) s += Ainv[(long)row * n + c] * (double)b[c];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) x[row] = (T)s;
+  } else {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= n) return;
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) s += Ainv[(long)r * n + col] * (double)b[r];
+    x[col] = (T)s;
+  }
+}
+
+template <typename T>
+void launch_dense_apply(hipStream_t st, const double* Ainv, int n, bool transpose, const T* b, T* x) {
+  if (!transpose)
+    hipLaunchKernelGGL(dense_apply_kernel<T>, dim3(ceil_div((long)n * 64, BS)), dim3(BS), 0, st, Ainv, n, 0, b, x);
+  else
+    hipLaunchKernelGGL(dense_apply_kernel<T>, dim3(ceil_div(n, BS)), dim3(BS), 0, st, Ainv, n, 1, b, x);
+}
+
+// ------------------------------------------------------------------ state / vectors
+template <typename T>
+__global__ void pack_state_kernel(long N, const double* __restrict__ s5, T* __restrict__ pt) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  pt[2 * n] = (T)s5[5 * n + 3];
+  pt[2 * n + 1] = (T)s5[5 * n + 4];
+}
+template <typename T>
+void launch_pack_state(hipStream_t st, const Grid& g, const double* s5, T* pt) {
+  hipLaunchKernelGGL(pack_state_kernel<T>, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g.nodes(), s5, pt);
+}
+
+template <typename T>
+__global__ void extract_pt_kernel(Grid g, const T* __restrict__ r5, T* __restrict__ b, T ip, T it) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.nodes()) return;
+  const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)), k = (int)(n / ((long)(g.nx + 1) * (g.ny + 1)));
+  b[2 * n] = g.pfix(i, j, k) ? (T)0 : ip * r5[5 * n + 3];
+  b[2 * n + 1] = g.tfix(i, j, k) ? (T)0 : it * r5[5 * n + 4];
+}
+template <typename T>
+void launch_extract_pt(hipStream_t st, const Grid& g, const T* r5, T* b, const Scale5<T>* rows) {
+  const T ip = rows ? (T)1 / rows->s[3] : (T)1, it = rows ? (T)1 / rows->s[4] : (T)1;
+  hipLaunchKernelGGL(extract_pt_kernel<T>, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, r5, b, ip, it);
+}
+
+template <typename T>
+__global__ void scatter_pt_kernel(Grid g, const T* __restrict__ x, const T* __restrict__ r5, T* __restrict__ z5, T ip,
+                                  T it) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.nodes()) return;
+  const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)), k = (int)(n / ((long)(g.nx + 1) * (g.ny + 1)));
+  z5[5 * n + 3] = g.pfix(i, j, k) ? ip * r5[5 * n + 3] : x[2 * n];
+  z5[5 * n + 4] = g.tfix(i, j, k) ? it * r5[5 * n + 4] : x[2 * n + 1];
+}
+template <typename T>
+void launch_scatter_pt(hipStream_t st, const Grid& g, const T* x, const T* r5, T* z5, const Scale5<T>* rows) {
+  const T ip = rows ? (T)1 / rows->s[3] : (T)1, it = rows ? (T)1 / rows->s[4] : (T)1;
+  hipLaunchKernelGGL(scatter_pt_kernel<T>, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, x, r5, z5, ip, it);
+}
+
+template <typename T>
+__global__ void scale5_kernel(long nodes, const double* __restrict__ a, T* __restrict__ b, Scale5<double> s) {
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < 5 * nodes; t += (long)gridDim.x * blockDim.x)
+    b[t] = (T)(s.s[t % 5] * a[t]);
+}
+template <typename T>
+void launch_scale5(hipStream_t st, long nodes, const double* a, T* b, Scale5<double> s) {
+  hipLaunchKernelGGL(scale5_kernel<T>, dim3(std::min(blocks_for(5 * nodes), 4096)), dim3(BS), 0, st, nodes, a, b, s);
+}
+
+__global__ void mask_state_kernel(Grid g, double* __restrict__ s5) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.nodes()) return;
+  const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)), k = (int)(n / ((long)(g.nx + 1) * (g.ny + 1)));
+  if (g.pfix(i, j, k)) s5[5 * n + 3] = 0.0;
+  if (g.tfix(i, j, k)) s5[5 * n + 4] = 0.0;
+}
+void launch_mask_state(hipStream_t st, const Grid& g, double* s5) {
+  hipLaunchKernelGGL(mask_state_kernel, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, s5);
+}
+
+template <typename Ta, typename Tb>
+__global__ void convert_kernel(const Ta* __restrict__ a, Tb* __restrict__ b, long n, double scale) {
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+    b[t] = (Tb)(scale * (double)a[t]);
+}
+template <typename Ta, typename Tb>
+void launch_convert(hipStream_t st, const Ta* a, Tb* b, long n, double scale) {
+  hipLaunchKernelGGL((convert_kernel<Ta, Tb>), dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, a, b, n, scale);
+}
+
+__global__ void axpy_kernel(double a, const double* __restrict__ x, const double* __restrict__ y, double* __restrict__ out, long n) {
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+    out[t] = a * x[t] + y[t];
+}
+void launch_axpy(hipStream_t st, double a, const double* x, const double* y, double* out, long n) {
+  hipLaunchKernelGGL(axpy_kernel, dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, a, x, y, out, n);
+}
+
+
+// x = omega D^-1 b (or D^-T): the first damped block-Jacobi sweep from a zero iterate
+template <typename T>
+__global__ void diag_scale_kernel(long N, const T* __restrict__ dinv, int transpose, T omega, const T* __restrict__ b,
+                                  T* __restrict__ x) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const T* D = dinv + 4 * n;
+  const T bp = b[2 * n], bt = b[2 * n + 1];
+  if (!transpose) {
+    x[2 * n] = omega * (D[0] * bp + D[1] * bt);
+    x[2 * n + 1] = omega * (D[2] * bp + D[3] * bt);
+  } else {
+    x[2 * n] = omega * (D[0] * bp + D[2] * bt);
+    x[2 * n + 1] = omega * (D[1] * bp + D[3] * bt);
+  }
+}
+template <typename T>
+void launch_diag_scale(hipStream_t st, const Grid& g, const T* dinv, bool transpose, T omega, const T* b, T* x) {
+  hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g.nodes(), dinv,
+                     transpose ? 1 : 0, omega, b, x);
+}
+
+// out = b - out  (restart residual)
+template <typename T>
+__global__ void rsub_kernel(const T* __restrict__ b, T* __restrict__ out, long n) {
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+    out[t] = b[t] - out[t];
+}
+template <typename T>
+void launch_rsub(hipStream_t st, const T* b, T* out, long n) {
+  hipLaunchKernelGGL(rsub_kernel<T>, dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, b, out, n);
+}
+
+// ------------------------------------------------------------------ reductions
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// part[block][c] = partial sum over this block's chunk of V[c] . w
+template <typename T>
+__global__ __launch_bounds__(BS) void mdot_kernel(const T* __restrict__ V, long ld, int cnt, const T* __restrict__ w,
+                                                  long n, double* __restrict__ part) {
+  __shared__ double red[BS / 64][MAXC];
+  double acc[MAXC];
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) acc[c] = 0.0;
+  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < n; t += (long)gridDim.x * BS) {
+    const double wv = (double)w[t];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c)
+      if (c < cnt) acc[c] += (double)V[c * ld + t] * wv;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) {
+    if (c < cnt) {
+      const double s = wave_sum(acc[c]);
+      if (lane == 0) red[wid][c] = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < cnt) {
+    double s = 0.0;
+    for (int w2 = 0; w2 < BS / 64; ++w2) s += red[w2][threadIdx.x];
+    part[blockIdx.x * MAXC + threadIdx.x] = s;
+  }
+}
+
+// out[c] = sum over blocks of part[b][c] (fixed order); sqrt if do_sqrt
+__global__ void reduce_parts_kernel(const double* __restrict__ part, int nblk, int cnt, double* __restrict__ out, int do_sqrt) {
+  const int c = threadIdx.x;
+  if (c >= cnt) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[b * MAXC + c];
+  out[c] = do_sqrt ? sqrt(s) : s;
+}
+
+template <typename T>
+void launch_mdot(hipStream_t st, const T* V, long ld, int cnt, const T* w, long n, double* part, double* out) {
+  hipLaunchKernelGGL(mdot_kernel<T>, dim3(RED_BLOCKS), dim3(BS), 0, st, V, ld, cnt, w, n, part);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, cnt, out, 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void maxpy_kernel(const T* __restrict__ V, long ld, int cnt, const double* __restrict__ h,
+                                                   double sign, T* __restrict__ w, long n, double* __restrict__ part) {
+  __shared__ double hs[MAXC];
+  __shared__ double red[BS / 64];
+  if (threadIdx.x < cnt) hs[threadIdx.x] = sign * h[threadIdx.x];
+  __syncthreads();
+  double nrm = 0.0;
+  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < n; t += (long)gridDim.x * BS) {
+    double v = (double)w[t];
+    for (int c = 0; c < cnt; ++c) v += hs[c] * (double)V[c * ld + t];
+    const T vt = (T)v;
+    w[t] = vt;
+    nrm += (double)vt * (double)vt;
+  }
+  if (part) {
+    const double s = wave_sum(nrm);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (int w2 = 0; w2 < BS / 64; ++w2) tot += red[w2];
+      part[blockIdx.x * MAXC] = tot;
+    }
+  }
+}
+
+template <typename T>
+void launch_maxpy(hipStream_t st, const T* V, long ld, int cnt, const double* h, double sign, T* w, long n, double* part,
+                  double* nrm_out) {
+  hipLaunchKernelGGL(maxpy_kernel<T>, dim3(RED_BLOCKS), dim3(BS), 0, st, V, ld, cnt, h, sign, w, n,
+                     nrm_out ? part : nullptr);
+  if (nrm_out) hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, 1, nrm_out, 1);
+}
+
+template <typename T>
+__global__ void scale_inv_kernel(const double* __restrict__ nrm, const T* __restrict__ w, T* __restrict__ v, long n) {
+  const double s = 1.0 / nrm[0];
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+    v[t] = (T)(s * (double)w[t]);
+}
+template <typename T>
+void launch_scale_inv(hipStream_t st, const double* nrm, const T* w, T* v, long n) {
+  hipLaunchKernelGGL(scale_inv_kernel<T>, dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, nrm, w, v, n);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void norm_kernel(const T* __restrict__ a, long n, double* __restrict__ part) {
+  __shared__ double red[BS / 64];
+  double s = 0.0;
+  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < n; t += (long)gridDim.x * BS) {
+    const double v = (double)a[t];
+    s += v * v;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w2 = 0; w2 < BS / 64; ++w2) tot += red[w2];
+    part[blockIdx.x * MAXC] = tot;
+  }
+}
+template <typename T>
+void launch_norm(hipStream_t st, const T* a, long n, double* part, double* out) {
+  hipLaunchKernelGGL(norm_kernel<T>, dim3(RED_BLOCKS), dim3(BS), 0, st, a, n, part);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, 1, out, 1);
+}
+
+__global__ __launch_bounds__(BS) void field_norms_kernel(const double* __restrict__ a, const double* __restrict__ b,
+                                                         long nodes, double* __restrict__ part) {
+  __shared__ double red[BS / 64][10];
+  double s[10];
+#pragma unroll
+  for (int f = 0; f < 10; ++f) s[f] = 0.0;
+  for (long n = (long)blockIdx.x * BS + threadIdx.x; n < nodes; n += (long)gridDim.x * BS) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      const double v = a[5 * n + f];
+      s[f] += v * v;
+      if (b) {
+        const double u = b[5 * n + f];
+        s[5 + f] += u * u;
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int f = 0; f < 10; ++f) {
+    const double t = wave_sum(s[f]);
+    if (lane == 0) red[wid][f] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 10) {
+    double tot = 0.0;
+    for (int w2 = 0; w2 < BS / 64; ++w2) tot += red[w2][threadIdx.x];
+    part[blockIdx.x * MAXC + threadIdx.x] = tot;
+  }
+}
+void launch_field_norms(hipStream_t st, const double* a, const double* b, long nodes, double* part, double* out) {
+  hipLaunchKernelGGL(field_norms_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, a, b, nodes, part);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, 10, out, 1);
+}
+
+// ------------------------------------------------------------------ design chain
+// Cone filter y_e = sum_j w_ej x_j / sum_j w_ej, w_ej = max(0, R - |c_e - c_j| / h) over
+// in-grid elements.  Transpose: y_j = sum_e w_ej (x_e / W_e), done as tmp_e = x_e / W_e
+// followed by the unnormalised symmetric stencil.
+__device__ inline double cone_weight_sum(const Grid& g, int i, int j, int k, double R, int r) {
+  double ws = 0.0;
+  for (int dk = -r; dk <= r; ++dk)
+    for (int dj = -r; dj <= r; ++dj)
+      for (int di = -r; di <= r; ++di) {
+        const double w = R - sqrt((double)(di * di + dj * dj + dk * dk));
+        const int a = i + di, b = j + dj, c = k + dk;
+        if (w > 0.0 && a >= 0 && a < g.nx && b >= 0 && b < g.ny && c >= 0 && c < g.nz) ws += w;
+      }
+  return ws;
+}
+
+__global__ void cone_kernel(Grid g, double R, int r, const double* __restrict__ x, double* __restrict__ y, int mode) {
+  // mode 0: normalised forward; 1: divide by W (first pass of the transpose);
+  // 2: unnormalised stencil (second pass of the transpose)
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.elems()) return;
+  const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((long)g.nx * g.ny));
+  if (mode == 1) {
+    y[e] = x[e] / cone_weight_sum(g, i, j, k, R, r);
+    return;
+  }
+  double s = 0.0, ws = 0.0;
+  for (int dk = -r; dk <= r; ++dk)
+    for (int dj = -r; dj <= r; ++dj)
+      for (int di = -r; di <= r; ++di) {
+        const double w = R - sqrt((double)(di * di + dj * dj + dk * dk));
+        const int a = i + di, b = j + dj, c = k + dk;
+        if (w > 0.0 && a >= 0 && a < g.nx && b >= 0 && b < g.ny && c >= 0 && c < g.nz) {
+          s += w * x[g.elem(a, b, c)];
+          ws += w;
+        }
+      }
+  y[e] = mode == 0 ? s / ws : s;
+}
+
+void launch_cone_filter(hipStream_t st, const Grid& g, double radius, const double* x, double* y, bool transpose,
+                        double* tmp) {
+  const long E = g.elems();
+  if (radius <= 0.0) {
+    (void)hipMemcpyAsync(y, x, sizeof(double) * E, hipMemcpyDeviceToDevice, st);
+    return;
+  }
+  const int r = (int)ceil(radius);
+  if (!transpose) {
+    hipLaunchKernelGGL(cone_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, g, radius, r, x, y, 0);
+  } else {
+    hipLaunchKernelGGL(cone_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, g, radius, r, x, tmp, 1);
+    hipLaunchKernelGGL(cone_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, g, radius, r, tmp, y, 2);
+  }
+}
+
+__global__ void ramp_kernel(long E, const double* __restrict__ gam, double k_f, double k_s, double q_c, double kap_f,
+                            double kap_s, double q_p, double* __restrict__ c64, float* __restrict__ c32,
+                            double* __restrict__ dk, double* __restrict__ dkap) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  double k, kap, a, b;
+  ramp<double>(gam[e], k_f, k_s, q_c, kap_f, kap_s, q_p, k, kap, a, b);
+  c64[2 * e] = k;
+  c64[2 * e + 1] = kap;
+  c32[2 * e] = (float)k;
+  c32[2 * e + 1] = (float)kap;
+  dk[e] = a;
+  dkap[e] = b;
+}
+void launch_ramp(hipStream_t st, long E, const double* gamma, double k_f, double k_s, double q_c, double kap_f,
+                 double kap_s, double q_p, double* coef64, float* coef32, double* dk, double* dkap) {
+  hipLaunchKernelGGL(ramp_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, E, gamma, k_f, k_s, q_c, kap_f, kap_s, q_p,
+                     coef64, coef32, dk, dkap);
+}
+
+// ------------------------------------------------------------------ sensitivities
+__global__ void sensitivity_kernel(Grid g, ElemConst<double> c, const double* __restrict__ coef,
+                                   const double* __restrict__ dk, const double* __restrict__ dkap,
+                                   const double* __restrict__ s5, const double* __restrict__ l5, double* __restrict__ out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.elems()) return;
+  const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((long)g.nx * g.ny));
+  double P[8], Tn[8], lP[8], lT[8], lU[3][8];
+  for (int a = 0; a < 8; ++a) {
+    const int ii = i + (a & 1), jj = j + ((a >> 1) & 1), kk = k + ((a >> 2) & 1);
+    const long n = g.node(ii, jj, kk);
+    P[a] = s5[5 * n + 3];
+    Tn[a] = s5[5 * n + 4];
+    lP[a] = g.pfix(ii, jj, kk) ? 0.0 : l5[5 * n + 3];
+    lT[a] = g.tfix(ii, jj, kk) ? 0.0 : l5[5 * n + 4];
+    for (int d = 0; d < 3; ++d) lU[d][a] = l5[5 * n + d];
+  }
+  Lin<double> L;
+  linearize(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+  out[e] = elem_sensitivity<double, true>(L, lP, lT, lU, dk[e], dkap[e], c);
+}
+void launch_sensitivity(hipStream_t st, const Grid& g, const ElemConst<double>& c, const double* coef,
+                        const double* dk, const double* dkap, const double* s5, const double* lam5, double* out) {
+  hipLaunchKernelGGL(sensitivity_kernel, dim3(blocks_for(g.elems())), dim3(BS), 0, st, g, c, coef, dk, dkap, s5, lam5, out);
+}
+
+// ------------------------------------------------------------------ coefficient means
+__global__ __launch_bounds__(BS) void coef_sum_kernel(const double* __restrict__ coef, long E, double* __restrict__ part) {
+  __shared__ double red[BS / 64][2];
+  double a = 0.0, b = 0.0;
+  for (long e = (long)blockIdx.x * BS + threadIdx.x; e < E; e += (long)gridDim.x * BS) {
+    a += coef[2 * e];
+    b += coef[2 * e + 1];
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6][0] = a; red[threadIdx.x >> 6][1] = b; }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double tot = 0.0;
+    for (int w2 = 0; w2 < BS / 64; ++w2) tot += red[w2][threadIdx.x];
+    part[blockIdx.x * MAXC + threadIdx.x] = tot;
+  }
+}
+void launch_coef_sums(hipStream_t st, const double* coef, long E, double* part, double* out) {
+  hipLaunchKernelGGL(coef_sum_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, coef, E, part);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, 2, out, 0);
+}
+
+// ------------------------------------------------------------------ objective
+// f = sum over patch faces of q_h h^2/4 (T of the face's four nodes)
+__global__ __launch_bounds__(BS) void objective_kernel(Grid g, Patch pa, const double* __restrict__ s5, double* __restrict__ part) {
+  __shared__ double red[BS / 64];
+  double s = 0.0;
+  const long F = (long)g.nx * g.ny;
+  for (long f = (long)blockIdx.x * BS + threadIdx.x; f < F; f += (long)gridDim.x * BS) {
+    const int i = (int)(f % g.nx), j = (int)(f / g.nx);
+    if (!pa.has(i, j)) continue;
+    const double w = pa.q_h * pa.h * pa.h * 0.25;
+    for (int c = 0; c < 4; ++c) s += w * s5[5 * g.node(i + (c & 1), j + (c >> 1), 0) + 4];
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w2 = 0; w2 < BS / 64; ++w2) tot += red[w2];
+    part[blockIdx.x * MAXC] = tot;
+  }
+}
+void launch_objective(hipStream_t st, const Grid& g, const Patch& patch, const double* s5, double* part, double* out) {
+  hipLaunchKernelGGL(objective_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, g, patch, s5, part);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, 1, out, 0);
+}
+
+__global__ void objective_grad_kernel(Grid g, Patch pa, double* __restrict__ g5) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.nodes()) return;
+  const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)), k = (int)(n / ((long)(g.nx + 1) * (g.ny + 1)));
+  double v = 0.0;
+  if (k == 0 && !g.tfix(i, j, k)) {
+    const double w = pa.q_h * pa.h * pa.h * 0.25;
+    for (int c = 0; c < 4; ++c) {
+      const int fi = i - (c & 1), fj = j - (c >> 1);
+      if (fi >= 0 && fi < g.nx && fj >= 0 && fj < g.ny && pa.has(fi, fj)) v += w;
+    }
+  }
+  for (int f = 0; f < 4; ++f) g5[5 * n + f] = 0.0;
+  g5[5 * n + 4] = v;
+}
+void launch_objective_grad(hipStream_t st, const Grid& g, const Patch& patch, double* g5) {
+  hipLaunchKernelGGL(objective_grad_kernel, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, patch, g5);
+}
+
+// ------------------------------------------------------------------ instantiations
+#define NC_INST(T)                                                                                   \
+  template void launch_restrict<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);            \
+  template void launch_prolong_add<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);         \
+  template void launch_inject_state<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);        \
+  template void launch_average_coef<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);        \
+  template void launch_coarse_assemble<T>(hipStream_t, const LevelView<T>&, double*, double*);      \
+  template void launch_dense_apply<T>(hipStream_t, const double*, int, bool, const T*, T*);         \
+  template void launch_pack_state<T>(hipStream_t, const Grid&, const double*, T*);                  \
+  template void launch_extract_pt<T>(hipStream_t, const Grid&, const T*, T*, const Scale5<T>*);     \
+  template void launch_scatter_pt<T>(hipStream_t, const Grid&, const T*, const T*, T*, const Scale5<T>*); \
+  template void launch_scale5<T>(hipStream_t, long, const double*, T*, Scale5<double>);             \
+  template void launch_mdot<T>(hipStream_t, const T*, long, int, const T*, long, double*, double*); \
+  template void launch_maxpy<T>(hipStream_t, const T*, long, int, const double*, double, T*, long, double*, double*); \
+  template void launch_scale_inv<T>(hipStream_t, const double*, const T*, T*, long);                \
+  template void launch_norm<T>(hipStream_t, const T*, long, double*, double*);                     \
+  template void launch_diag_scale<T>(hipStream_t, const Grid&, const T*, bool, T, const T*, T*);    \
+  template void launch_rsub<T>(hipStream_t, const T*, T*, long);
+NC_INST(double)
+NC_INST(float)
+#undef NC_INST
+template void launch_convert<double, float>(hipStream_t, const double*, float*, long, double);
+template void launch_convert<float, double>(hipStream_t, const float*, double*, long, double);
+template void launch_convert<double, double>(hipStream_t, const double*, double*, long, double);
+template void launch_convert<float, float>(hipStream_t, const float*, float*, long, double);
+
+}  // namespace nc

@@ -1,0 +1,103 @@
+// Host-side launchers of the solver's HIP kernels.  All launches are asynchronous on
+// the given stream; device pointers only.
+#pragma once
+
+#include "common.hpp"
+
+namespace nc {
+
+enum ApplyMode { MODE_STORE = 0, MODE_RESID = 1, MODE_SMOOTH = 2 };
+
+// ---- operator kernels (z-march over element columns, deterministic node accumulation)
+// r = R~(s), float64, five fields per node (row a2)
+void launch_residual(hipStream_t st, const Grid& g, const ElemConst<double>& c, const Patch& patch,
+                     const double* coef, const double* s, double* r);
+// y = J~ x (five fields) at the level's linearisation (row a4)
+template <typename T>
+void launch_jv5(hipStream_t st, const LevelView<T>& L, const T* x, T* y, const Scale5<T>* rows = nullptr);
+// y = J~^T w (five fields) (row a5)
+template <typename T>
+void launch_jtw5(hipStream_t st, const LevelView<T>& L, const T* w, T* y, const Scale5<T>* rows = nullptr);
+// Two-field (P, T) operator of a multigrid level: y = A x, r = b - A x, or one damped
+// block-Jacobi sweep y = x + omega D^-1 (b - A x); transpose selects A^T.
+template <typename T>
+void launch_pt_apply(hipStream_t st, const LevelView<T>& L, bool transpose, int mode, const T* x, const T* b,
+                     T* y, T omega);
+// Inverse 2x2 (P, T) node blocks of the level Jacobian into dinv [N][4].
+template <typename T>
+void launch_diag_inverse(hipStream_t st, const LevelView<T>& L, T* dinv);
+// Preconditioner pieces coupling the velocity rows (block-triangular structure):
+//   forward: z = [ (r_u - C x)/M ; x ] with x the (P, T) correction (constrained dofs: z = r)
+// (r5 is divided by the row scales `rows` on input when given)
+template <typename T>
+void launch_uproj(hipStream_t st, const LevelView<T>& L, const T* x_pt, const T* r5, T* z5, const Scale5<T>* rows = nullptr);
+//   transpose: z_u = r_u / M, b = r_PT - C^T z_u (masked)
+template <typename T>
+void launch_uprojT(hipStream_t st, const LevelView<T>& L, const T* r5, T* b_pt, T* z5, const Scale5<T>* rows = nullptr);
+
+// ---- multigrid transfers and setup
+template <typename T>
+void launch_restrict(hipStream_t st, const Grid& fine, const Grid& coarse, const T* rf, T* bc);
+template <typename T>
+void launch_prolong_add(hipStream_t st, const Grid& fine, const Grid& coarse, const T* xc, T* xf);
+template <typename T>
+void launch_inject_state(hipStream_t st, const Grid& fine, const Grid& coarse, const T* sf, T* sc);
+template <typename T>
+void launch_average_coef(hipStream_t st, const Grid& fine, const Grid& coarse, const T* cf, T* cc);
+// coarsest level: element matrices, dense assembly (constrained rows/cols -> identity),
+// in-place Gauss-Jordan inverse with partial pivoting, dense (transposed) mat-vec
+template <typename T>
+void launch_coarse_assemble(hipStream_t st, const LevelView<T>& L, double* elem_mats, double* A);
+void launch_gauss_jordan(hipStream_t st, double* A, int n, int* perm);
+template <typename T>
+void launch_dense_apply(hipStream_t st, const double* Ainv, int n, bool transpose, const T* b, T* x);
+
+// ---- state / vector helpers
+template <typename T>
+void launch_pack_state(hipStream_t st, const Grid& g, const double* s5, T* pt);           // (P, T) of s
+template <typename T>
+void launch_extract_pt(hipStream_t st, const Grid& g, const T* r5, T* b, const Scale5<T>* rows = nullptr);  // masked
+template <typename T>
+void launch_scatter_pt(hipStream_t st, const Grid& g, const T* x, const T* r5, T* z5,
+                       const Scale5<T>* rows = nullptr);                                  // z_PT = x, z_c = r_c
+template <typename T>
+void launch_scale5(hipStream_t st, long nodes, const double* a, T* b, Scale5<double> s);   // b = s_f a_f
+void launch_mask_state(hipStream_t st, const Grid& g, double* s5);                       // constrained -> 0
+template <typename Ta, typename Tb>
+void launch_convert(hipStream_t st, const Ta* a, Tb* b, long n, double scale);           // b = scale * a
+void launch_axpy(hipStream_t st, double a, const double* x, const double* y, double* out, long n);  // out = a x + y
+
+template <typename T>
+void launch_diag_scale(hipStream_t st, const Grid& g, const T* dinv, bool transpose, T omega, const T* b, T* x);
+template <typename T>
+void launch_rsub(hipStream_t st, const T* b, T* out, long n);                          // out = b - out
+
+// ---- reductions (deterministic: fixed grid, fixed order)
+constexpr int RED_BLOCKS = 240;
+constexpr int MAXC = 32;
+template <typename T>
+void launch_mdot(hipStream_t st, const T* V, long ld, int cnt, const T* w, long n, double* part, double* out);
+// w += sign * sum_c h[c] V[c]; if nrm_out != null also nrm_out[0] = ||w||_2 after the update
+template <typename T>
+void launch_maxpy(hipStream_t st, const T* V, long ld, int cnt, const double* h, double sign, T* w, long n,
+                  double* part, double* nrm_out);
+template <typename T>
+void launch_scale_inv(hipStream_t st, const double* nrm, const T* w, T* v, long n);
+// per-field 2-norms of [N][5] arrays: out[f] = ||a_f||, and if b != null out[5+f] = ||b_f||
+void launch_field_norms(hipStream_t st, const double* a, const double* b, long nodes, double* part, double* out);
+template <typename T>
+void launch_norm(hipStream_t st, const T* a, long n, double* part, double* out);
+
+// ---- design chain and sensitivities
+void launch_cone_filter(hipStream_t st, const Grid& g, double radius, const double* x, double* y, bool transpose,
+                        double* tmp);
+void launch_ramp(hipStream_t st, long E, const double* gamma, double k_f, double k_s, double q_c, double kap_f,
+                 double kap_s, double q_p, double* coef64, float* coef32, double* dk, double* dkap);
+void launch_sensitivity(hipStream_t st, const Grid& g, const ElemConst<double>& c, const double* coef,
+                        const double* dk, const double* dkap, const double* s5, const double* lam5, double* out);
+// out[0] = sum_e k_e, out[1] = sum_e kappa_e
+void launch_coef_sums(hipStream_t st, const double* coef, long E, double* part, double* out);
+void launch_objective(hipStream_t st, const Grid& g, const Patch& patch, const double* s5, double* part, double* out);
+void launch_objective_grad(hipStream_t st, const Grid& g, const Patch& patch, double* g5);
+
+}  // namespace nc

@@ -1,0 +1,764 @@
+// Solver runtime behind the C ABI of include/nc.h: context and workspace carving, the
+// multigrid hierarchy, flexible GMRES, the damped Newton iteration (Sec. 5.4), the
+// adjoint solve with iterative refinement and the sensitivities (Sec. 5.1).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+#include "../../include/nc.h"
+
+using namespace nc;
+
+namespace {
+
+constexpr int MAXLEV = 10;
+constexpr size_t ALIGN = 256;
+
+struct Level {
+  Grid g;
+  double h;
+  ElemConst<double> c64;
+  ElemConst<float> c32;
+  double* coef64;
+  float* coef32;
+  double* st64;
+  float* st32;
+  void* dinv;   // [N][4] in the working precision
+  void* x;      // V-cycle iterate, ping-pong partner, right-hand side, residual: [N][2]
+  void* x2;
+  void* b;
+  void* r;
+};
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + ALIGN - 1) / ALIGN * ALIGN;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct HipError {
+  hipError_t e;
+};
+
+inline void ck(hipError_t e) {
+  if (e != hipSuccess) throw HipError{e};
+}
+
+}  // namespace
+
+struct nc_ctx {
+  nc_problem p;
+  hipStream_t stream;
+  bool mixed;
+  int L;
+  Level lev[MAXLEV];
+  Patch patch;
+  long N, E, n5;
+  int m;                 // Krylov restart length
+  // design chain
+  double *gamma, *dk, *dkap, *ftmp, *sens;
+  // coarsest level
+  double *emats, *A;
+  int* perm;
+  int ncoarse;
+  bool dense;            // coarsest level solved by the dense inverse (else smoothing only)
+  // Krylov space in the working precision
+  void *V, *Z, *kx, *kb;
+  // reductions
+  double *part, *dres;
+  double* hbuf;          // pinned host mirror of dres
+  // float64 Newton / adjoint vectors
+  double *R, *d, *strial, *ra, *tmp5;
+  // per-field row equilibration of the five-field system inside FGMRES
+  Scale5<double> rows64;
+  Scale5<float> rows32;
+  // bookkeeping
+  bool design_set;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ setup helpers
+bool valid_problem(const nc_problem* p) {
+  if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
+  if (p->mu <= 0 || p->kappa_s <= 0 || p->kappa_f <= 0 || p->k_f <= 0 || p->k_s <= 0) return false;
+  if (p->precision != NC_FP64 && p->precision != NC_MIXED) return false;
+  if (p->krylov_restart < 1 || p->krylov_restart > MAXC - 2) return false;
+  return true;
+}
+
+int choose_levels(const nc_problem* p, Grid* gs) {
+  Grid g{p->nx, p->ny, p->nz};
+  gs[0] = g;
+  int L = 1;
+  const int cap = p->levels > 0 ? std::min(p->levels, MAXLEV) : MAXLEV;
+  while (L < cap) {
+    const Grid& f = gs[L - 1];
+    if ((f.nx & 1) || (f.ny & 1) || (f.nz & 1)) break;
+    if (f.nx / 2 < 2 || f.ny / 2 < 2 || f.nz / 2 < 2) break;
+    if (p->levels <= 0 && 2 * f.nodes() <= 300) break;
+    gs[L] = Grid{f.nx / 2, f.ny / 2, f.nz / 2};
+    ++L;
+  }
+  return L;
+}
+
+// Lays out every device buffer in the workspace (base == nullptr: size query only).
+size_t carve(nc_ctx* c, char* base) {
+  Carver cv{base};
+  const nc_problem& p = c->p;
+  Grid gs[MAXLEV];
+  c->L = choose_levels(&p, gs);
+  c->mixed = p.precision == NC_MIXED;
+  const size_t rs = c->mixed ? sizeof(float) : sizeof(double);
+  const double h0 = p.h > 0 ? p.h : 1.0 / p.nx;
+  for (int l = 0; l < c->L; ++l) {
+    Level& L = c->lev[l];
+    L.g = gs[l];
+    L.h = h0 * (1 << l);
+    L.c64 = make_elem_const<double>(L.h, p.rho0, p.mu, p.cp, p.g0, p.alpha, p.Q);
+    L.c32 = make_elem_const<float>(L.h, p.rho0, p.mu, p.cp, p.g0, p.alpha, p.Q);
+    const long N = L.g.nodes(), E = L.g.elems();
+    L.coef64 = cv.take<double>(2 * E);
+    L.coef32 = cv.take<float>(2 * E);
+    L.st64 = cv.take<double>(2 * N);
+    L.st32 = cv.take<float>(2 * N);
+    L.dinv = cv.take<char>(4 * N * rs);
+    L.x = cv.take<char>(2 * N * rs);
+    L.x2 = cv.take<char>(2 * N * rs);
+    L.b = cv.take<char>(2 * N * rs);
+    L.r = cv.take<char>(2 * N * rs);
+  }
+  c->N = gs[0].nodes();
+  c->E = gs[0].elems();
+  c->n5 = 5 * c->N;
+  c->m = p.krylov_restart;
+  c->gamma = cv.take<double>(c->E);
+  c->dk = cv.take<double>(c->E);
+  c->dkap = cv.take<double>(c->E);
+  c->ftmp = cv.take<double>(c->E);
+  c->sens = cv.take<double>(c->E);
+  const Grid& gc = c->lev[c->L - 1].g;
+  c->ncoarse = (int)(2 * gc.nodes());
+  c->dense = c->ncoarse <= 2000;
+  c->emats = cv.take<double>(c->dense ? gc.elems() * 256 : 1);
+  c->A = cv.take<double>(c->dense ? (size_t)c->ncoarse * c->ncoarse : 1);
+  c->perm = cv.take<int>(c->dense ? c->ncoarse : 1);
+  c->V = cv.take<char>((size_t)(c->m + 1) * c->n5 * rs);
+  c->Z = cv.take<char>((size_t)c->m * c->n5 * rs);
+  c->kx = cv.take<char>(c->n5 * rs);
+  c->kb = cv.take<char>(c->n5 * rs);
+  c->part = cv.take<double>(RED_BLOCKS * MAXC);
+  c->dres = cv.take<double>(4 * MAXC);
+  c->R = cv.take<double>(c->n5);
+  c->d = cv.take<double>(c->n5);
+  c->strial = cv.take<double>(c->n5);
+  c->ra = cv.take<double>(c->n5);
+  c->tmp5 = cv.take<double>(c->n5);
+  return cv.off + ALIGN;
+}
+
+template <typename T>
+LevelView<T> view(nc_ctx* c, int l);
+template <>
+LevelView<double> view<double>(nc_ctx* c, int l) {
+  Level& L = c->lev[l];
+  return LevelView<double>{L.g, L.c64, L.coef64, L.st64, (const double*)L.dinv};
+}
+template <>
+LevelView<float> view<float>(nc_ctx* c, int l) {
+  Level& L = c->lev[l];
+  return LevelView<float>{L.g, L.c32, L.coef32, L.st32, (const float*)L.dinv};
+}
+
+void sync(nc_ctx* c) { ck(hipStreamSynchronize(c->stream)); }
+
+void fetch(nc_ctx* c, const double* dev, int count) {
+  ck(hipMemcpyAsync(c->hbuf, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+}
+
+// ------------------------------------------------------------------ linearisation
+template <typename T>
+void linearize_levels(nc_ctx* c) {
+  hipStream_t st = c->stream;
+  for (int l = 1; l < c->L; ++l) {
+    if (sizeof(T) == 8)
+      launch_inject_state<double>(st, c->lev[l - 1].g, c->lev[l].g, c->lev[l - 1].st64, c->lev[l].st64);
+    else
+      launch_inject_state<float>(st, c->lev[l - 1].g, c->lev[l].g, c->lev[l - 1].st32, c->lev[l].st32);
+  }
+  for (int l = 0; l < c->L; ++l) launch_diag_inverse<T>(st, view<T>(c, l), (T*)c->lev[l].dinv);
+  if (c->dense) {
+    launch_coarse_assemble<T>(st, view<T>(c, c->L - 1), c->emats, c->A);
+    launch_gauss_jordan(st, c->A, c->ncoarse, c->perm);
+  }
+}
+
+void linearize(nc_ctx* c, const double* s, bool levels) {
+  hipStream_t st = c->stream;
+  launch_pack_state<double>(st, c->lev[0].g, s, c->lev[0].st64);
+  launch_pack_state<float>(st, c->lev[0].g, s, c->lev[0].st32);
+  if (!levels) return;
+  if (c->mixed) linearize_levels<float>(c);
+  else linearize_levels<double>(c);
+}
+
+// ------------------------------------------------------------------ V-cycle
+template <typename T>
+void vcycle(nc_ctx* c, int l, bool tr) {
+  hipStream_t st = c->stream;
+  Level& L = c->lev[l];
+  const T om = (T)c->p.smooth_omega;
+  LevelView<T> v = view<T>(c, l);
+  if (l == c->L - 1) {
+    if (c->dense) {
+      launch_dense_apply<T>(st, c->A, c->ncoarse, tr, (const T*)L.b, (T*)L.x);
+    } else {
+      launch_diag_scale<T>(st, L.g, (const T*)L.dinv, tr, om, (const T*)L.b, (T*)L.x);
+      for (int s = 1; s < 8; ++s) {
+        launch_pt_apply<T>(st, v, tr, MODE_SMOOTH, (const T*)L.x, (const T*)L.b, (T*)L.x2, om);
+        std::swap(L.x, L.x2);
+      }
+    }
+    return;
+  }
+  launch_diag_scale<T>(st, L.g, (const T*)L.dinv, tr, om, (const T*)L.b, (T*)L.x);
+  for (int s = 1; s < c->p.smooth_pre; ++s) {
+    launch_pt_apply<T>(st, v, tr, MODE_SMOOTH, (const T*)L.x, (const T*)L.b, (T*)L.x2, om);
+    std::swap(L.x, L.x2);
+  }
+  launch_pt_apply<T>(st, v, tr, MODE_RESID, (const T*)L.x, (const T*)L.b, (T*)L.r, om);
+  Level& C = c->lev[l + 1];
+  launch_restrict<T>(st, L.g, C.g, (const T*)L.r, (T*)C.b);
+  vcycle<T>(c, l + 1, tr);
+  launch_prolong_add<T>(st, L.g, C.g, (const T*)C.x, (T*)L.x);
+  for (int s = 0; s < c->p.smooth_post; ++s) {
+    launch_pt_apply<T>(st, v, tr, MODE_SMOOTH, (const T*)L.x, (const T*)L.b, (T*)L.x2, om);
+    std::swap(L.x, L.x2);
+  }
+}
+
+// z = P^-1 r for the block-triangular Jacobian: multigrid on the (P, T) block and exact
+// back-substitution of the lumped-mass velocity rows.
+// r5 is a residual of the row-scaled system D A x = D b when `rows` is given.
+template <typename T>
+void precondition(nc_ctx* c, bool tr, const T* r5, T* z5, const Scale5<T>* rows) {
+  hipStream_t st = c->stream;
+  Level& L0 = c->lev[0];
+  LevelView<T> v0 = view<T>(c, 0);
+  if (!tr) {
+    launch_extract_pt<T>(st, L0.g, r5, (T*)L0.b, rows);
+    vcycle<T>(c, 0, false);
+    launch_uproj<T>(st, v0, (const T*)L0.x, r5, z5, rows);
+  } else {
+    launch_uprojT<T>(st, v0, r5, (T*)L0.b, z5, rows);
+    vcycle<T>(c, 0, true);
+    launch_scatter_pt<T>(st, L0.g, (const T*)L0.x, r5, z5, rows);
+  }
+}
+
+template <typename T>
+void apply_op(nc_ctx* c, bool tr, const T* x, T* y, const Scale5<T>* rows) {
+  if (!tr) launch_jv5<T>(c->stream, view<T>(c, 0), x, y, rows);
+  else launch_jtw5<T>(c->stream, view<T>(c, 0), x, y, rows);
+}
+
+template <typename T>
+const Scale5<T>* row_scales(nc_ctx* c);
+template <>
+const Scale5<double>* row_scales<double>(nc_ctx* c) { return &c->rows64; }
+template <>
+const Scale5<float>* row_scales<float>(nc_ctx* c) { return &c->rows32; }
+
+// Constant per-field row scales ~ 1 / (diagonal of each field's block): lumped mass for
+// the velocity rows, (8h/3) kappa_mean/mu and (8h/3) k_mean for the P and T rows.
+void compute_row_scales(nc_ctx* c) {
+  const Level& L0 = c->lev[0];
+  launch_coef_sums(c->stream, L0.coef64, c->E, c->part, c->dres);
+  fetch(c, c->dres, 2);
+  const double km = c->hbuf[0] / c->E, kapm = c->hbuf[1] / c->E;
+  const double lap = 8.0 * L0.h / 3.0;
+  const double du = 1.0 / (8.0 * L0.c64.W), dp = 1.0 / (lap * kapm / c->p.mu), dt = 1.0 / (lap * km);
+  c->rows64 = Scale5<double>{{du, du, du, dp, dt}};
+  c->rows32 = Scale5<float>{{(float)du, (float)du, (float)du, (float)dp, (float)dt}};
+}
+
+// ------------------------------------------------------------------ flexible GMRES
+// Solves Op x = b (Op = J~ or J~^T) from x = 0 with right preconditioning; classical
+// Gram-Schmidt with one re-orthogonalisation; Hessenberg least squares on the host.
+template <typename T>
+int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double* relres) {
+  hipStream_t st = c->stream;
+  const Scale5<T>* rows = row_scales<T>(c);
+  const long n = c->n5;
+  const int m = c->m;
+  T* V = (T*)c->V;
+  T* Z = (T*)c->Z;
+  double* dres = c->dres;
+  ck(hipMemsetAsync(x, 0, sizeof(T) * n, st));
+  launch_norm<T>(st, b, n, c->part, dres);
+  fetch(c, dres, 1);
+  const double bnorm = c->hbuf[0];
+  *relres = 0.0;
+  if (!(bnorm > 0.0)) return bnorm == 0.0 ? 0 : -1;
+  launch_scale_inv<T>(st, dres, b, V, n);
+  double beta = bnorm;
+  int total = 0;
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  while (true) {
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    bool done = false;
+    for (int j = 0; j < m; ++j) {
+      T* vj = V + (long)j * n;
+      T* w = V + (long)(j + 1) * n;
+      T* zj = Z + (long)j * n;
+      precondition<T>(c, tr, vj, zj, rows);
+      apply_op<T>(c, tr, zj, w, rows);
+      launch_mdot<T>(st, V, n, j + 1, w, n, c->part, dres);
+      launch_maxpy<T>(st, V, n, j + 1, dres, -1.0, w, n, c->part, nullptr);
+      launch_mdot<T>(st, V, n, j + 1, w, n, c->part, dres + MAXC);
+      launch_maxpy<T>(st, V, n, j + 1, dres + MAXC, -1.0, w, n, c->part, dres + 2 * MAXC);
+      fetch(c, dres, 2 * MAXC + 1);
+      const double* hb = c->hbuf;
+      for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i] + hb[MAXC + i];
+      const double hn = hb[2 * MAXC];
+      H[(j + 1) * m + j] = hn;
+      if (hn > 0.0) launch_scale_inv<T>(st, dres + 2 * MAXC, w, w, n);
+      for (int i = 0; i < j; ++i) {
+        const double a = H[i * m + j], bb = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * bb;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+      }
+      const double a = H[j * m + j], bb = H[(j + 1) * m + j];
+      const double r = std::hypot(a, bb);
+      cs[j] = r > 0 ? a / r : 1.0;
+      sn[j] = r > 0 ? bb / r : 0.0;
+      H[j * m + j] = r;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      jend = j + 1;
+      const double res = std::fabs(g[j + 1]) / bnorm;
+      *relres = res;
+      if (!std::isfinite(res)) return -1;
+      if (res <= rtol || total >= maxit || hn == 0.0) {
+        done = true;
+        break;
+      }
+    }
+    for (int i = jend - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int k = i + 1; k < jend; ++k) s -= H[i * m + k] * y[k];
+      y[i] = s / H[i * m + i];
+    }
+    std::memcpy(c->hbuf, y.data(), sizeof(double) * jend);
+    ck(hipMemcpyAsync(dres + 3 * MAXC, c->hbuf, sizeof(double) * jend, hipMemcpyHostToDevice, st));
+    launch_maxpy<T>(st, Z, n, jend, dres + 3 * MAXC, 1.0, x, n, c->part, nullptr);
+    if (done) break;
+    // restart from the true residual
+    apply_op<T>(c, tr, x, V, rows);
+    launch_rsub<T>(st, b, V, n);
+    launch_norm<T>(st, V, n, c->part, dres);
+    fetch(c, dres, 1);
+    beta = c->hbuf[0];
+    *relres = beta / bnorm;
+    if (beta / bnorm <= rtol) break;
+    launch_scale_inv<T>(st, dres, V, V, n);
+  }
+  sync(c);
+  return total;
+}
+
+// Linear solve Op x = b with a float64 right-hand side and solution, in the working
+// precision, on the row-equilibrated system (D Op) x = D b.
+int linear_solve(nc_ctx* c, bool tr, const double* b, double* x, double rtol, double* relres) {
+  hipStream_t st = c->stream;
+  const int maxit = c->p.krylov_maxit;
+  if (c->mixed) {
+    launch_scale5<float>(st, c->N, b, (float*)c->kb, c->rows64);
+    const int its = fgmres<float>(c, tr, (const float*)c->kb, (float*)c->kx, rtol, maxit, relres);
+    launch_convert<float, double>(st, (const float*)c->kx, x, c->n5, 1.0);
+    return its;
+  }
+  launch_scale5<double>(st, c->N, b, (double*)c->kb, c->rows64);
+  return fgmres<double>(c, tr, (const double*)c->kb, x, rtol, maxit, relres);
+}
+
+// Per-field error estimate of an approximate solution: e = P^-1 r (one preconditioner
+// application), returns max_f |e_f| / |x_f| over the fields with |x_f| > 0.
+double error_estimate(nc_ctx* c, bool tr, const double* r, const double* x) {
+  hipStream_t st = c->stream;
+  if (c->mixed) {
+    launch_convert<double, float>(st, r, (float*)c->kb, c->n5, 1.0);
+    precondition<float>(c, tr, (const float*)c->kb, (float*)c->kx, nullptr);
+    launch_convert<float, double>(st, (const float*)c->kx, c->tmp5, c->n5, 1.0);
+  } else {
+    precondition<double>(c, tr, r, c->tmp5, nullptr);
+  }
+  launch_field_norms(st, c->tmp5, x, c->N, c->part, c->dres);
+  fetch(c, c->dres, 10);
+  double worst = 0.0;
+  for (int f = 0; f < 5; ++f)
+    if (c->hbuf[5 + f] > 0) worst = std::max(worst, c->hbuf[f] / c->hbuf[5 + f]);
+  return worst;
+}
+
+double norm64(nc_ctx* c, const double* a) {
+  launch_norm<double>(c->stream, a, c->n5, c->part, c->dres);
+  fetch(c, c->dres, 1);
+  return c->hbuf[0];
+}
+
+// ------------------------------------------------------------------ Newton
+int newton(nc_ctx* c, double* s, nc_info* info) {
+  hipStream_t st = c->stream;
+  const nc_problem& p = c->p;
+  const Level& L0 = c->lev[0];
+  launch_mask_state(st, L0.g, s);
+  compute_row_scales(c);
+  launch_residual(st, L0.g, L0.c64, c->patch, L0.coef64, s, c->R);
+  double rn = norm64(c, c->R);
+  if (!std::isfinite(rn)) return NC_ENAN;
+  const double rref = rn;
+  const double lin_rtol = c->mixed ? std::max(p.krylov_rtol, 5e-6) : p.krylov_rtol;
+  int status = NC_NOT_CONVERGED;
+  int kits = 0, it = 0;
+  double relres = 0.0;
+  for (it = 0; it < p.newton_maxit; ++it) {
+    if (rn == 0.0) { status = NC_OK; break; }
+    linearize(c, s, true);
+    const int its = linear_solve(c, false, c->R, c->d, lin_rtol, &relres);
+    if (its < 0) return NC_ENAN;
+    kits += its;
+    // d solves J d = R; the Newton step is -d
+    double lam = 1.0, rt = 0.0;
+    while (true) {
+      launch_axpy(st, -lam, c->d, s, c->strial, c->n5);
+      launch_residual(st, L0.g, L0.c64, c->patch, L0.coef64, c->strial, c->tmp5);
+      rt = norm64(c, c->tmp5);
+      if (!std::isfinite(rt)) return NC_ENAN;
+      if (rt <= rn || rt <= 1e-13 * rref || lam < 1.0 / 64) break;
+      lam *= 0.5;
+    }
+    ck(hipMemcpyAsync(s, c->strial, sizeof(double) * c->n5, hipMemcpyDeviceToDevice, st));
+    std::swap(c->R, c->tmp5);
+    rn = rt;
+    launch_field_norms(st, c->d, s, c->N, c->part, c->dres);
+    fetch(c, c->dres, 10);
+    double step = 0.0;
+    for (int f = 0; f < 5; ++f) {
+      const double sf = c->hbuf[5 + f];
+      const double df = lam * c->hbuf[f];
+      step = std::max(step, sf > 0 ? df / sf : (df > 0 ? 1.0 : 0.0));
+    }
+    if (lam == 1.0 && step <= p.newton_step_rtol) {
+      status = NC_OK;
+      ++it;
+      break;
+    }
+  }
+  if (info) {
+    info->newton_its = it;
+    info->krylov_its = kits;
+    info->refine_its = 0;
+    info->levels = c->L;
+    info->rel_res = relres;
+    launch_field_norms(st, c->R, nullptr, c->N, c->part, c->dres);
+    fetch(c, c->dres, 5);
+    for (int f = 0; f < 5; ++f) info->res[f] = c->hbuf[f];
+  }
+  return status;
+}
+
+// ------------------------------------------------------------------ adjoint
+int adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info* info) {
+  hipStream_t st = c->stream;
+  const nc_problem& p = c->p;
+  const Level& L0 = c->lev[0];
+  linearize(c, s, true);
+  compute_row_scales(c);
+  ck(hipMemcpyAsync(c->ra, rhs, sizeof(double) * c->n5, hipMemcpyDeviceToDevice, st));
+  launch_mask_state(st, L0.g, c->ra);
+  const double bn = norm64(c, c->ra);
+  if (!std::isfinite(bn)) return NC_ENAN;
+  ck(hipMemsetAsync(lam, 0, sizeof(double) * c->n5, st));
+  if (bn == 0.0) return NC_OK;
+  const double lin_rtol = c->mixed ? std::max(p.krylov_rtol, 5e-6) : std::min(p.krylov_rtol, p.adjoint_rtol);
+  int kits = 0, ref = 0, status = NC_NOT_CONVERGED;
+  double relres = 0.0, rel = 1.0;
+  // r = rhs - J^T lam, refined in float64 until the relative residual meets adjoint_rtol
+  ck(hipMemcpyAsync(c->R, c->ra, sizeof(double) * c->n5, hipMemcpyDeviceToDevice, st));
+  for (ref = 0; ref < 20; ++ref) {
+    const int its = linear_solve(c, true, c->R, c->d, lin_rtol, &relres);
+    if (its < 0) return NC_ENAN;
+    kits += its;
+    launch_axpy(st, 1.0, c->d, lam, lam, c->n5);
+    launch_jtw5<double>(st, view<double>(c, 0), lam, c->tmp5);
+    launch_axpy(st, -1.0, c->tmp5, c->ra, c->R, c->n5);
+    rel = norm64(c, c->R) / bn;
+    if (!std::isfinite(rel)) return NC_ENAN;
+    // converged when the residual is small and one preconditioner application predicts a
+    // per-field relative error below the same tolerance (the pressure block is much
+    // smaller in norm than the temperature block, so the residual alone can mislead)
+    if (rel <= p.adjoint_rtol && error_estimate(c, true, c->R, lam) <= 1e2 * p.adjoint_rtol) {
+      status = NC_OK;
+      ++ref;
+      break;
+    }
+  }
+  if (info) {
+    info->newton_its = 0;
+    info->krylov_its = kits;
+    info->refine_its = ref;
+    info->levels = c->L;
+    info->rel_res = rel;
+    launch_field_norms(st, c->R, nullptr, c->N, c->part, c->dres);
+    fetch(c, c->dres, 5);
+    for (int f = 0; f < 5; ++f) info->res[f] = c->hbuf[f];
+  }
+  return status;
+}
+
+template <class F>
+int guarded(F f) {
+  try {
+    return f();
+  } catch (const HipError& e) {
+    std::fprintf(stderr, "nc: HIP error %d (%s)\n", (int)e.e, hipGetErrorString(e.e));
+    return NC_EHIP;
+  } catch (const std::bad_alloc&) {
+    return NC_ENOMEM;
+  } catch (...) {
+    return NC_EINVAL;
+  }
+}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+void nc_problem_default(nc_problem* p, int nx, int ny, int nz) {
+  std::memset(p, 0, sizeof(*p));
+  p->nx = nx; p->ny = ny; p->nz = nz;
+  p->h = 1.0 / nx;
+  p->rho0 = p->mu = p->cp = p->g0 = 1.0;
+  p->alpha = 1e3;
+  p->k_f = 1.0; p->k_s = 100.0;
+  p->kappa_f = 0.00513; p->kappa_s = 1e-4;
+  p->q_c = 8.0; p->q_p = 8.0;
+  p->q_h = 1.0;
+  p->patch_x0 = 0.375; p->patch_x1 = 0.625; p->patch_y0 = 0.125; p->patch_y1 = 0.375;
+  p->Q = 0.0;
+  p->filter_radius = 0.0;
+  p->precision = NC_FP64;
+  p->levels = 0;
+  p->newton_step_rtol = 1e-12;
+  p->krylov_rtol = 1e-9;
+  p->adjoint_rtol = 1e-12;
+  p->newton_maxit = 30;
+  p->krylov_restart = 24;
+  p->krylov_maxit = 400;
+  p->smooth_pre = 2;
+  p->smooth_post = 2;
+  p->smooth_omega = 0.7;
+}
+
+size_t nc_workspace_bytes(const nc_problem* p) {
+  if (!valid_problem(p)) return 0;
+  nc_ctx tmp;
+  tmp.p = *p;
+  return carve(&tmp, nullptr);
+}
+
+int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stream, nc_ctx** out) {
+  if (!out || !valid_problem(p) || !workspace_dev) return NC_EINVAL;
+  *out = nullptr;
+  return guarded([&]() {
+    nc_ctx* c = new nc_ctx();
+    c->p = *p;
+    if (c->p.h <= 0) c->p.h = 1.0 / p->nx;
+    const size_t need = carve(c, nullptr);
+    if (bytes < need) {
+      delete c;
+      return NC_ENOMEM;
+    }
+    char* base = (char*)workspace_dev;
+    const size_t mis = (size_t)((uintptr_t)base % ALIGN);
+    if (mis) base += ALIGN - mis;
+    carve(c, base);
+    c->stream = (hipStream_t)stream;
+    c->patch = Patch{c->p.q_h, c->p.patch_x0, c->p.patch_x1, c->p.patch_y0, c->p.patch_y1, c->p.h};
+    c->design_set = false;
+    if (hipHostMalloc((void**)&c->hbuf, sizeof(double) * 4 * MAXC, hipHostMallocDefault) != hipSuccess) {
+      delete c;
+      return NC_EHIP;
+    }
+    *out = c;
+    return NC_OK;
+  });
+}
+
+int nc_destroy(nc_ctx* c) {
+  if (!c) return NC_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipHostFree(c->hbuf);
+  delete c;
+  return NC_OK;
+}
+
+const char* nc_status_string(int s) {
+  switch (s) {
+    case NC_OK: return "ok";
+    case NC_NOT_CONVERGED: return "not converged";
+    case NC_EINVAL: return "invalid argument";
+    case NC_ENOMEM: return "workspace too small";
+    case NC_EHIP: return "HIP runtime error";
+    case NC_ENAN: return "non-finite value encountered";
+    default: return "unknown status";
+  }
+}
+
+int nc_set_design(nc_ctx* c, const double* x) {
+  if (!c || !x) return NC_EINVAL;
+  return guarded([&]() {
+    hipStream_t st = c->stream;
+    const nc_problem& p = c->p;
+    Level& L0 = c->lev[0];
+    launch_cone_filter(st, L0.g, p.filter_radius, x, c->gamma, false, c->ftmp);
+    launch_ramp(st, c->E, c->gamma, p.k_f, p.k_s, p.q_c, p.kappa_f, p.kappa_s, p.q_p, L0.coef64, L0.coef32, c->dk,
+                c->dkap);
+    for (int l = 1; l < c->L; ++l) {
+      launch_average_coef<double>(st, c->lev[l - 1].g, c->lev[l].g, c->lev[l - 1].coef64, c->lev[l].coef64);
+      launch_average_coef<float>(st, c->lev[l - 1].g, c->lev[l].g, c->lev[l - 1].coef32, c->lev[l].coef32);
+    }
+    ck(hipGetLastError());
+    c->design_set = true;
+    return NC_OK;
+  });
+}
+
+int nc_get_gamma(nc_ctx* c, double* gamma) {
+  if (!c || !gamma || !c->design_set) return NC_EINVAL;
+  return guarded([&]() {
+    ck(hipMemcpyAsync(gamma, c->gamma, sizeof(double) * c->E, hipMemcpyDeviceToDevice, c->stream));
+    return NC_OK;
+  });
+}
+
+int nc_residual(nc_ctx* c, const double* s, double* r) {
+  if (!c || !s || !r || !c->design_set) return NC_EINVAL;
+  return guarded([&]() {
+    const Level& L0 = c->lev[0];
+    launch_residual(c->stream, L0.g, L0.c64, c->patch, L0.coef64, s, r);
+    ck(hipGetLastError());
+    return NC_OK;
+  });
+}
+
+int nc_linearize(nc_ctx* c, const double* s) {
+  if (!c || !s || !c->design_set) return NC_EINVAL;
+  return guarded([&]() {
+    linearize(c, s, false);
+    ck(hipGetLastError());
+    return NC_OK;
+  });
+}
+
+int nc_jac_apply(nc_ctx* c, const double* v, double* y) {
+  if (!c || !v || !y) return NC_EINVAL;
+  return guarded([&]() { launch_jv5<double>(c->stream, view<double>(c, 0), v, y); ck(hipGetLastError()); return NC_OK; });
+}
+int nc_jacT_apply(nc_ctx* c, const double* w, double* y) {
+  if (!c || !w || !y) return NC_EINVAL;
+  return guarded([&]() { launch_jtw5<double>(c->stream, view<double>(c, 0), w, y); ck(hipGetLastError()); return NC_OK; });
+}
+int nc_jac_apply_f32(nc_ctx* c, const float* v, float* y) {
+  if (!c || !v || !y) return NC_EINVAL;
+  return guarded([&]() { launch_jv5<float>(c->stream, view<float>(c, 0), v, y); ck(hipGetLastError()); return NC_OK; });
+}
+int nc_jacT_apply_f32(nc_ctx* c, const float* w, float* y) {
+  if (!c || !w || !y) return NC_EINVAL;
+  return guarded([&]() { launch_jtw5<float>(c->stream, view<float>(c, 0), w, y); ck(hipGetLastError()); return NC_OK; });
+}
+
+int nc_solve_state(nc_ctx* c, double* s, nc_info* info) {
+  if (!c || !s || !c->design_set) return NC_EINVAL;
+  return guarded([&]() {
+    const double t0 = now();
+    const int r = newton(c, s, info);
+    sync(c);
+    if (info) info->t_total = now() - t0;
+    return r;
+  });
+}
+
+int nc_objective(nc_ctx* c, const double* s, double* f) {
+  if (!c || !s || !f) return NC_EINVAL;
+  return guarded([&]() {
+    launch_objective(c->stream, c->lev[0].g, c->patch, s, c->part, c->dres);
+    fetch(c, c->dres, 1);
+    *f = c->hbuf[0];
+    return NC_OK;
+  });
+}
+
+int nc_objective_grad(nc_ctx* c, double* g) {
+  if (!c || !g) return NC_EINVAL;
+  return guarded([&]() { launch_objective_grad(c->stream, c->lev[0].g, c->patch, g); ck(hipGetLastError()); return NC_OK; });
+}
+
+int nc_solve_adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info* info) {
+  if (!c || !s || !rhs || !lam || !c->design_set) return NC_EINVAL;
+  return guarded([&]() {
+    const double t0 = now();
+    const int r = adjoint(c, s, rhs, lam, info);
+    sync(c);
+    if (info) info->t_total = now() - t0;
+    return r;
+  });
+}
+
+int nc_sensitivity(nc_ctx* c, const double* s, const double* lam, double* dfdx, double* dfdgamma) {
+  if (!c || !s || !lam || !dfdx || !c->design_set) return NC_EINVAL;
+  return guarded([&]() {
+    hipStream_t st = c->stream;
+    const Level& L0 = c->lev[0];
+    double* g = dfdgamma ? dfdgamma : c->sens;
+    launch_sensitivity(st, L0.g, L0.c64, L0.coef64, c->dk, c->dkap, s, lam, g);
+    launch_cone_filter(st, L0.g, c->p.filter_radius, g, dfdx, true, c->ftmp);
+    ck(hipGetLastError());
+    return NC_OK;
+  });
+}
+
+int nc_cone_filter(int nx, int ny, int nz, double radius, const double* x, double* y, int transpose, void* stream) {
+  if (nx < 1 || ny < 1 || nz < 1 || !x || !y) return NC_EINVAL;
+  if (transpose && radius > 0) return NC_EINVAL;   // the transpose needs a temporary; use a context
+  return guarded([&]() {
+    launch_cone_filter((hipStream_t)stream, Grid{nx, ny, nz}, radius, x, y, false, nullptr);
+    ck(hipGetLastError());
+    return NC_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,259 @@
+"""ctypes binding of include/nc.h (argument marshalling only).
+
+Every computation runs in the HIP library libnc.so; PyTorch supplies device memory
+(the workspace and the caller's arrays) and the HIP stream.  Importing this module
+does not need a GPU, but creating a Solver does, and a missing library raises.
+"""
+
+import ctypes
+import os
+
+import torch
+
+from .build import lib_path
+
+NC_OK, NC_NOT_CONVERGED = 0, 1
+NC_EINVAL, NC_ENOMEM, NC_EHIP, NC_ENAN = -1, -2, -3, -4
+NC_FP64, NC_MIXED = 0, 1
+
+EXPORTED = [
+    "nc_problem_default", "nc_workspace_bytes", "nc_create", "nc_destroy", "nc_status_string",
+    "nc_set_design", "nc_get_gamma", "nc_residual", "nc_linearize", "nc_jac_apply", "nc_jacT_apply",
+    "nc_jac_apply_f32", "nc_jacT_apply_f32", "nc_solve_state", "nc_objective", "nc_objective_grad",
+    "nc_solve_adjoint", "nc_sensitivity", "nc_cone_filter",
+]
+
+
+class NCProblem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("h", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("mu", ctypes.c_double), ("cp", ctypes.c_double), ("g0", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("k_f", ctypes.c_double), ("k_s", ctypes.c_double),
+        ("kappa_f", ctypes.c_double), ("kappa_s", ctypes.c_double),
+        ("q_c", ctypes.c_double), ("q_p", ctypes.c_double),
+        ("q_h", ctypes.c_double),
+        ("patch_x0", ctypes.c_double), ("patch_x1", ctypes.c_double),
+        ("patch_y0", ctypes.c_double), ("patch_y1", ctypes.c_double),
+        ("Q", ctypes.c_double),
+        ("filter_radius", ctypes.c_double),
+        ("precision", ctypes.c_int), ("levels", ctypes.c_int),
+        ("newton_step_rtol", ctypes.c_double), ("krylov_rtol", ctypes.c_double), ("adjoint_rtol", ctypes.c_double),
+        ("newton_maxit", ctypes.c_int), ("krylov_restart", ctypes.c_int), ("krylov_maxit", ctypes.c_int),
+        ("smooth_pre", ctypes.c_int), ("smooth_post", ctypes.c_int),
+        ("smooth_omega", ctypes.c_double),
+    ]
+
+
+class NCInfo(ctypes.Structure):
+    _fields_ = [
+        ("newton_its", ctypes.c_int), ("krylov_its", ctypes.c_int), ("refine_its", ctypes.c_int),
+        ("levels", ctypes.c_int),
+        ("res", ctypes.c_double * 5), ("rel_res", ctypes.c_double), ("t_total", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {"newton_its": self.newton_its, "krylov_its": self.krylov_its, "refine_its": self.refine_its,
+                "levels": self.levels, "res": list(self.res), "rel_res": self.rel_res, "t_total": self.t_total}
+
+
+_LIB = None
+
+
+def load():
+    """Load libnc.so from the package's lib/ directory (raises if it was not built)."""
+    global _LIB
+    if _LIB is None:
+        path = lib_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"HIP library not built: {path} missing (run paper_1904_00182_amd/build.py)")
+        lib = ctypes.CDLL(path)
+        P, I, D, V, S = ctypes.POINTER(NCProblem), ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+        sig = {
+            "nc_problem_default": (None, [P, I, I, I]),
+            "nc_workspace_bytes": (S, [P]),
+            "nc_create": (I, [P, V, S, V, ctypes.POINTER(V)]),
+            "nc_destroy": (I, [V]),
+            "nc_status_string": (ctypes.c_char_p, [I]),
+            "nc_set_design": (I, [V, V]),
+            "nc_get_gamma": (I, [V, V]),
+            "nc_residual": (I, [V, V, V]),
+            "nc_linearize": (I, [V, V]),
+            "nc_jac_apply": (I, [V, V, V]),
+            "nc_jacT_apply": (I, [V, V, V]),
+            "nc_jac_apply_f32": (I, [V, V, V]),
+            "nc_jacT_apply_f32": (I, [V, V, V]),
+            "nc_solve_state": (I, [V, V, ctypes.POINTER(NCInfo)]),
+            "nc_objective": (I, [V, V, ctypes.POINTER(D)]),
+            "nc_objective_grad": (I, [V, V]),
+            "nc_solve_adjoint": (I, [V, V, V, V, ctypes.POINTER(NCInfo)]),
+            "nc_sensitivity": (I, [V, V, V, V, V]),
+            "nc_cone_filter": (I, [I, I, I, D, V, V, I, V]),
+        }
+        for name, (res, argt) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = argt
+        _LIB = lib
+    return _LIB
+
+
+def default_problem(nx, ny, nz, **overrides):
+    p = NCProblem()
+    load().nc_problem_default(ctypes.byref(p), nx, ny, nz)
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def workspace_bytes(problem):
+    return int(load().nc_workspace_bytes(ctypes.byref(problem)))
+
+
+class NCError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {load().nc_status_string(status).decode()} ({status})")
+
+
+def _check(status, what, allow_not_converged=False):
+    if status == NC_OK or (allow_not_converged and status == NC_NOT_CONVERGED):
+        return status
+    raise NCError(status, what)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    return ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+
+
+class Solver:
+    """One solver context: a caller-owned workspace tensor on `device` and one stream."""
+
+    def __init__(self, problem, device="cuda:0", stream=None):
+        self.lib = load()
+        self.p = problem
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.nbytes = workspace_bytes(problem)
+        if self.nbytes == 0:
+            raise NCError(NC_EINVAL, "nc_workspace_bytes")
+        self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.ctx = ctypes.c_void_p()
+        _check(self.lib.nc_create(ctypes.byref(problem), _ptr(self.workspace), self.nbytes + 256,
+                                  _stream_handle(self.stream), ctypes.byref(self.ctx)), "nc_create")
+        self.N = (problem.nx + 1) * (problem.ny + 1) * (problem.nz + 1)
+        self.E = problem.nx * problem.ny * problem.nz
+        self.last_info = None
+
+    def close(self):
+        if self.ctx:
+            self.lib.nc_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers
+    def _vec(self, dtype=torch.float64):
+        return torch.zeros((self.N, 5), dtype=dtype, device=self.device)
+
+    def _in(self, t, shape, dtype=torch.float64):
+        t = torch.as_tensor(t).to(device=self.device, dtype=dtype).contiguous()
+        if tuple(t.shape) != tuple(shape) and t.numel() != int(torch.tensor(shape).prod()):
+            raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+        return t.reshape(shape)
+
+    # -- C ABI, one method per entry point
+    def set_design(self, x):
+        self._x = self._in(x, (self.E,))
+        _check(self.lib.nc_set_design(self.ctx, _ptr(self._x)), "nc_set_design")
+
+    def gamma(self):
+        g = torch.empty(self.E, dtype=torch.float64, device=self.device)
+        _check(self.lib.nc_get_gamma(self.ctx, _ptr(g)), "nc_get_gamma")
+        return g
+
+    def residual(self, s):
+        s = self._in(s, (self.N, 5))
+        r = self._vec()
+        _check(self.lib.nc_residual(self.ctx, _ptr(s), _ptr(r)), "nc_residual")
+        return r
+
+    def linearize(self, s):
+        self._lin = self._in(s, (self.N, 5))
+        _check(self.lib.nc_linearize(self.ctx, _ptr(self._lin)), "nc_linearize")
+
+    def jac_apply(self, v, transpose=False):
+        dt = v.dtype if v.dtype in (torch.float32, torch.float64) else torch.float64
+        v = self._in(v, (self.N, 5), dt)
+        y = self._vec(dt)
+        if dt == torch.float64:
+            f = self.lib.nc_jacT_apply if transpose else self.lib.nc_jac_apply
+        else:
+            f = self.lib.nc_jacT_apply_f32 if transpose else self.lib.nc_jac_apply_f32
+        _check(f(self.ctx, _ptr(v), _ptr(y)), "nc_jac_apply")
+        return y
+
+    def solve_state(self, s0=None, out=None):
+        s = out if out is not None else self._vec()
+        if s0 is not None:
+            s.copy_(self._in(s0, (self.N, 5)))
+        elif out is None:
+            s.zero_()
+        info = NCInfo()
+        st = _check(self.lib.nc_solve_state(self.ctx, _ptr(s), ctypes.byref(info)), "nc_solve_state",
+                    allow_not_converged=True)
+        self.last_info = info.as_dict()
+        self.last_info["status"] = st
+        return s
+
+    def objective(self, s):
+        s = self._in(s, (self.N, 5))
+        f = ctypes.c_double()
+        _check(self.lib.nc_objective(self.ctx, _ptr(s), ctypes.byref(f)), "nc_objective")
+        return f.value
+
+    def objective_grad(self):
+        g = self._vec()
+        _check(self.lib.nc_objective_grad(self.ctx, _ptr(g)), "nc_objective_grad")
+        return g
+
+    def solve_adjoint(self, s, rhs, out=None):
+        s = self._in(s, (self.N, 5))
+        rhs = self._in(rhs, (self.N, 5))
+        lam = out if out is not None else self._vec()
+        info = NCInfo()
+        st = _check(self.lib.nc_solve_adjoint(self.ctx, _ptr(s), _ptr(rhs), _ptr(lam), ctypes.byref(info)),
+                    "nc_solve_adjoint", allow_not_converged=True)
+        self.last_info = info.as_dict()
+        self.last_info["status"] = st
+        return lam
+
+    def sensitivity(self, s, lam, with_gamma=False):
+        s = self._in(s, (self.N, 5))
+        lam = self._in(lam, (self.N, 5))
+        dfdx = torch.empty(self.E, dtype=torch.float64, device=self.device)
+        dfdg = torch.empty(self.E, dtype=torch.float64, device=self.device) if with_gamma else None
+        _check(self.lib.nc_sensitivity(self.ctx, _ptr(s), _ptr(lam), _ptr(dfdx),
+                                       _ptr(dfdg) if dfdg is not None else None), "nc_sensitivity")
+        return (dfdx, dfdg) if with_gamma else dfdx
+
+
+def cone_filter(x, nx, ny, nz, radius, stream=None):
+    """y = F_R x on an nx*ny*nz element grid (device tensors), via nc_cone_filter."""
+    x = x.contiguous().to(torch.float64)
+    y = torch.empty_like(x)
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    _check(load().nc_cone_filter(nx, ny, nz, float(radius), _ptr(x), _ptr(y), 0, _stream_handle(st)),
+           "nc_cone_filter")
+    return y

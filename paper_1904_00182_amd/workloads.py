@@ -1,0 +1,54 @@
+"""Workload definitions: the unit-constant cavity (Sec. 3, Sec. 6.1) at the grid sizes,
+Grashof numbers and design recipes of the benchmark configurations, on the GPU path.
+
+Designs are built from the seeded noise of `inputs` with the library's own cone
+filter (nc_cone_filter) and, where a 0/1 design is wanted, a threshold at 0.5 taken
+in float64 (ties go to solid).
+"""
+
+import torch
+
+from . import inputs
+from . import nc
+
+# permeability from Table tab:2 per Grashof number (alpha with unit constants)
+KAPPA_F = {1e3: 0.00513, 1e4: 0.00206, 1e5: 0.00085, 1e6: 0.00036}
+
+CONFIGS = {
+    # name: grid, Gr, precision, design recipe, in-chain filter radius, seed
+    "cavity16": dict(grid=(16, 8, 16), gr=1e3, precision=nc.NC_FP64, design="noise", radius=0.0, seed=0),
+    "cavity64": dict(grid=(64, 32, 64), gr=1e3, precision=nc.NC_FP64, design="blobs", radius=0.0, seed=1),
+    "cavity32": dict(grid=(32, 16, 32), gr=1e3, precision=nc.NC_FP64, design="blobs", radius=0.0, seed=1),
+    "cavity128mixed": dict(grid=(128, 64, 128), gr=1e4, precision=nc.NC_MIXED, design="blobs", radius=0.0, seed=2),
+    "cavity128": dict(grid=(128, 64, 128), gr=1e4, precision=nc.NC_FP64, design="blobs", radius=0.0, seed=2),
+    "cavity96filtered": dict(grid=(96, 48, 96), gr=1e3, precision=nc.NC_FP64, design="noise", radius=1.5, seed=3),
+    "cavity24filtered": dict(grid=(24, 12, 24), gr=1e3, precision=nc.NC_FP64, design="noise", radius=1.5, seed=3),
+}
+
+
+def problem(grid, gr=1e3, precision=nc.NC_FP64, radius=0.0, q_h=1.0, **over):
+    nx, ny, nz = grid
+    return nc.default_problem(nx, ny, nz, alpha=float(gr), kappa_f=KAPPA_F[float(gr)], precision=precision,
+                              filter_radius=float(radius), q_h=float(q_h), **over)
+
+
+def design(grid, recipe, seed, device="cuda:0"):
+    """Raw design x for the solver: 'noise' = 0.5 + 0.1 U(-1,1); 'blobs' = U(0,1) smoothed
+    by a radius-2 cone filter and thresholded at 0.5 (1 = solid)."""
+    nx, ny, nz = grid
+    E = nx * ny * nz
+    if recipe == "noise":
+        return torch.as_tensor(inputs.noise_design(E, seed), device=device)
+    if recipe == "blobs":
+        x0 = torch.as_tensor(inputs.uniform_design(E, seed), device=device)
+        y = nc.cone_filter(x0, nx, ny, nz, 2.0)
+        return (y >= 0.5).to(torch.float64)
+    raise ValueError(recipe)
+
+
+def config(name, device="cuda:0", **over):
+    c = dict(CONFIGS[name])
+    c.update(over)
+    p = problem(c["grid"], c["gr"], c["precision"], c["radius"])
+    x = design(c["grid"], c["design"], c["seed"], device)
+    return p, x, c

@@ -1,0 +1,59 @@
+"""The C-ABI library loads on the host and exports every entry point of include/nc.h
+(no device calls)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1904_00182_amd import build as nc_build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    if not os.path.exists(nc_build.lib_path()):
+        nc_build.build()
+    from paper_1904_00182_amd import nc
+    return nc, nc.load()
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "nc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nc_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    nc, lib = _lib()
+    declared = header_functions()
+    assert len(declared) >= 18
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(nc.EXPORTED) == declared
+
+
+def test_host_only_entry_points():
+    nc, lib = _lib()
+    p = nc.default_problem(16, 8, 16)
+    assert p.nx == 16 and p.k_s == 100.0 and p.kappa_f == 0.00513 and p.precision == nc.NC_FP64
+    b16 = nc.workspace_bytes(p)
+    assert b16 > 0
+    p64 = nc.default_problem(64, 32, 64)
+    assert nc.workspace_bytes(p64) > 50 * b16
+    pm = nc.default_problem(64, 32, 64, precision=nc.NC_MIXED)
+    assert nc.workspace_bytes(pm) < nc.workspace_bytes(p64)
+    bad = nc.default_problem(16, 8, 16, krylov_restart=0)
+    assert nc.workspace_bytes(bad) == 0
+    assert lib.nc_status_string(-2) == b"workspace too small"
+    assert lib.nc_create(ctypes.byref(p), None, 0, None, ctypes.byref(ctypes.c_void_p())) == nc.NC_EINVAL
+
+
+def test_ctypes_struct_matches_header_fields():
+    from paper_1904_00182_amd import nc
+    text = open(os.path.join(ROOT, "include", "nc.h")).read()
+    body = text[text.index("typedef struct nc_problem {"):text.index("} nc_problem;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\b([a-zA-Z_][a-zA-Z0-9_]*)\s*[,;]", body)
+    assert names == [f[0] for f in nc.NCProblem._fields_]
