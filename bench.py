@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-grid", default="20,10,20")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run one device copy of this many MiB (a kernel of known traffic for counter scaling)")
     return ap.parse_args()
 
 
@@ -129,6 +131,14 @@ def main():
     from paper_1904_00182_amd import nc, workloads
 
     dev = "cuda:0"
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb << 18          # float32 elements
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(args, f"copy calibration: {4 * n} bytes read, {4 * n} bytes written")
+        del a, b
     p, x, cfg = workloads.config(args.workload, dev)
     sol = nc.Solver(p, dev)
     N, E = sol.N, sol.E
@@ -162,6 +172,20 @@ def main():
     f_val = sol.objective(s)
     log(args, f"step {t_step * 1e3:.1f} ms  state {i_state}  adjoint {i_adj}  f={f_val:.6e}")
 
+    # the same steps again with HIP-event timing of every kernel class on the solver's
+    # stream: the per-launch durations of the dominant operator kernel inside the solve
+    sol.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_step_timed = (time.perf_counter() - t0) / args.steps
+    classes = sol.timing()
+    sol.set_timing(False)
+    log(args, "kernel classes (ms, launches) over the instrumented steps:",
+        {k: (round(v[0], 2), v[1]) for k, v in classes.items() if v[1]})
+
     # operator apply throughput and roofline of the dominant kernel (the float32 and
     # float64 five-field Jacobian applies), timed live with HIP events on the solver's stream
     sol.linearize(s)
@@ -176,8 +200,21 @@ def main():
     # linearisation state (P, T per node) and the two element coefficients (k, kappa)
     bytes_jv = (N * (5 + 5 + 2) + E * 2) * sz
     bytes_jv64 = (N * (5 + 5 + 2) + E * 2) * 8
-    ach = bytes_jv / t_jv / 1e9
     dofs = 5 * N
+    # dominant operator kernel of the solve.  Algorithmic bytes per launch, per node and
+    # element of the finest grid: five-field applies read v (5) and the (P, T) state (2)
+    # and write y (5); a finest-grid smoothing sweep reads x (2), b (2), the 2x2 block
+    # inverse (4) and the state (2) and writes x' (2); both read (k, kappa) per element.
+    ops = {"jv5": "zmarch_kernel<JvOp<{t},5,0>,33,17,1> (five-field J v)",
+           "jtw5": "zmarch_kernel<JtwOp<{t},5,0>,33,17,1> (five-field J^T w)",
+           "smooth": "zmarch_kernel<JvOp<{t},2,2>,33,17,1> (finest-grid block-Jacobi sweep, J)",
+           "smooth_T": "zmarch_kernel<JtwOp<{t},2,2>,33,17,1> (finest-grid block-Jacobi sweep, J^T)"}
+    dom = max(ops, key=lambda k: classes[k][0])
+    dom_ms, dom_n = classes[dom]
+    t_dom = dom_ms / max(dom_n, 1) * 1e-3
+    bytes_dom = (N * 12 + E * 2) * sz
+    ach = bytes_dom / t_dom / 1e9
+    share = dom_ms / max(1e-9, sum(v[0] for v in classes.values()))
     result = {
         "metric": "state+adjoint solve s at 1M elems",
         "value": round(t_step, 5),
@@ -203,17 +240,23 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": {
-            "kernel": f"zmarch_kernel<JvOp<{'float' if mixed else 'double'},5,0>> (five-field Jacobian apply)",
+            "kernel": ops[dom].format(t="float" if mixed else "double"),
             "bound": "hbm",
             "achieved": round(ach, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "launch_us": round(t_jv * 1e6, 2),
-            "bytes_per_launch": bytes_jv,
+            "launch_us": round(t_dom * 1e6, 2),
+            "launches": dom_n,
+            "bytes_per_launch": bytes_dom,
+            "share_of_kernel_time": round(share, 3),
+            "timed_step_ms": round(t_step_timed * 1e3, 3),
         },
+        "kernel_classes_ms": {k: round(v[0] / args.steps, 3) for k, v in classes.items() if v[1]},
         "operator": {
+            "jv_working_precision_us": round(t_jv * 1e6, 2),
+            "jv_working_precision_hbm_frac": round(bytes_jv / t_jv / 1e9 / HBM_PEAK_GBS, 4),
             "gdofs_jv_working_precision": round(dofs / t_jv / 1e9, 3),
             "gdofs_jv_f64": round(dofs / t_jv64 / 1e9, 3),
             "gdofs_jtw_f64": round(dofs / t_jtw64 / 1e9, 3),

@@ -147,6 +147,19 @@ int    nc_solve_adjoint(nc_ctx* ctx, const double* s_dev, const double* rhs_dev,
  * dfdx = F_R^T dfdgamma.  dfdx_dev [E] (required), dfdgamma_dev [E] (may be NULL). */
 int    nc_sensitivity(nc_ctx* ctx, const double* s_dev, const double* lam_dev, double* dfdx_dev, double* dfdgamma_dev);
 
+/* Optional per-context timing of the solver's kernels with HIP events on the context's
+ * stream (a tracing aid; adds one event pair per timed launch).  nc_set_timing(ctx, 1)
+ * creates the events (once) and zeroes the counters; 0 turns timing off.
+ * nc_get_timing synchronises, then fills ms[k] (summed milliseconds) and counts[k]
+ * (launches) for k < n over the kernel classes 0 residual, 1 five-field J v,
+ * 2 five-field J^T w, 3 smoothing sweep on the finest grid, 4 transposed sweep on the
+ * finest grid, 5 multigrid residual, 6 node-block diagonal, 7 velocity coupling,
+ * 8 grid transfers, 9 coarsest solve, 10 Krylov multi-dot, 11 Krylov multi-axpy,
+ * 12 other vector kernels, 13 preconditioner setup, 14 smoothing sweeps on coarser
+ * levels; returns the number of classes (15) or an error code. */
+int    nc_set_timing(nc_ctx* ctx, int enable);
+int    nc_get_timing(nc_ctx* ctx, double* ms, long* counts, int n);
+
 /* Stand-alone cone filter on an nx*ny*nz element grid (y = F_R x, or F_R^T x when
  * transpose != 0); used to build filtered designs.  Enqueued on stream. */
 int    nc_cone_filter(int nx, int ny, int nz, double radius, const double* x_dev, double* y_dev, int transpose, void* stream);

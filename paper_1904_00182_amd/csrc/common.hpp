@@ -15,8 +15,9 @@ struct Grid {
   int nx, ny, nz;
   __host__ __device__ long nodes() const { return (long)(nx + 1) * (ny + 1) * (nz + 1); }
   __host__ __device__ long elems() const { return (long)nx * ny * nz; }
-  __host__ __device__ long node(int i, int j, int k) const { return i + (long)(nx + 1) * (j + (long)(ny + 1) * k); }
-  __host__ __device__ long elem(int i, int j, int k) const { return i + (long)nx * (j + (long)ny * k); }
+  // 32-bit indices: grids are limited to fewer than 2^31 / 5 nodes (checked at context creation)
+  __host__ __device__ int node(int i, int j, int k) const { return i + (nx + 1) * (j + (ny + 1) * k); }
+  __host__ __device__ int elem(int i, int j, int k) const { return i + nx * (j + ny * k); }
   // Dirichlet sets of the cavity: T on the vertical walls and the top, P at (0, 0, nz).
   __host__ __device__ bool tfix(int i, int j, int k) const { return i == 0 || i == nx || j == 0 || j == ny || k == nz; }
   __host__ __device__ bool pfix(int i, int j, int k) const { return i == 0 && j == 0 && k == nz; }

@@ -255,7 +255,7 @@ NC_HD void elem_residual(const Lin<T>& L, const ElemConst<T>& c, T rP[8], T rT[8
   }
   project<T>(nullptr, FPx, FPy, FPz, c, c.W, rP);
   project<T>(L.conv, FTx, FTy, FTz, c, c.W, rT);
-  if (WITH_U) {
+  if constexpr (WITH_U) {
     project<T>(FPx, nullptr, nullptr, nullptr, c, c.W, rU[0]);
     project<T>(FPy, nullptr, nullptr, nullptr, c, c.W, rU[1]);
     project<T>(FPz, nullptr, nullptr, nullptr, c, c.W, rU[2]);
@@ -301,7 +301,7 @@ NC_HD void elem_jv(const Lin<T>& L, const T p[8], const T t[8], const ElemConst<
   }
   project<T>(nullptr, FPx, FPy, FPz, c, c.W, yP);
   project<T>(sT, FTx, FTy, FTz, c, c.W, yT);
-  if (WITH_U) {
+  if constexpr (WITH_U) {
     project<T>(FPx, nullptr, nullptr, nullptr, c, c.W, yU[0]);
     project<T>(FPy, nullptr, nullptr, nullptr, c, c.W, yU[1]);
     project<T>(FPz, nullptr, nullptr, nullptr, c, c.W, yU[2]);
@@ -324,7 +324,7 @@ NC_HD void elem_jtw(const Lin<T>& L, const T wP[8], const T wT[8], const T wU[3]
   grad_from_modal(mwt, c, gwtx, gwty, gwtz, gwtc);
   val_from_modal(mwt, wtq, wtc);
   T wuq[3][8];
-  if (WITH_U) {
+  if constexpr (WITH_U) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       T m[8], vc;
@@ -354,7 +354,7 @@ NC_HD void elem_jtw(const Lin<T>& L, const T wP[8], const T wT[8], const T wU[3]
     ub[0][q] = -W * gwpx[jx] + rb * L.gTx[jx];
     ub[1][q] = -W * gwpy[jy] + rb * L.gTy[jy];
     ub[2][q] = -W * gwpz[jz] + rb * L.gTz[jz];
-    if (WITH_U) {
+    if constexpr (WITH_U) {
       ub[0][q] -= W * wuq[0][q];
       ub[1][q] -= W * wuq[1][q];
       ub[2][q] -= W * wuq[2][q];
@@ -396,7 +396,7 @@ NC_HD T elem_sensitivity(const Lin<T>& L, const T lP[8], const T lT[8], const T 
   grad_from_modal(mlt, c, gltx, glty, gltz, gltc);
   val_from_modal(mlt, ltq, ltc);
   T luq[3][8];
-  if (WITH_U) {
+  if constexpr (WITH_U) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       T m[8], vc;
@@ -418,7 +418,7 @@ NC_HD T elem_sensitivity(const Lin<T>& L, const T lP[8], const T lT[8], const T 
     rk += gx * L.gTx[jx] + gy * L.gTy[jy] + gz * L.gTz[jz];
     const T uhx = L.uhx[jx], uhy = L.uhy[jy], uhz = L.uhz[q];
     T a = -(glpx[jx] * uhx + glpy[jy] * uhy + glpz[jz] * uhz);
-    if (WITH_U) a -= luq[0][q] * uhx + luq[1][q] * uhy + luq[2][q] * uhz;
+    if constexpr (WITH_U) a -= luq[0][q] * uhx + luq[1][q] * uhy + luq[2][q] * uhz;
     const T star = ltq[q] + L.tau * (L.u0[0] * gx + L.u0[1] * gy + L.u0[2] * gz);
     a += star * c.rcp * (uhx * L.gTx[jx] + uhy * L.gTy[jy] + uhz * L.gTz[jz]);
     a += (bx * gx + by * gy + bz * gz) * L.conv[q];
@@ -471,6 +471,433 @@ NC_HD void elem_uprojT(const T zu[3][8], T kap, const ElemConst<T>& c, T yP[8], 
   }
   project<T>(nullptr, Fx, Fy, Fz, c, (T)1, yP);
   project<T>(s, nullptr, nullptr, nullptr, c, (T)1, yT);
+}
+
+// ===================================================================================
+// Fast element operators in the modal basis.
+//
+// With the 2x2x2 Gauss rule on a cube the modal functions are orthogonal, which makes
+// the state-independent parts of the element operator nearly diagonal:
+//   sum_q grad phi_m . grad phi_n = K_m delta_mn,  K = (0, 8, 8, 8, 16/3, 16/3, 16/3, 8/3)
+//   sum_q d(phi_m)/dzeta phi_n    = B_mn with B_30 = 8, B_51 = B_62 = 8/3, B_74 = 8/9
+// so the pressure rows (Darcy stiffness and buoyancy) and the conduction part of the
+// energy rows cost a handful of multiplies per element.  The streamline-upwind term and
+// the derivative of the SUPG weight reduce to sums of the Hadamard transform of the
+// Gauss-point convection (12 multiply-adds each, see modal_grad_dot).  Only the
+// convective Gauss-point products remain per Gauss point.  The arithmetic is the same
+// discrete operator as the Gauss-point form above.
+// ===================================================================================
+
+template <typename T> struct MC {
+  static constexpr T K1 = (T)8, K4 = (T)(16.0 / 3.0), K7 = (T)(8.0 / 3.0);
+  static constexpr T B0 = (T)8, B1 = (T)(8.0 / 3.0), B4 = (T)(8.0 / 9.0);
+};
+
+// rho += v (x) F: contributions of sum_q grad N_a(q) . v f(q) to the modal coefficients
+// rho, where F = hadamard_fwd(f) (f given at the Gauss points), up to the factor dxi/8.
+template <typename T>
+NC_HD void modal_grad_dot(T vx, T vy, T vz, const T F[8], T rho[8]) {
+  const T g = GC<T>::g, g2 = GC<T>::g2;
+  rho[1] += vx * F[0];
+  rho[2] += vy * F[0];
+  rho[3] += vz * F[0];
+  rho[4] += g * (vx * F[2] + vy * F[1]);
+  rho[5] += g * (vx * F[3] + vz * F[1]);
+  rho[6] += g * (vy * F[3] + vz * F[2]);
+  rho[7] += g2 * (vx * F[6] + vy * F[5] + vz * F[4]);
+}
+
+// transpose of modal_grad_dot with respect to F
+template <typename T>
+NC_HD void modal_grad_dot_T_F(T vx, T vy, T vz, const T rb[8], T Fb[8]) {
+  const T g = GC<T>::g, g2 = GC<T>::g2;
+  Fb[0] += vx * rb[1] + vy * rb[2] + vz * rb[3];
+  Fb[1] += g * (vy * rb[4] + vz * rb[5]);
+  Fb[2] += g * (vx * rb[4] + vz * rb[6]);
+  Fb[3] += g * (vx * rb[5] + vy * rb[6]);
+  Fb[4] += g2 * vz * rb[7];
+  Fb[5] += g2 * vy * rb[7];
+  Fb[6] += g2 * vx * rb[7];
+}
+
+// transpose of modal_grad_dot with respect to v
+template <typename T>
+NC_HD void modal_grad_dot_T_v(const T F[8], const T rb[8], T& vx, T& vy, T& vz) {
+  const T g = GC<T>::g, g2 = GC<T>::g2;
+  vx = F[0] * rb[1] + g * (F[2] * rb[4] + F[3] * rb[5]) + g2 * F[6] * rb[7];
+  vy = F[0] * rb[2] + g * (F[1] * rb[4] + F[3] * rb[6]) + g2 * F[5] * rb[7];
+  vz = F[0] * rb[3] + g * (F[1] * rb[5] + F[2] * rb[6]) + g2 * F[4] * rb[7];
+}
+
+// transpose of bilinear4: (a, b, c, d) += sums of o weighted by 1, s_i, s_j, s_i s_j
+template <typename T>
+NC_HD void bilinear4_T(const T o[4], T& a, T& b, T& c, T& d) {
+  a += (o[0] + o[1]) + (o[2] + o[3]);
+  b += (o[1] + o[3]) - (o[0] + o[2]);
+  c += (o[2] + o[3]) - (o[0] + o[1]);
+  d += (o[0] + o[3]) - (o[1] + o[2]);
+}
+
+// Per-element linearisation data for the modal operators.
+template <typename T>
+struct LinM {
+  T ux[4], uy[4], uz[8];       // Darcy velocity at the Gauss points
+  T gTx[4], gTy[4], gTz[4];    // grad T at the Gauss points
+  T C[8];                      // hadamard_fwd of conv_q = rho0 c_p u_q . grad T_q - Q
+  T u0[3];                     // centroid velocity
+  T tau, dtau;                 // SUPG parameter and d tau / d (u0 . du0)
+  T k, cm;                     // conductivity and kappa / mu
+  T mP[8], mT[8];              // modal coefficients of P and T (8 x)
+};
+
+// Gauss-point velocity of a (pressure, temperature) pair given by modal coefficients:
+// u = -cm (grad p - beta t e_z); ux indexed by (qy, qz), uy by (qx, qz), uz by q.
+template <typename T>
+NC_HD void modal_velocity(const T mp[8], const T mt[8], T cm, const ElemConst<T>& c, T ux[4], T uy[4], T uz[8],
+                          T u0[3]) {
+  const T g = GC<T>::g, g2 = GC<T>::g2, g3 = GC<T>::g3;
+  const T fu = -cm * c.dxi * (T)0.125;
+  const T e1 = fu * mp[1], e2 = fu * mp[2], e3 = fu * mp[3];
+  const T e4 = fu * g * mp[4], e5 = fu * g * mp[5], e6 = fu * g * mp[6], e7 = fu * g2 * mp[7];
+  bilinear4(e1, e4, e5, e7, ux);
+  bilinear4(e2, e4, e6, e7, uy);
+  T uzp[4];
+  bilinear4(e3, e5, e6, e7, uzp);
+  const T ft = cm * c.beta * (T)0.125;
+  const T et[8] = {ft * mt[0], ft * g * mt[1], ft * g * mt[2], ft * g * mt[3],
+                   ft * g2 * mt[4], ft * g2 * mt[5], ft * g2 * mt[6], ft * g3 * mt[7]};
+  T tq[8];
+  hadamard_inv(et, tq);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) uz[q] = uzp[jz_of(q)] + tq[q];
+  u0[0] = e1;
+  u0[1] = e2;
+  u0[2] = e3 + et[0];
+}
+
+template <typename T>
+NC_HD void lin_modal(const T P[8], const T Tn[8], T k, T kap, const ElemConst<T>& c, LinM<T>& L) {
+  hadamard_fwd(P, L.mP);
+  hadamard_fwd(Tn, L.mT);
+  L.k = k;
+  L.cm = kap * c.inv_mu;
+  modal_velocity(L.mP, L.mT, L.cm, c, L.ux, L.uy, L.uz, L.u0);
+  T gc[3];
+  grad_from_modal(L.mT, c, L.gTx, L.gTy, L.gTz, gc);
+  T conv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int jx = jx_of(q), jy = jy_of(q), jz = jz_of(q);
+    conv[q] = c.rcp * (L.ux[jx] * L.gTx[jx] + L.uy[jy] * L.gTy[jy] + L.uz[q] * L.gTz[jz]) - c.Q;
+  }
+  hadamard_fwd(conv, L.C);
+  const T s = (T)4 * (L.u0[0] * L.u0[0] + L.u0[1] * L.u0[1] + L.u0[2] * L.u0[2]) * c.inv_he2 + c.tau3inv2;
+  const T tau = (T)1 / sqrt(s);
+  L.tau = tau;
+  L.dtau = (T)(-4) * tau * tau * tau * c.inv_he2;
+}
+
+// Pressure rows in modal form: rho_m = W cm [dxi^2/64 K_m mp_m - beta dxi/64 B mt]
+template <typename T>
+NC_HD void modal_prow(const T mp[8], const T mt[8], T cm, const ElemConst<T>& c, T rho[8]) {
+  const T a = cm * c.W * c.dxi * c.dxi * (T)(1.0 / 64.0);
+  const T b = cm * c.W * c.dxi * c.beta * (T)(1.0 / 64.0);
+  rho[0] = (T)0;
+  rho[1] = a * MC<T>::K1 * mp[1];
+  rho[2] = a * MC<T>::K1 * mp[2];
+  rho[3] = a * MC<T>::K1 * mp[3] - b * MC<T>::B0 * mt[0];
+  rho[4] = a * MC<T>::K4 * mp[4];
+  rho[5] = a * MC<T>::K4 * mp[5] - b * MC<T>::B1 * mt[1];
+  rho[6] = a * MC<T>::K4 * mp[6] - b * MC<T>::B1 * mt[2];
+  rho[7] = a * MC<T>::K7 * mp[7] - b * MC<T>::B4 * mt[4];
+}
+
+// Velocity rows: yU_a = -W sum_q N_a(q) u_q for u = (ux, uy, uzp[jz] + t-part), using
+// that ux depends on (qy, qz) only (the x-sum of N_a is one), and likewise uy, uzp.  The
+// temperature part of uz is projected in modal form (mass matrix diagonal).
+template <typename T>
+NC_HD void modal_urows(const T ux[4], const T uy[4], const T uzp[4], const T mt[8], T cmbeta, const ElemConst<T>& c,
+                       T yU[3][8]) {
+  const T g = GC<T>::g, g2 = GC<T>::g2, g4 = GC<T>::g2 * GC<T>::g2;
+  const T w4 = -c.W * (T)0.25;
+  T vx[4], vy[4], vz[4];
+  {
+    T a = 0, b = 0, cc = 0, d = 0;
+    bilinear4_T(ux, a, b, cc, d);
+    bilinear4(w4 * a, w4 * g * b, w4 * g * cc, w4 * g2 * d, vx);
+  }
+  {
+    T a = 0, b = 0, cc = 0, d = 0;
+    bilinear4_T(uy, a, b, cc, d);
+    bilinear4(w4 * a, w4 * g * b, w4 * g * cc, w4 * g2 * d, vy);
+  }
+  {
+    T a = 0, b = 0, cc = 0, d = 0;
+    bilinear4_T(uzp, a, b, cc, d);
+    bilinear4(w4 * a, w4 * g * b, w4 * g * cc, w4 * g2 * d, vz);
+  }
+  const T ft = -c.W * cmbeta * (T)0.125;
+  const T et[8] = {ft * mt[0], ft * g2 * mt[1], ft * g2 * mt[2], ft * g2 * mt[3],
+                   ft * g4 * mt[4], ft * g4 * mt[5], ft * g4 * mt[6], ft * g4 * g2 * mt[7]};
+  T tz[8];
+  hadamard_inv(et, tz);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ia = a & 1, ja = (a >> 1) & 1, ka = (a >> 2) & 1;
+    yU[0][a] += vx[ja + 2 * ka];
+    yU[1][a] += vy[ia + 2 * ka];
+    yU[2][a] += vz[ia + 2 * ja] + tz[a];
+  }
+}
+
+// Energy rows in modal form for a Gauss-point convection f with transform F: the
+// Galerkin and streamline parts plus conduction k K_m mt_m:
+//   rho_m = W/8 g^deg(m) F_m + W dxi/8 (tau u0) (x) F + W k dxi^2/64 K_m mt_m
+template <typename T>
+NC_HD void modal_trow(const T F[8], const T mt[8], const LinM<T>& L, const ElemConst<T>& c, T rho[8]) {
+  const T g = GC<T>::g, g2 = GC<T>::g2, g3 = GC<T>::g3;
+  const T w8 = c.W * (T)0.125;
+  const T kd = L.k * c.W * c.dxi * c.dxi * (T)(1.0 / 64.0);
+  rho[0] = w8 * F[0];
+  rho[1] = w8 * g * F[1] + kd * MC<T>::K1 * mt[1];
+  rho[2] = w8 * g * F[2] + kd * MC<T>::K1 * mt[2];
+  rho[3] = w8 * g * F[3] + kd * MC<T>::K1 * mt[3];
+  rho[4] = w8 * g2 * F[4] + kd * MC<T>::K4 * mt[4];
+  rho[5] = w8 * g2 * F[5] + kd * MC<T>::K4 * mt[5];
+  rho[6] = w8 * g2 * F[6] + kd * MC<T>::K4 * mt[6];
+  rho[7] = w8 * g3 * F[7] + kd * MC<T>::K7 * mt[7];
+  const T sd = w8 * c.dxi * L.tau;
+  modal_grad_dot(sd * L.u0[0], sd * L.u0[1], sd * L.u0[2], F, rho);
+}
+
+template <typename T, bool WITH_U>
+NC_HD void elem_residual_m(const LinM<T>& L, const ElemConst<T>& c, T rP[8], T rT[8], T rU[3][8]) {
+  T rho[8];
+  modal_prow(L.mP, L.mT, L.cm, c, rho);
+  T v[8];
+  hadamard_inv(rho, v);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) rP[a] += v[a];
+  modal_trow(L.C, L.mT, L, c, rho);
+  hadamard_inv(rho, v);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) rT[a] += v[a];
+  if constexpr (WITH_U) {
+    // split uz into its pressure part (bilinear in x, y) and temperature part
+    T uzp[4];
+    {
+      const T g = GC<T>::g, g2 = GC<T>::g2;
+      const T fu = -L.cm * c.dxi * (T)0.125;
+      bilinear4(fu * L.mP[3], fu * g * L.mP[5], fu * g * L.mP[6], fu * g2 * L.mP[7], uzp);
+    }
+    modal_urows(L.ux, L.uy, uzp, L.mT, L.cm * c.beta, c, rU);
+  }
+}
+
+// Exact Newton Jacobian times (p, t), modal form of elem_jv.
+template <typename T, bool WITH_U>
+NC_HD void elem_jv_m(const LinM<T>& L, const T p[8], const T t[8], const ElemConst<T>& c, T yP[8], T yT[8],
+                     T yU[3][8]) {
+  T mp[8], mt[8];
+  hadamard_fwd(p, mp);
+  hadamard_fwd(t, mt);
+  T rho[8], v[8];
+  modal_prow(mp, mt, L.cm, c, rho);
+  hadamard_inv(rho, v);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) yP[a] += v[a];
+  T dux[4], duy[4], duz[8], du0[3];
+  modal_velocity(mp, mt, L.cm, c, dux, duy, duz, du0);
+  T gtx[4], gty[4], gtz[4], gtc[3];
+  grad_from_modal(mt, c, gtx, gty, gtz, gtc);
+  const T dtau = L.dtau * (L.u0[0] * du0[0] + L.u0[1] * du0[1] + L.u0[2] * du0[2]);
+  T dconv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int jx = jx_of(q), jy = jy_of(q), jz = jz_of(q);
+    dconv[q] = c.rcp * (dux[jx] * L.gTx[jx] + duy[jy] * L.gTy[jy] + duz[q] * L.gTz[jz] + L.ux[jx] * gtx[jx] +
+                        L.uy[jy] * gty[jy] + L.uz[q] * gtz[jz]);
+  }
+  T S[8];
+  hadamard_fwd(dconv, S);
+  modal_trow(S, mt, L, c, rho);
+  const T sd = c.W * (T)0.125 * c.dxi;
+  modal_grad_dot(sd * (dtau * L.u0[0] + L.tau * du0[0]), sd * (dtau * L.u0[1] + L.tau * du0[1]),
+                 sd * (dtau * L.u0[2] + L.tau * du0[2]), L.C, rho);
+  hadamard_inv(rho, v);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) yT[a] += v[a];
+  if constexpr (WITH_U) {
+    T duzp[4];
+    const T g = GC<T>::g, g2 = GC<T>::g2;
+    const T fu = -L.cm * c.dxi * (T)0.125;
+    bilinear4(fu * mp[3], fu * g * mp[5], fu * g * mp[6], fu * g2 * mp[7], duzp);
+    modal_urows(dux, duy, duzp, mt, L.cm * c.beta, c, yU);
+  }
+}
+
+// Transpose of elem_jv_m: contributions of the row weights (wP, wT, wU) to the P and T
+// columns, obtained by running each step of elem_jv_m backwards.
+template <typename T, bool WITH_U>
+NC_HD void elem_jtw_m(const LinM<T>& L, const T wP[8], const T wT[8], const T wU[3][8], const ElemConst<T>& c,
+                      T yP[8], T yT[8]) {
+  const T g = GC<T>::g, g2 = GC<T>::g2, g3 = GC<T>::g3, g4 = GC<T>::g2 * GC<T>::g2;
+  const T cm = L.cm;
+  T rbP[8], rbT[8];
+  hadamard_fwd(wP, rbP);
+  hadamard_fwd(wT, rbT);
+  T mbp[8] = {0, 0, 0, 0, 0, 0, 0, 0}, mbt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // pressure rows
+  {
+    const T a = cm * c.W * c.dxi * c.dxi * (T)(1.0 / 64.0);
+    const T b = cm * c.W * c.dxi * c.beta * (T)(1.0 / 64.0);
+    mbp[1] += a * MC<T>::K1 * rbP[1];
+    mbp[2] += a * MC<T>::K1 * rbP[2];
+    mbp[3] += a * MC<T>::K1 * rbP[3];
+    mbp[4] += a * MC<T>::K4 * rbP[4];
+    mbp[5] += a * MC<T>::K4 * rbP[5];
+    mbp[6] += a * MC<T>::K4 * rbP[6];
+    mbp[7] += a * MC<T>::K7 * rbP[7];
+    mbt[0] -= b * MC<T>::B0 * rbP[3];
+    mbt[1] -= b * MC<T>::B1 * rbP[5];
+    mbt[2] -= b * MC<T>::B1 * rbP[6];
+    mbt[4] -= b * MC<T>::B4 * rbP[7];
+  }
+  // energy rows: rho = w8 g^deg S + kd K mt + sd tau u0 (x) S + sd A (x) C
+  const T w8 = c.W * (T)0.125;
+  const T kd = L.k * c.W * c.dxi * c.dxi * (T)(1.0 / 64.0);
+  T Sb[8] = {w8 * rbT[0], w8 * g * rbT[1], w8 * g * rbT[2], w8 * g * rbT[3],
+             w8 * g2 * rbT[4], w8 * g2 * rbT[5], w8 * g2 * rbT[6], w8 * g3 * rbT[7]};
+  mbt[1] += kd * MC<T>::K1 * rbT[1];
+  mbt[2] += kd * MC<T>::K1 * rbT[2];
+  mbt[3] += kd * MC<T>::K1 * rbT[3];
+  mbt[4] += kd * MC<T>::K4 * rbT[4];
+  mbt[5] += kd * MC<T>::K4 * rbT[5];
+  mbt[6] += kd * MC<T>::K4 * rbT[6];
+  mbt[7] += kd * MC<T>::K7 * rbT[7];
+  const T sd = w8 * c.dxi;
+  modal_grad_dot_T_F(sd * L.tau * L.u0[0], sd * L.tau * L.u0[1], sd * L.tau * L.u0[2], rbT, Sb);
+  T Ab[3];
+  modal_grad_dot_T_v(L.C, rbT, Ab[0], Ab[1], Ab[2]);
+  Ab[0] *= sd; Ab[1] *= sd; Ab[2] *= sd;
+  // A = dtau u0 + tau du0 with dtau = L.dtau (u0 . du0)
+  const T ua = L.u0[0] * Ab[0] + L.u0[1] * Ab[1] + L.u0[2] * Ab[2];
+  T du0b[3] = {L.tau * Ab[0] + L.dtau * ua * L.u0[0], L.tau * Ab[1] + L.dtau * ua * L.u0[1],
+               L.tau * Ab[2] + L.dtau * ua * L.u0[2]};
+  // S = hadamard_fwd(dconv)
+  T dcb[8];
+  hadamard_inv(Sb, dcb);
+  // dconv = rcp (du . gT + u . gt)
+  T duxb[4] = {0, 0, 0, 0}, duyb[4] = {0, 0, 0, 0}, duzb[8], gtxb[4] = {0, 0, 0, 0}, gtyb[4] = {0, 0, 0, 0},
+    gtzb[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int jx = jx_of(q), jy = jy_of(q), jz = jz_of(q);
+    const T r = c.rcp * dcb[q];
+    duxb[jx] += r * L.gTx[jx];
+    duyb[jy] += r * L.gTy[jy];
+    duzb[q] = r * L.gTz[jz];
+    gtxb[jx] += r * L.ux[jx];
+    gtyb[jy] += r * L.uy[jy];
+    gtzb[jz] += r * L.uz[q];
+  }
+  // velocity rows
+  T duzpb[4] = {0, 0, 0, 0};
+  if constexpr (WITH_U) {
+    const T w4 = -c.W * (T)0.25;
+    T ox[4], oy[4], oz[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ox[i] = wU[0][2 * i] + wU[0][2 * i + 1];                    // sum over ia at (ja, ka) = i
+      oy[i] = wU[1][(i & 1) + 4 * (i >> 1)] + wU[1][(i & 1) + 2 + 4 * (i >> 1)];   // sum over ja at (ia, ka)
+      oz[i] = wU[2][i] + wU[2][i + 4];                            // sum over ka at (ia, ja)
+    }
+    {
+      T a = 0, b = 0, cc = 0, d = 0;
+      bilinear4_T(ox, a, b, cc, d);
+      T tmp[4];
+      bilinear4(w4 * a, w4 * g * b, w4 * g * cc, w4 * g2 * d, tmp);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) duxb[j] += tmp[j];
+    }
+    {
+      T a = 0, b = 0, cc = 0, d = 0;
+      bilinear4_T(oy, a, b, cc, d);
+      T tmp[4];
+      bilinear4(w4 * a, w4 * g * b, w4 * g * cc, w4 * g2 * d, tmp);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) duyb[j] += tmp[j];
+    }
+    {
+      T a = 0, b = 0, cc = 0, d = 0;
+      bilinear4_T(oz, a, b, cc, d);
+      bilinear4(w4 * a, w4 * g * b, w4 * g * cc, w4 * g2 * d, duzpb);
+    }
+    T mwz[8];
+    hadamard_fwd(wU[2], mwz);
+    const T ft = -c.W * cm * c.beta * (T)0.125;
+    mbt[0] += ft * mwz[0];
+    mbt[1] += ft * g2 * mwz[1];
+    mbt[2] += ft * g2 * mwz[2];
+    mbt[3] += ft * g2 * mwz[3];
+    mbt[4] += ft * g4 * mwz[4];
+    mbt[5] += ft * g4 * mwz[5];
+    mbt[6] += ft * g4 * mwz[6];
+    mbt[7] += ft * g4 * g2 * mwz[7];
+  }
+  // uz = uzp[jz] + tq: tq from mt, uzp from mp
+#pragma unroll
+  for (int q = 0; q < 8; ++q) duzpb[jz_of(q)] += duzb[q];
+  {
+    const T ft = cm * c.beta * (T)0.125;
+    T Tq[8];
+    hadamard_fwd(duzb, Tq);
+    mbt[0] += ft * Tq[0] + ft * du0b[2];      // centroid du0z = e3 + ft mt0
+    mbt[1] += ft * g * Tq[1];
+    mbt[2] += ft * g * Tq[2];
+    mbt[3] += ft * g * Tq[3];
+    mbt[4] += ft * g2 * Tq[4];
+    mbt[5] += ft * g2 * Tq[5];
+    mbt[6] += ft * g2 * Tq[6];
+    mbt[7] += ft * g3 * Tq[7];
+  }
+  // ux = bilinear4(e1, e4, e5, e7), uy = bilinear4(e2, e4, e6, e7), uzp = bilinear4(e3, e5, e6, e7)
+  {
+    T e1 = du0b[0], e2 = du0b[1], e3 = du0b[2], e4 = 0, e5 = 0, e6 = 0, e7 = 0;
+    bilinear4_T(duxb, e1, e4, e5, e7);
+    bilinear4_T(duyb, e2, e4, e6, e7);
+    bilinear4_T(duzpb, e3, e5, e6, e7);
+    const T fu = -cm * c.dxi * (T)0.125;
+    mbp[1] += fu * e1;
+    mbp[2] += fu * e2;
+    mbp[3] += fu * e3;
+    mbp[4] += fu * g * e4;
+    mbp[5] += fu * g * e5;
+    mbp[6] += fu * g * e6;
+    mbp[7] += fu * g2 * e7;
+  }
+  // grad t = bilinear4 of (s mt1, s g mt4, s g mt5, s g2 mt7) etc.
+  {
+    T e1 = 0, e2 = 0, e3 = 0, e4 = 0, e5 = 0, e6 = 0, e7 = 0;
+    bilinear4_T(gtxb, e1, e4, e5, e7);
+    bilinear4_T(gtyb, e2, e4, e6, e7);
+    bilinear4_T(gtzb, e3, e5, e6, e7);
+    const T s = c.dxi * (T)0.125;
+    mbt[1] += s * e1;
+    mbt[2] += s * e2;
+    mbt[3] += s * e3;
+    mbt[4] += s * g * e4;
+    mbt[5] += s * g * e5;
+    mbt[6] += s * g * e6;
+    mbt[7] += s * g2 * e7;
+  }
+  T v[8];
+  hadamard_inv(mbp, v);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) yP[a] += v[a];
+  hadamard_inv(mbt, v);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) yT[a] += v[a];
 }
 
 // RAMP interpolation (Sec. 5.2, eqs. condRAMP and permRAMP) and derivatives.

@@ -3,18 +3,24 @@
 //
 // Work decomposition ("z-march").  A workgroup of TX x TY threads covers a tile of TX x
 // TY element columns and marches up in z through KZ + 1 element layers.  Thread (tx, ty)
-// computes element (I0 - 1 + tx, J0 - 1 + ty, k) of every layer in registers and owns
-// node column (I0 - 1 + tx, J0 - 1 + ty) for tx, ty >= 1 -- the lower-left node of its
-// own element.  Each node gathers the contributions of its four elements per layer
-// through LDS (the three neighbours' corners) and the contribution of the layer below
-// from a register accumulator, always in the same order, so results are bitwise
-// reproducible and no atomics are needed.  Elements on the tile's lower x / y edge and
-// the layer below the z chunk are recomputed by the neighbouring workgroup.
+// computes element (I0 - 1 + tx, J0 - 1 + ty, k) of every layer in registers (modal
+// element operators of element.hpp) and owns node column (I0 - 1 + tx, J0 - 1 + ty) for
+// tx, ty >= 1 -- the lower-left node of its own element.  Each node gathers the
+// contributions of its four elements per layer through LDS (the three neighbours'
+// corners) and the contribution of the layer below from a register accumulator, always
+// in the same order, so results are bitwise reproducible and no atomics are needed.
+// Elements on the tile's lower x / y edge and the layer below the z chunk are recomputed
+// by the neighbouring workgroup; the tile shape is chosen per grid to keep that halo and
+// idle lanes small.
+#include <cstdlib>
+
 #include "kernels.hpp"
 
 namespace nc {
 
-template <class Op, int TX, int TY>
+// FINE: 1 for launches on the finest grid, 0 on coarser multigrid levels (the same code;
+// separate instantiations keep the two apart in kernel traces).
+template <class Op, int TX, int TY, int FINE>
 __global__ __launch_bounds__(TX* TY) void zmarch_kernel(const Op op, const int KZ) {
   using T = typename Op::real;
   constexpr int NI = Op::NIN, NO = Op::NOUT, NT = TX * TY;
@@ -76,19 +82,55 @@ __global__ __launch_bounds__(TX* TY) void zmarch_kernel(const Op op, const int K
   }
 }
 
-constexpr int TILE_X = 16, TILE_Y = 16;
+// Tile shapes (threads in x, y); a tile owns (TX-1) x (TY-1) node columns.
+struct TileCfg {
+  int tx, ty;
+};
+constexpr int NTILES = 3;
+constexpr TileCfg TILES[NTILES] = {{16, 16}, {32, 8}, {8, 8}};
 
-template <class Op>
-static void run_zmarch(hipStream_t st, const Op& op) {
+// Fewest launched lanes over the grid's tiles; NC_TILE=<index> forces a shape.
+static int pick_tile(const Grid& g) {
+  static const int forced = [] {
+    const char* e = std::getenv("NC_TILE");
+    return e ? std::atoi(e) : -1;
+  }();
+  if (forced >= 0 && forced < NTILES) return forced;
+  long best = -1;
+  int bi = 0;
+  for (int c = 0; c < NTILES; ++c) {
+    const long lanes = (long)TILES[c].tx * TILES[c].ty;
+    const long cost = lanes * ceil_div(g.nx + 1, TILES[c].tx - 1) * ceil_div(g.ny + 1, TILES[c].ty - 1);
+    if (best < 0 || cost < best) { best = cost; bi = c; }
+  }
+  return bi;
+}
+
+template <class Op, int TX, int TY, int FINE>
+static void run_zmarch_t(hipStream_t st, const Op& op) {
   const Grid& g = op.g;
-  const int tiles_x = ceil_div(g.nx + 1, TILE_X - 1);
-  const int tiles_y = ceil_div(g.ny + 1, TILE_Y - 1);
-  // enough z chunks for ~4 workgroups per CU, but at least 4 planes per chunk
-  const int want = std::max(1, 1024 / std::max(1, tiles_x * tiles_y));
-  int KZ = std::max(4, ceil_div(g.nz + 1, want));
+  const int tiles_x = ceil_div(g.nx + 1, TX - 1);
+  const int tiles_y = ceil_div(g.ny + 1, TY - 1);
+  // z chunks: about `target` workgroups over the device (NC_ZBLOCKS overrides), at least
+  // 4 node planes per chunk
+  static const int target = [] {
+    const char* e = std::getenv("NC_ZBLOCKS");
+    return e ? std::max(1, std::atoi(e)) : 1024;
+  }();
+  const int want = std::max(1, target * 256 / (TX * TY) / std::max(1, tiles_x * tiles_y));
+  const int KZ = std::max(4, ceil_div(g.nz + 1, want));
   const int chunks = ceil_div(g.nz + 1, KZ);
-  dim3 grid(tiles_x, tiles_y, chunks), block(TILE_X, TILE_Y, 1);
-  hipLaunchKernelGGL((zmarch_kernel<Op, TILE_X, TILE_Y>), grid, block, 0, st, op, KZ);
+  dim3 grid(tiles_x, tiles_y, chunks), block(TX, TY, 1);
+  hipLaunchKernelGGL((zmarch_kernel<Op, TX, TY, FINE>), grid, block, 0, st, op, KZ);
+}
+
+template <class Op, int FINE = 1>
+static void run_zmarch(hipStream_t st, const Op& op) {
+  switch (pick_tile(op.g)) {
+    case 0: run_zmarch_t<Op, 16, 16, FINE>(st, op); break;
+    case 1: run_zmarch_t<Op, 32, 8, FINE>(st, op); break;
+    default: run_zmarch_t<Op, 8, 8, FINE>(st, op); break;
+  }
 }
 
 // ------------------------------------------------------------------ residual (float64)
@@ -111,10 +153,10 @@ struct ResidualOp {
 #pragma unroll
     for (int a = 0; a < 8; ++a) { P[a] = nd[a][0]; Tn[a] = nd[a][1]; }
     const long e = g.elem(i, j, k);
-    Lin<double> L;
-    linearize(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    LinM<double> L;
+    lin_modal(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
     double rP[8] = {0}, rT[8] = {0}, rU[3][8] = {{0}};
-    elem_residual<double, true>(L, c, rP, rT, rU);
+    elem_residual_m<double, true>(L, c, rP, rT, rU);
     if (k == 0 && patch.has(i, j)) {
       const double fl = patch.q_h * patch.h * patch.h * 0.25;
 #pragma unroll
@@ -174,13 +216,13 @@ struct JvOp {
 #pragma unroll
     for (int a = 0; a < 8; ++a) { P[a] = nd[a][0]; Tn[a] = nd[a][1]; p[a] = nd[a][2]; t[a] = nd[a][3]; }
     const long e = g.elem(i, j, k);
-    Lin<T> L;
-    linearize(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    LinM<T> L;
+    lin_modal(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
     T yP[8] = {0}, yT[8] = {0}, yU[3][8] = {{0}};
-    elem_jv<T, NF == 5>(L, p, t, c, yP, yT, yU);
+    elem_jv_m<T, NF == 5>(L, p, t, c, yP, yT, yU);
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
-      if (NF == 5) { out[a][0] = yU[0][a]; out[a][1] = yU[1][a]; out[a][2] = yU[2][a]; }
+      if constexpr (NF == 5) { out[a][0] = yU[0][a]; out[a][1] = yU[1][a]; out[a][2] = yU[2][a]; }
       out[a][NF - 2] = yP[a];
       out[a][NF - 1] = yT[a];
     }
@@ -190,7 +232,7 @@ struct JvOp {
     const bool pf = g.pfix(i, j, k), tf = g.tfix(i, j, k);
     const T ap = pf ? x[NF * n + NF - 2] : v[NF - 2];
     const T at = tf ? x[NF * n + NF - 1] : v[NF - 1];
-    if (NF == 5) {
+    if constexpr (NF == 5) {
       const T M = c.W * (T)g.valence(i, j, k);
 #pragma unroll
       for (int d = 0; d < 3; ++d) y[5 * n + d] = rs.s[d] * (v[d] + M * x[5 * n + d]);
@@ -235,7 +277,7 @@ struct JtwOp {
     if (g.tfix(i, j, k)) t = (T)0;
     in[2] = p;
     in[3] = t;
-    if (NF == 5) {
+    if constexpr (NF == 5) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) in[4 + d] = x[5 * n + d];
     }
@@ -245,13 +287,13 @@ struct JtwOp {
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       P[a] = nd[a][0]; Tn[a] = nd[a][1]; wP[a] = nd[a][2]; wT[a] = nd[a][3];
-      if (NF == 5) { wU[0][a] = nd[a][4 % NIN]; wU[1][a] = nd[a][5 % NIN]; wU[2][a] = nd[a][6 % NIN]; }
+      if constexpr (NF == 5) { wU[0][a] = nd[a][4]; wU[1][a] = nd[a][5]; wU[2][a] = nd[a][6]; }
     }
     const long e = g.elem(i, j, k);
-    Lin<T> L;
-    linearize(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    LinM<T> L;
+    lin_modal(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
     T yP[8] = {0}, yT[8] = {0};
-    elem_jtw<T, NF == 5>(L, wP, wT, wU, c, yP, yT);
+    elem_jtw_m<T, NF == 5>(L, wP, wT, wU, c, yP, yT);
 #pragma unroll
     for (int a = 0; a < 8; ++a) { out[a][0] = yP[a]; out[a][1] = yT[a]; }
   }
@@ -260,7 +302,7 @@ struct JtwOp {
     const bool pf = g.pfix(i, j, k), tf = g.tfix(i, j, k);
     const T ap = pf ? x[NF * n + NF - 2] : v[0];
     const T at = tf ? x[NF * n + NF - 1] : v[1];
-    if (NF == 5) {
+    if constexpr (NF == 5) {
       const T M = c.W * (T)g.valence(i, j, k);
 #pragma unroll
       for (int d = 0; d < 3; ++d) y[5 * n + d] = rs.s[d] * M * x[5 * n + d];
@@ -300,11 +342,11 @@ void launch_jtw5(hipStream_t st, const LevelView<T>& L, const T* w, T* y, const 
 
 template <typename T>
 void launch_pt_apply(hipStream_t st, const LevelView<T>& L, bool transpose, int mode, const T* x, const T* b, T* y,
-                     T omega) {
+                     T omega, bool fine) {
 #define NC_PT(OP, M)                                                              \
   {                                                                             \
     OP<T, 2, M> op{L.g, L.c, L.coef, L.st, x, b, L.dinv, y, omega, ones_or<T>(nullptr)}; \
-    run_zmarch(st, op);                                                         \
+    if (fine) run_zmarch<OP<T, 2, M>, 1>(st, op); else run_zmarch<OP<T, 2, M>, 0>(st, op); \
   }
   if (!transpose) {
     if (mode == MODE_STORE) NC_PT(JvOp, MODE_STORE)
@@ -338,13 +380,13 @@ struct DiagOp {
 #pragma unroll
     for (int a = 0; a < 8; ++a) { P[a] = nd[a][0]; Tn[a] = nd[a][1]; }
     const long e = g.elem(i, j, k);
-    Lin<T> L;
-    linearize(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    LinM<T> L;
+    lin_modal(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
     for (int a = 0; a < 8; ++a) {
       for (int fld = 0; fld < 2; ++fld) {
         T p[8] = {0}, t[8] = {0}, yP[8] = {0}, yT[8] = {0}, yU[3][8];
         if (fld == 0) p[a] = (T)1; else t[a] = (T)1;
-        elem_jv<T, false>(L, p, t, c, yP, yT, yU);
+        elem_jv_m<T, false>(L, p, t, c, yP, yT, yU);
         // row-major block [dRP/dP, dRP/dT; dRT/dP, dRT/dT]
         out[a][fld] = yP[a];
         out[a][2 + fld] = yT[a];
@@ -461,7 +503,7 @@ void launch_uprojT(hipStream_t st, const LevelView<T>& L, const T* r5, T* b_pt, 
 #define NC_INST(T)                                                                                  \
   template void launch_jv5<T>(hipStream_t, const LevelView<T>&, const T*, T*, const Scale5<T>*);    \
   template void launch_jtw5<T>(hipStream_t, const LevelView<T>&, const T*, T*, const Scale5<T>*);   \
-  template void launch_pt_apply<T>(hipStream_t, const LevelView<T>&, bool, int, const T*, const T*, T*, T); \
+  template void launch_pt_apply<T>(hipStream_t, const LevelView<T>&, bool, int, const T*, const T*, T*, T, bool); \
   template void launch_diag_inverse<T>(hipStream_t, const LevelView<T>&, T*);                       \
   template void launch_uproj<T>(hipStream_t, const LevelView<T>&, const T*, const T*, T*, const Scale5<T>*); \
   template void launch_uprojT<T>(hipStream_t, const LevelView<T>&, const T*, T*, T*, const Scale5<T>*);

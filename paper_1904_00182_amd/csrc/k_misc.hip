@@ -1,5 +1,7 @@
 // Multigrid transfers and setup, dense coarse solve, vector kernels, deterministic
 // reductions, design chain (cone filter, RAMP), sensitivities and the objective.
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace nc {
@@ -283,12 +285,21 @@ __global__ void dense_apply_kernel(const double* __restrict__ Ainv, int n, int t
   }
 }
 
+// Ainv holds A^-1 followed by (A^-1)^T (row-major n x n each); both products read rows.
 template <typename T>
 void launch_dense_apply(hipStream_t st, const double* Ainv, int n, bool transpose, const T* b, T* x) {
-  if (!transpose)
-    hipLaunchKernelGGL(dense_apply_kernel<T>, dim3(ceil_div((long)n * 64, BS)), dim3(BS), 0, st, Ainv, n, 0, b, x);
-  else
-    hipLaunchKernelGGL(dense_apply_kernel<T>, dim3(ceil_div(n, BS)), dim3(BS), 0, st, Ainv, n, 1, b, x);
+  const double* M = transpose ? Ainv + (long)n * n : Ainv;
+  hipLaunchKernelGGL(dense_apply_kernel<T>, dim3(ceil_div((long)n * 64, BS)), dim3(BS), 0, st, M, n, 0, b, x);
+}
+
+__global__ void transpose_kernel(const double* __restrict__ A, double* __restrict__ At, int n) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)n * n) return;
+  const long r = t / n, c = t % n;
+  At[c * n + r] = A[t];
+}
+void launch_dense_transpose(hipStream_t st, const double* A, double* At, int n) {
+  hipLaunchKernelGGL(transpose_kernel, dim3(blocks_for((long)n * n)), dim3(BS), 0, st, A, At, n);
 }
 
 // ------------------------------------------------------------------ state / vectors
@@ -412,84 +423,186 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// part[block][c] = partial sum over this block's chunk of V[c] . w
+// Vector loads of 16 bytes: 4 floats or 2 doubles per lane.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int W = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int W = 2; };
+
+__device__ inline double hsum(float4 a, float4 b) {
+  return (double)a.x * b.x + (double)a.y * b.y + (double)a.z * b.z + (double)a.w * b.w;
+}
+__device__ inline double hsum(double2 a, double2 b) { return a.x * b.x + a.y * b.y; }
+
+// Multi-dot and multi-axpy of the Krylov solver.
+//
+// Multi-dot: a 2-D grid, grid row c computes partial sums of V[c] . w over the blocks'
+// chunks (plain streaming dot products; w is re-read by every row and stays in the
+// last-level cache).  The last block to finish (counted with a device-wide atomic ticket
+// that it resets) adds the partials in block order, so the result is deterministic and
+// needs no second launch.  Multi-axpy: each thread updates its elements of w with all
+// the vectors (runtime count, one accumulator per element).
+constexpr int MD_BLOCKS = 256;   // blocks per vector in the multi-dot
+
+__device__ inline void last_block_sum(const double* part, int nblk, int cnt, double* out, unsigned* ticket,
+                                      int do_sqrt, int nb_total) {
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == (unsigned)(nb_total - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // BS threads: (column c, 8 lanes); each lane sums a strided subset, then the 8 lanes
+  // combine in a fixed pattern
+  for (int c0 = 0; c0 < cnt; c0 += BS / 8) {
+    const int c = c0 + (threadIdx.x >> 3), sub = threadIdx.x & 7;
+    double s = 0.0;
+    if (c < cnt) {
+      double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+      int b = sub;
+      for (; b + 24 < nblk; b += 32) {
+        s0 += part[(long)c * MD_BLOCKS + b];
+        s1 += part[(long)c * MD_BLOCKS + b + 8];
+        s2 += part[(long)c * MD_BLOCKS + b + 16];
+        s3 += part[(long)c * MD_BLOCKS + b + 24];
+      }
+      for (; b < nblk; b += 8) s0 += part[(long)c * MD_BLOCKS + b];
+      s = (s0 + s1) + (s2 + s3);
+    }
+    s += __shfl_down(s, 4, 8);
+    s += __shfl_down(s, 2, 8);
+    s += __shfl_down(s, 1, 8);
+    if (sub == 0 && c < cnt) out[c] = do_sqrt ? sqrt(s) : s;
+  }
+  if (threadIdx.x == 0) *ticket = 0u;
+}
+
+// part[c][block] = partial sum of V[c] . w (c = blockIdx.y; row cnt of the grid, if
+// present, computes w . w)
 template <typename T>
 __global__ __launch_bounds__(BS) void mdot_kernel(const T* __restrict__ V, long ld, int cnt, const T* __restrict__ w,
-                                                  long n, double* __restrict__ part) {
-  __shared__ double red[BS / 64][MAXC];
-  double acc[MAXC];
-#pragma unroll
-  for (int c = 0; c < MAXC; ++c) acc[c] = 0.0;
-  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < n; t += (long)gridDim.x * BS) {
-    const double wv = (double)w[t];
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c)
-      if (c < cnt) acc[c] += (double)V[c * ld + t] * wv;
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < MAXC; ++c) {
-    if (c < cnt) {
-      const double s = wave_sum(acc[c]);
-      if (lane == 0) red[wid][c] = s;
-    }
-  }
+                                                  long n, double* __restrict__ part, double* __restrict__ out,
+                                                  unsigned* __restrict__ ticket) {
+  using V16 = typename Vec16<T>::type;
+  constexpr int VW = Vec16<T>::W;
+  __shared__ double red[BS / 64];
+  const int c = blockIdx.y;
+  const T* v = c < cnt ? V + c * ld : w;
+  double acc = 0.0;
+  const long nv = n / VW;
+  const V16* w4 = reinterpret_cast<const V16*>(w);
+  const V16* v4 = reinterpret_cast<const V16*>(v);
+  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < nv; t += (long)gridDim.x * BS) acc += hsum(v4[t], w4[t]);
+  if (blockIdx.x == 0)
+    for (long t = nv * VW + threadIdx.x; t < n; t += BS) acc += (double)v[t] * (double)w[t];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x < cnt) {
+  if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int w2 = 0; w2 < BS / 64; ++w2) s += red[w2][threadIdx.x];
-    part[blockIdx.x * MAXC + threadIdx.x] = s;
+    for (int w2 = 0; w2 < BS / 64; ++w2) s += red[w2];
+    part[(long)c * MD_BLOCKS + blockIdx.x] = s;
   }
+  last_block_sum(part, gridDim.x, gridDim.y, out, ticket, 0, gridDim.x * gridDim.y);
 }
 
-// out[c] = sum over blocks of part[b][c] (fixed order); sqrt if do_sqrt
-__global__ void reduce_parts_kernel(const double* __restrict__ part, int nblk, int cnt, double* __restrict__ out, int do_sqrt) {
-  const int c = threadIdx.x;
-  if (c >= cnt) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[b * MAXC + c];
-  out[c] = do_sqrt ? sqrt(s) : s;
+static inline int md_blocks(long n, int vw) {
+  const long b = (n / vw + BS - 1) / BS;
+  return (int)std::max<long>(1, std::min<long>(b, MD_BLOCKS));
 }
 
+// out[0..cnt-1] = V[c] . w; with `with_norm` also out[cnt] = w . w
 template <typename T>
-void launch_mdot(hipStream_t st, const T* V, long ld, int cnt, const T* w, long n, double* part, double* out) {
-  hipLaunchKernelGGL(mdot_kernel<T>, dim3(RED_BLOCKS), dim3(BS), 0, st, V, ld, cnt, w, n, part);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, cnt, out, 0);
+void launch_mdot(hipStream_t st, const T* V, long ld, int cnt, const T* w, long n, double* part, double* out,
+                 bool with_norm) {
+  const int nb = md_blocks(n, Vec16<T>::W);
+  unsigned* ticket = reinterpret_cast<unsigned*>(part + RED_BLOCKS * MAXC);
+  hipLaunchKernelGGL(mdot_kernel<T>, dim3(nb, cnt + (with_norm ? 1 : 0)), dim3(BS), 0, st, V, ld, cnt, w, n, part,
+                     out, ticket);
 }
+
+// out[c] = sum over blocks of part[b][c] in a fixed order; sqrt if do_sqrt.
+__global__ __launch_bounds__(1024) void reduce_parts_kernel(const double* __restrict__ part, int nblk, int cnt,
+                                                            double* __restrict__ out, int do_sqrt) {
+  const int c = threadIdx.x >> 5, sub = threadIdx.x & 31;
+  double s0 = 0, s1 = 0;
+  if (c < cnt) {
+    int b = sub;
+    for (; b + 32 < nblk; b += 64) {
+      s0 += part[b * MAXC + c];
+      s1 += part[(b + 32) * MAXC + c];
+    }
+    for (; b < nblk; b += 32) s0 += part[b * MAXC + c];
+  }
+  double s = s0 + s1;
+  for (int off = 16; off > 0; off >>= 1) s += __shfl_down(s, off, 32);
+  if (sub == 0 && c < cnt) out[c] = do_sqrt ? sqrt(s) : s;
+}
+
+constexpr int AX_BLOCKS = 1024;
 
 template <typename T>
 __global__ __launch_bounds__(BS) void maxpy_kernel(const T* __restrict__ V, long ld, int cnt, const double* __restrict__ h,
-                                                   double sign, T* __restrict__ w, long n, double* __restrict__ part) {
+                                                   double sign, T* __restrict__ w, long n, double* __restrict__ part,
+                                                   double* __restrict__ nrm_out, unsigned* __restrict__ ticket) {
+  using V16 = typename Vec16<T>::type;
+  constexpr int VW = Vec16<T>::W;
   __shared__ double hs[MAXC];
   __shared__ double red[BS / 64];
   if (threadIdx.x < cnt) hs[threadIdx.x] = sign * h[threadIdx.x];
   __syncthreads();
   double nrm = 0.0;
-  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < n; t += (long)gridDim.x * BS) {
-    double v = (double)w[t];
-    for (int c = 0; c < cnt; ++c) v += hs[c] * (double)V[c * ld + t];
-    const T vt = (T)v;
-    w[t] = vt;
-    nrm += (double)vt * (double)vt;
+  const long nv = n / VW;
+  V16* w4 = reinterpret_cast<V16*>(w);
+  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < nv; t += (long)gridDim.x * BS) {
+    V16 wv = w4[t];
+    double a[VW];
+    T* po = reinterpret_cast<T*>(&wv);
+#pragma unroll
+    for (int q = 0; q < VW; ++q) a[q] = (double)po[q];
+#pragma unroll 4
+    for (int c = 0; c < cnt; ++c) {
+      const V16 vv = reinterpret_cast<const V16*>(V + c * ld)[t];
+      const T* pv = reinterpret_cast<const T*>(&vv);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) a[q] += hs[c] * (double)pv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < VW; ++q) {
+      po[q] = (T)a[q];
+      nrm += (double)po[q] * (double)po[q];
+    }
+    w4[t] = wv;
   }
-  if (part) {
+  if (blockIdx.x == 0) {
+    for (long t = nv * VW + threadIdx.x; t < n; t += BS) {
+      double v = (double)w[t];
+      for (int c = 0; c < cnt; ++c) v += hs[c] * (double)V[c * ld + t];
+      const T vt = (T)v;
+      w[t] = vt;
+      nrm += (double)vt * (double)vt;
+    }
+  }
+  if (nrm_out) {
     const double s = wave_sum(nrm);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
       double tot = 0.0;
       for (int w2 = 0; w2 < BS / 64; ++w2) tot += red[w2];
-      part[blockIdx.x * MAXC] = tot;
+      part[blockIdx.x] = tot;
     }
+    last_block_sum(part, gridDim.x, 1, nrm_out, ticket, 1, gridDim.x);
   }
 }
 
 template <typename T>
 void launch_maxpy(hipStream_t st, const T* V, long ld, int cnt, const double* h, double sign, T* w, long n, double* part,
                   double* nrm_out) {
-  hipLaunchKernelGGL(maxpy_kernel<T>, dim3(RED_BLOCKS), dim3(BS), 0, st, V, ld, cnt, h, sign, w, n,
-                     nrm_out ? part : nullptr);
-  if (nrm_out) hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, 1, nrm_out, 1);
+  const long b = (n / Vec16<T>::W + BS - 1) / BS;
+  const int nb = (int)std::max<long>(1, std::min<long>(b, AX_BLOCKS));
+  unsigned* ticket = reinterpret_cast<unsigned*>(part + RED_BLOCKS * MAXC);
+  hipLaunchKernelGGL(maxpy_kernel<T>, dim3(nb), dim3(BS), 0, st, V, ld, cnt, h, sign, w, n, part, nrm_out, ticket);
 }
 
 template <typename T>
@@ -523,7 +636,7 @@ __global__ __launch_bounds__(BS) void norm_kernel(const T* __restrict__ a, long 
 template <typename T>
 void launch_norm(hipStream_t st, const T* a, long n, double* part, double* out) {
   hipLaunchKernelGGL(norm_kernel<T>, dim3(RED_BLOCKS), dim3(BS), 0, st, a, n, part);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, 1, out, 1);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 1);
 }
 
 __global__ __launch_bounds__(BS) void field_norms_kernel(const double* __restrict__ a, const double* __restrict__ b,
@@ -558,7 +671,7 @@ __global__ __launch_bounds__(BS) void field_norms_kernel(const double* __restric
 }
 void launch_field_norms(hipStream_t st, const double* a, const double* b, long nodes, double* part, double* out) {
   hipLaunchKernelGGL(field_norms_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, a, b, nodes, part);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, 10, out, 1);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 10, out, 1);
 }
 
 // ------------------------------------------------------------------ design chain
@@ -683,7 +796,7 @@ __global__ __launch_bounds__(BS) void coef_sum_kernel(const double* __restrict__
 }
 void launch_coef_sums(hipStream_t st, const double* coef, long E, double* part, double* out) {
   hipLaunchKernelGGL(coef_sum_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, coef, E, part);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, 2, out, 0);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 2, out, 0);
 }
 
 // ------------------------------------------------------------------ objective
@@ -709,7 +822,7 @@ __global__ __launch_bounds__(BS) void objective_kernel(Grid g, Patch pa, const d
 }
 void launch_objective(hipStream_t st, const Grid& g, const Patch& patch, const double* s5, double* part, double* out) {
   hipLaunchKernelGGL(objective_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, g, patch, s5, part);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, part, RED_BLOCKS, 1, out, 0);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 0);
 }
 
 __global__ void objective_grad_kernel(Grid g, Patch pa, double* __restrict__ g5) {
@@ -743,7 +856,7 @@ void launch_objective_grad(hipStream_t st, const Grid& g, const Patch& patch, do
   template void launch_extract_pt<T>(hipStream_t, const Grid&, const T*, T*, const Scale5<T>*);     \
   template void launch_scatter_pt<T>(hipStream_t, const Grid&, const T*, const T*, T*, const Scale5<T>*); \
   template void launch_scale5<T>(hipStream_t, long, const double*, T*, Scale5<double>);             \
-  template void launch_mdot<T>(hipStream_t, const T*, long, int, const T*, long, double*, double*); \
+  template void launch_mdot<T>(hipStream_t, const T*, long, int, const T*, long, double*, double*, bool); \
   template void launch_maxpy<T>(hipStream_t, const T*, long, int, const double*, double, T*, long, double*, double*); \
   template void launch_scale_inv<T>(hipStream_t, const double*, const T*, T*, long);                \
   template void launch_norm<T>(hipStream_t, const T*, long, double*, double*);                     \

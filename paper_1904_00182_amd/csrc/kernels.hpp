@@ -22,7 +22,7 @@ void launch_jtw5(hipStream_t st, const LevelView<T>& L, const T* w, T* y, const 
 // block-Jacobi sweep y = x + omega D^-1 (b - A x); transpose selects A^T.
 template <typename T>
 void launch_pt_apply(hipStream_t st, const LevelView<T>& L, bool transpose, int mode, const T* x, const T* b,
-                     T* y, T omega);
+                     T* y, T omega, bool fine);
 // Inverse 2x2 (P, T) node blocks of the level Jacobian into dinv [N][4].
 template <typename T>
 void launch_diag_inverse(hipStream_t st, const LevelView<T>& L, T* dinv);
@@ -49,6 +49,7 @@ void launch_average_coef(hipStream_t st, const Grid& fine, const Grid& coarse, c
 template <typename T>
 void launch_coarse_assemble(hipStream_t st, const LevelView<T>& L, double* elem_mats, double* A);
 void launch_gauss_jordan(hipStream_t st, double* A, int n, int* perm);
+void launch_dense_transpose(hipStream_t st, const double* A, double* At, int n);
 template <typename T>
 void launch_dense_apply(hipStream_t st, const double* Ainv, int n, bool transpose, const T* b, T* x);
 
@@ -72,11 +73,14 @@ void launch_diag_scale(hipStream_t st, const Grid& g, const T* dinv, bool transp
 template <typename T>
 void launch_rsub(hipStream_t st, const T* b, T* out, long n);                          // out = b - out
 
-// ---- reductions (deterministic: fixed grid, fixed order)
-constexpr int RED_BLOCKS = 240;
+// ---- reductions (deterministic: fixed grid, fixed order).  `part` must hold
+// RED_BLOCKS * MAXC doubles followed by one zero-initialised unsigned ticket.
+constexpr int RED_BLOCKS = 2048;
 constexpr int MAXC = 32;
+// out[c] = V[c] . w for c < cnt (and out[cnt] = w . w when with_norm)
 template <typename T>
-void launch_mdot(hipStream_t st, const T* V, long ld, int cnt, const T* w, long n, double* part, double* out);
+void launch_mdot(hipStream_t st, const T* V, long ld, int cnt, const T* w, long n, double* part, double* out,
+                 bool with_norm = false);
 // w += sign * sum_c h[c] V[c]; if nrm_out != null also nrm_out[0] = ||w||_2 after the update
 template <typename T>
 void launch_maxpy(hipStream_t st, const T* V, long ld, int cnt, const double* h, double sign, T* w, long n,

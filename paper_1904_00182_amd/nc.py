@@ -20,8 +20,11 @@ EXPORTED = [
     "nc_problem_default", "nc_workspace_bytes", "nc_create", "nc_destroy", "nc_status_string",
     "nc_set_design", "nc_get_gamma", "nc_residual", "nc_linearize", "nc_jac_apply", "nc_jacT_apply",
     "nc_jac_apply_f32", "nc_jacT_apply_f32", "nc_solve_state", "nc_objective", "nc_objective_grad",
-    "nc_solve_adjoint", "nc_sensitivity", "nc_cone_filter",
+    "nc_solve_adjoint", "nc_sensitivity", "nc_cone_filter", "nc_set_timing", "nc_get_timing",
 ]
+
+TIMER_CLASSES = ["residual", "jv5", "jtw5", "smooth", "smooth_T", "pt_residual", "diag", "uproj", "transfer",
+                 "coarse", "mdot", "maxpy", "vector", "setup", "smooth_coarse"]
 
 
 class NCProblem(ctypes.Structure):
@@ -90,6 +93,8 @@ def load():
             "nc_solve_adjoint": (I, [V, V, V, V, ctypes.POINTER(NCInfo)]),
             "nc_sensitivity": (I, [V, V, V, V, V]),
             "nc_cone_filter": (I, [I, I, I, D, V, V, I, V]),
+            "nc_set_timing": (I, [V, I]),
+            "nc_get_timing": (I, [V, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long), I]),
         }
         for name, (res, argt) in sig.items():
             f = getattr(lib, name)
@@ -238,6 +243,19 @@ class Solver:
         self.last_info = info.as_dict()
         self.last_info["status"] = st
         return lam
+
+    def set_timing(self, enable=True):
+        _check(self.lib.nc_set_timing(self.ctx, 1 if enable else 0), "nc_set_timing")
+
+    def timing(self):
+        """{class: (total ms, launches)} of the kernels timed since set_timing(True)."""
+        n = len(TIMER_CLASSES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_long * n)()
+        r = self.lib.nc_get_timing(self.ctx, ms, cnt, n)
+        if r < 0:
+            raise NCError(r, "nc_get_timing")
+        return {TIMER_CLASSES[k]: (ms[k], cnt[k]) for k in range(n)}
 
     def sensitivity(self, s, lam, with_gamma=False):
         s = self._in(s, (self.N, 5))

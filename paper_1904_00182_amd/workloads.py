@@ -27,9 +27,13 @@ CONFIGS = {
 
 
 def problem(grid, gr=1e3, precision=nc.NC_FP64, radius=0.0, q_h=1.0, **over):
+    """Cavity problem at Grashof number gr (alpha = gr, kappa_f from Table tab:2); keyword
+    overrides replace any field (e.g. alpha=0 for pure conduction)."""
     nx, ny, nz = grid
-    return nc.default_problem(nx, ny, nz, alpha=float(gr), kappa_f=KAPPA_F[float(gr)], precision=precision,
-                              filter_radius=float(radius), q_h=float(q_h), **over)
+    fields = dict(alpha=float(gr), kappa_f=KAPPA_F[float(gr)], precision=precision, filter_radius=float(radius),
+                  q_h=float(q_h), smooth_omega=0.8)
+    fields.update(over)
+    return nc.default_problem(nx, ny, nz, **fields)
 
 
 def design(grid, recipe, seed, device="cuda:0"):

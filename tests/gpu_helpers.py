@@ -41,3 +41,86 @@ def rel_fields(a, b):
 
 def to_dev(a, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def local_rows(p, s, k, kap, nodes, v=None, transpose_w=None):
+    """Oracle rows at a few nodes of a large grid, computed from the elements around
+    each node only (oracle.element_residual, complex step for the Jacobian).
+
+    Returns an array (len(nodes), 5): R~ at those nodes, or (J~ v) when v is given.
+    s, v: (N, 5) float64; k, kap: (E,) element coefficients; nodes: list of (i, j, k).
+    """
+    prm = oracle_params(p)
+    mesh = oracle.Mesh(prm)
+    mask, _ = oracle.default_constraints(mesh)
+    out = np.zeros((len(nodes), NFIELD))
+    h = 1e-30
+    for r, (i, j, kk) in enumerate(nodes):
+        n = mesh.node_id(i, j, kk)
+        elems, corner = [], []
+        for c in range(8):
+            ei, ej, ek = i - (c & 1), j - ((c >> 1) & 1), kk - ((c >> 2) & 1)
+            if 0 <= ei < p.nx and 0 <= ej < p.ny and 0 <= ek < p.nz:
+                elems.append(mesh.elem_id(ei, ej, ek))
+                corner.append(c)
+        elems = np.array(elems)
+        conn = mesh.conn[elems]
+        se = s[conn]                                    # (Ee, 8, 5)
+        if transpose_w is not None:
+            wm = transpose_w.copy()
+            wm[mask] = 0.0
+            we = wm[conn]
+            for f in range(NFIELD):
+                if mask[n, f]:
+                    out[r, f] = transpose_w[n, f]
+                    continue
+                sp = se.astype(complex)
+                for e_loc, c in enumerate(corner):
+                    sp[e_loc, c, f] += 1j * h
+                RP, RT, RU = oracle.element_residual(sp[:, :, 3], sp[:, :, 4], sp[:, :, 0:3], k[elems], kap[elems], prm)
+                col = (np.einsum("ea,ea->", RP.imag, we[:, :, 3]) + np.einsum("ea,ea->", RT.imag, we[:, :, 4])
+                       + np.einsum("ead,ead->", RU.imag, we[:, :, 0:3])) / h
+                out[r, f] = col
+            continue
+        if v is not None:
+            vm = v.copy()
+            vm[mask] = 0.0
+            se = se.astype(complex) + 1j * h * vm[conn]
+        RP, RT, RU = oracle.element_residual(se[:, :, 3], se[:, :, 4], se[:, :, 0:3], k[elems], kap[elems], prm)
+        row = np.zeros(NFIELD, dtype=se.dtype)
+        for e_loc, c in enumerate(corner):
+            row[0:3] += RU[e_loc, c]
+            row[3] += RP[e_loc, c]
+            row[4] += RT[e_loc, c]
+        if v is None:
+            row = row.real
+            # flux load of the patch faces around a bottom node
+            if kk == 0:
+                x0, x1, y0, y1 = prm.patch
+                for c in range(4):
+                    fi, fj = i - (c & 1), j - (c >> 1)
+                    if 0 <= fi < p.nx and 0 <= fj < p.ny:
+                        xc, yc = (fi + 0.5) * prm.h, (fj + 0.5) * prm.h
+                        if x0 <= xc <= x1 and y0 <= yc <= y1:
+                            row[4] -= prm.q_h * prm.h * prm.h / 4
+            for f in range(NFIELD):
+                if mask[n, f]:
+                    row[f] = s[n, f]
+        else:
+            row = row.imag / h
+            for f in range(NFIELD):
+                if mask[n, f]:
+                    row[f] = v[n, f]
+        out[r] = row
+    return out
+
+
+def sample_nodes(p, count, seed):
+    """Random nodes plus corners, wall, top, pinned and patch nodes."""
+    g = inputs.rng(seed)
+    pts = {(0, 0, 0), (p.nx, p.ny, p.nz), (0, 0, p.nz), (p.nx, 0, 0), (0, p.ny, 0),
+           (p.nx // 2, p.ny // 2, 0), (p.nx // 2, p.ny // 4, 0), (p.nx // 2 + 1, p.ny // 4, 0),
+           (1, 1, p.nz - 1), (p.nx - 1, p.ny - 1, 1), (p.nx // 2, p.ny // 2, p.nz // 2)}
+    while len(pts) < count:
+        pts.add((int(g.integers(p.nx + 1)), int(g.integers(p.ny + 1)), int(g.integers(p.nz + 1))))
+    return sorted(pts)

@@ -10,6 +10,8 @@
 
 using namespace nc;
 
+static int g_variant = 0;   // 0: Gauss-point element functions, 1: modal element functions
+
 namespace {
 struct Grid {
   int nx, ny, nz;
@@ -47,6 +49,8 @@ void for_elems(const Grid& g, F f) {
 
 extern "C" {
 
+void hc_set_variant(int v) { g_variant = v; }
+
 int hc_residual(const int* dims, const double* prm, const double* kk, const double* kap, const double* s, double* r) {
   Grid g = make(dims, prm);
   long N = (long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
@@ -54,9 +58,15 @@ int hc_residual(const int* dims, const double* prm, const double* kk, const doub
   for_elems(g, [&](int i, int j, int k, long e, const long* n) {
     double P[8], T[8], rP[8] = {0}, rT[8] = {0}, rU[3][8] = {{0}};
     for (int a = 0; a < 8; ++a) { P[a] = s[5 * n[a] + 3]; T[a] = s[5 * n[a] + 4]; }
-    Lin<double> L;
-    linearize(P, T, kk[e], kap[e], g.c, L);
-    elem_residual<double, true>(L, g.c, rP, rT, rU);
+    if (g_variant == 0) {
+      Lin<double> L;
+      linearize(P, T, kk[e], kap[e], g.c, L);
+      elem_residual<double, true>(L, g.c, rP, rT, rU);
+    } else {
+      LinM<double> L;
+      lin_modal(P, T, kk[e], kap[e], g.c, L);
+      elem_residual_m<double, true>(L, g.c, rP, rT, rU);
+    }
     if (k == 0) {
       double xc = (i + 0.5) * g.h, yc = (j + 0.5) * g.h;
       if (xc >= g.px0 && xc <= g.px1 && yc >= g.py0 && yc <= g.py1)
@@ -114,9 +124,15 @@ int hc_jv(const int* dims, const double* prm, const double* kk, const double* ka
       P[a] = s[5 * n[a] + 3]; T[a] = s[5 * n[a] + 4];
       p[a] = vm[5 * n[a] + 3]; t[a] = vm[5 * n[a] + 4];
     }
-    Lin<double> L;
-    linearize(P, T, kk[e], kap[e], g.c, L);
-    elem_jv<double, true>(L, p, t, g.c, yP, yT, yU);
+    if (g_variant == 0) {
+      Lin<double> L;
+      linearize(P, T, kk[e], kap[e], g.c, L);
+      elem_jv<double, true>(L, p, t, g.c, yP, yT, yU);
+    } else {
+      LinM<double> L;
+      lin_modal(P, T, kk[e], kap[e], g.c, L);
+      elem_jv_m<double, true>(L, p, t, g.c, yP, yT, yU);
+    }
     for (int a = 0; a < 8; ++a) {
       for (int d = 0; d < 3; ++d) y[5 * n[a] + d] += yU[d][a];
       y[5 * n[a] + 3] += yP[a];
@@ -140,9 +156,15 @@ int hc_jtw(const int* dims, const double* prm, const double* kk, const double* k
       wP[a] = wm[5 * n[a] + 3]; wT[a] = wm[5 * n[a] + 4];
       for (int d = 0; d < 3; ++d) wU[d][a] = wm[5 * n[a] + d];
     }
-    Lin<double> L;
-    linearize(P, T, kk[e], kap[e], g.c, L);
-    elem_jtw<double, true>(L, wP, wT, wU, g.c, yP, yT);
+    if (g_variant == 0) {
+      Lin<double> L;
+      linearize(P, T, kk[e], kap[e], g.c, L);
+      elem_jtw<double, true>(L, wP, wT, wU, g.c, yP, yT);
+    } else {
+      LinM<double> L;
+      lin_modal(P, T, kk[e], kap[e], g.c, L);
+      elem_jtw_m<double, true>(L, wP, wT, wU, g.c, yP, yT);
+    }
     for (int a = 0; a < 8; ++a) {
       y[5 * n[a] + 3] += yP[a];
       y[5 * n[a] + 4] += yT[a];

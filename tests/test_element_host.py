@@ -54,8 +54,15 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+@pytest.fixture(params=[0, 1], ids=["gauss", "modal"])
+def variant(request):
+    lib().hc_set_variant(request.param)
+    yield request.param
+    lib().hc_set_variant(0)
+
+
 @pytest.mark.parametrize("kw", [dict(alpha=1e3), dict(alpha=1e4, kappa_f=0.00206, Q=0.7, q_h=3.0)])
-def test_host_residual_matches_oracle(kw):
+def test_host_residual_matches_oracle(kw, variant):
     p, m, s = setup(**kw)
     dims, prm = args(p)
     r = np.zeros_like(s)
@@ -66,7 +73,7 @@ def test_host_residual_matches_oracle(kw):
 
 
 @pytest.mark.parametrize("kw", [dict(alpha=1e3), dict(alpha=1e4, kappa_f=0.00206, Q=0.7)])
-def test_host_jacobian_and_transpose_match_oracle(kw):
+def test_host_jacobian_and_transpose_match_oracle(kw, variant):
     p, m, s = setup(**kw)
     dims, prm = args(p)
     J = m.jacobian(s)

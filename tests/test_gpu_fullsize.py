@@ -1,0 +1,119 @@
+"""Full-size checks in the benchmark's launch configuration: sampled outputs that the
+oracle computes node by node, and properties that hold at any size."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.problem import NFIELD
+from paper_1904_00182_amd import nc, inputs, workloads
+from gpu_helpers import oracle_params, local_rows, sample_nodes, to_dev, DEV
+
+pytestmark = pytest.mark.gpu
+
+FULL = [("cavity64", 1e-11), ("cavity96filtered", 1e-11), ("cavity128mixed", 1e-11)]
+
+
+@pytest.mark.parametrize("name,tol", FULL)
+def test_sampled_rows_full_size(name, tol):
+    """R(s), J v and J^T w at ~40 sampled nodes (corners, walls, top, pin, patch, random)
+    of the full grid, at a random state, against the oracle's element rows there."""
+    p, x, cfg = workloads.config(name, DEV)
+    sol = nc.Solver(p, DEV)
+    sol.set_design(x)
+    gam = sol.gamma().cpu().numpy()
+    op = oracle_params(p)
+    k = oracle.ramp_k(gam, op.k_f, op.k_s, op.q_c)
+    kap = oracle.ramp_kappa(gam, op.kappa_f, op.kappa_s, op.q_p)
+    N = sol.N
+    rng = inputs.rng(31)
+    s = rng.standard_normal((N, NFIELD)) * 0.05
+    s[:, 3] *= 20.0
+    v = rng.standard_normal((N, NFIELD))
+    w = rng.standard_normal((N, NFIELD))
+    sd = to_dev(s)
+    mesh = oracle.Mesh(op)
+    mask, _ = oracle.default_constraints(mesh)
+    s[mask] = 0.0
+    sd = to_dev(s)
+    nodes = sample_nodes(p, 40, 5)
+    ids = [mesh.node_id(*n) for n in nodes]
+    r = sol.residual(sd).cpu().numpy()[ids]
+    ro = local_rows(p, s, k, kap, nodes)
+    assert np.abs(r - ro).max() <= tol * np.abs(ro).max() + 1e-300
+    sol.linearize(sd)
+    y = sol.jac_apply(to_dev(v)).cpu().numpy()[ids]
+    yo = local_rows(p, s, k, kap, nodes, v=v)
+    for f in range(NFIELD):
+        assert np.abs(y[:, f] - yo[:, f]).max() <= tol * np.abs(yo[:, f]).max(), f
+    y = sol.jac_apply(to_dev(w), transpose=True).cpu().numpy()[ids]
+    yo = local_rows(p, s, k, kap, nodes, transpose_w=w)
+    for f in range(NFIELD):
+        assert np.abs(y[:, f] - yo[:, f]).max() <= tol * np.abs(yo[:, f]).max(), f
+    y32 = sol.jac_apply(to_dev(v, torch.float32)).cpu().numpy()[ids]
+    yo = local_rows(p, s, k, kap, nodes, v=v)
+    for f in range(NFIELD):
+        assert np.abs(y32[:, f] - yo[:, f]).max() <= 2e-5 * np.abs(yo[:, f]).max(), f
+
+
+def _energy_balance(p, gam, s):
+    """sum of the unconstrained energy rows at the isothermal nodes + q_h A_patch, from the
+    oracle's element rows of the elements touching an isothermal node."""
+    op = oracle_params(p)
+    mesh = oracle.Mesh(op)
+    mask, _ = oracle.default_constraints(mesh)
+    iso = mask[:, 4]
+    k = oracle.ramp_k(gam, op.k_f, op.k_s, op.q_c)
+    kap = oracle.ramp_kappa(gam, op.kappa_f, op.kappa_s, op.q_p)
+    touch = np.nonzero(iso[mesh.conn].any(axis=1))[0]
+    conn = mesh.conn[touch]
+    se = s[conn]
+    RP, RT, RU = oracle.element_residual(se[:, :, 3], se[:, :, 4], se[:, :, 0:3], k[touch], kap[touch], op)
+    total = RT[iso[conn]].sum()
+    flux = oracle.patch_flux(mesh, op)
+    heat_in = flux.sum()
+    return total, heat_in
+
+
+@pytest.mark.parametrize("name", ["cavity128mixed", "cavity96filtered"])
+def test_full_size_solution_properties(name):
+    """At full size: the heat leaving through the isothermal walls equals the heat entering
+    through the patch (discrete energy balance of the weak form), the residual of the
+    solution is at round-off, and the solve converged."""
+    p, x, cfg = workloads.config(name, DEV)
+    sol = nc.Solver(p, DEV)
+    sol.set_design(x)
+    s = sol.solve_state()
+    assert sol.last_info["status"] == nc.NC_OK, sol.last_info
+    r = sol.residual(s).cpu().numpy()
+    sn = s.cpu().numpy()
+    total, heat_in = _energy_balance(p, sol.gamma().cpu().numpy(), sn)
+    assert abs(total + heat_in) < 1e-9 * heat_in, (total, heat_in)
+    assert np.abs(r[:, 4]).max() < 1e-12 * np.abs(oracle.patch_flux(oracle.Mesh(oracle_params(p)), oracle_params(p))).max()
+    assert np.all(np.isfinite(sn))
+
+
+def test_mixed_precision_error_vs_fp64_at_1m_elements():
+    """128x64x128, Gr 1e4: the mixed-precision state, adjoint and df/dx agree with the
+    float64 GPU solve to 1e-8 per field (iterative refinement restores float64 accuracy)."""
+    out = {}
+    for name in ("cavity128mixed", "cavity128"):
+        p, x, cfg = workloads.config(name, DEV)
+        sol = nc.Solver(p, DEV)
+        sol.set_design(x)
+        s = sol.solve_state()
+        assert sol.last_info["status"] == nc.NC_OK
+        lam = sol.solve_adjoint(s, sol.objective_grad())
+        assert sol.last_info["status"] == nc.NC_OK
+        out[name] = (s.cpu().numpy(), lam.cpu().numpy(), sol.sensitivity(s, lam).cpu().numpy())
+        del sol
+        torch.cuda.empty_cache()
+    for a, b in zip(out["cavity128mixed"], out["cavity128"]):
+        a2, b2 = a.reshape(len(a), -1), b.reshape(len(b), -1)
+        for f in range(a2.shape[1]):
+            nb = np.linalg.norm(b2[:, f])
+            if nb > 0:
+                err = np.linalg.norm(a2[:, f] - b2[:, f]) / nb
+                print("mixed vs fp64 field", f, err)
+                assert err < 1e-8

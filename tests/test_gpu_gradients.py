@@ -1,0 +1,99 @@
+"""Design sensitivities through torch.autograd (adjoint + RAMP + filter transpose) against
+central finite differences of the GPU objective and against the oracle's adjoint."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1904_00182_amd import nc, inputs, workloads
+from paper_1904_00182_amd.autograd import solve_state, compliance
+from gpu_helpers import oracle_params, to_dev, DEV
+
+pytestmark = pytest.mark.gpu
+
+
+def _f(sol, x, s0):
+    sol.set_design(x)
+    s = sol.solve_state(s0=s0)
+    assert sol.last_info["status"] == nc.NC_OK
+    return sol.objective(s)
+
+
+def test_autograd_vs_central_fd_cavity96():
+    """96x48x96, design 0.5 + 0.1 U(-1,1) (seed 3), cone filter R = 1.5 in the chain:
+    autograd gradient vs central FD (h = 1e-6) on 16 elements drawn from seed 33, within
+    the round-off bound of the FD quotient, and a tight random-direction check."""
+    p, x, cfg = workloads.config("cavity96filtered", DEV)
+    sol = nc.Solver(p, DEV)
+    xr = x.clone().requires_grad_(True)
+    s = solve_state(xr, sol)
+    f = compliance(s, sol)
+    f.backward()
+    g = xr.grad.detach().cpu().numpy()
+    f0 = float(f)
+    base = s.detach().clone()
+    assert abs(f0 - sol.objective(base)) < 1e-14 * abs(f0)
+    idx = inputs.choose_elements(sol.E, 16, 33)
+    h = 1e-6
+    eps_f = 1e-13 * abs(f0)
+    for e in idx:
+        vals = []
+        for sg in (1.0, -1.0):
+            xx = x.clone()
+            xx[e] += sg * h
+            vals.append(_f(sol, xx, base))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[e]) <= 3 * eps_f / h + 1e-6 * np.abs(g).max(), (e, fd, g[e])
+    # directional derivative along a random +-1 direction: large signal, tight check
+    v = torch.as_tensor(np.sign(inputs.rng(34).standard_normal(sol.E)), device=DEV)
+    hd = 1e-4
+    fp = _f(sol, x + hd * v, base)
+    fm = _f(sol, x - hd * v, base)
+    dd = (fp - fm) / (2 * hd)
+    gv = float(np.dot(g, v.cpu().numpy()))
+    assert abs(dd - gv) <= 1e-5 * abs(gv), (dd, gv)
+
+
+def test_adjoint_gradient_vs_oracle_cavity24():
+    """24x12x24 version of the same chain: GPU df/dx (and df/dgamma) within 1e-8 of the
+    oracle's SuperLU adjoint and complex-step sensitivities."""
+    p, x, cfg = workloads.config("cavity24filtered", DEV)
+    sol = nc.Solver(p, DEV)
+    xr = x.clone().requires_grad_(True)
+    s = solve_state(xr, sol)
+    compliance(s, sol).backward()
+    g = xr.grad.detach().cpu().numpy()
+    m = oracle.Model(oracle_params(p), x.cpu().numpy())
+    so, _ = m.solve_state()
+    lo = m.solve_adjoint(so, m.dfds())
+    go_gamma, go = m.sensitivity(so, lo)
+    assert np.linalg.norm(g - go) / np.linalg.norm(go) < 1e-8
+    lam = sol.solve_adjoint(s.detach(), sol.objective_grad())
+    _, dfdg = sol.sensitivity(s.detach(), lam, with_gamma=True)
+    assert np.linalg.norm(dfdg.cpu().numpy() - go_gamma) / np.linalg.norm(go_gamma) < 1e-8
+
+
+def test_autograd_general_loss_uses_velocity():
+    """A loss on the velocity unknowns (not the compliance): autograd vs central FD along a
+    random direction on a small grid (checks the velocity rows of the adjoint)."""
+    p = workloads.problem((16, 8, 16), 1e4, q_h=5.0)
+    x = torch.as_tensor(inputs.noise_design(16 * 8 * 16, 7), device=DEV)
+    sol = nc.Solver(p, DEV)
+    wts = torch.as_tensor(inputs.rng(8).standard_normal((sol.N, 5)), device=DEV)
+    xr = x.clone().requires_grad_(True)
+    s = solve_state(xr, sol)
+    loss = (s[:, 0:3] * wts[:, 0:3]).sum() + (s[:, 3:5] ** 2).sum()
+    loss.backward()
+    g = xr.grad.detach()
+    v = torch.as_tensor(inputs.rng(9).standard_normal(sol.E), device=DEV)
+
+    def L(xx):
+        sol.set_design(xx)
+        ss = sol.solve_state()
+        return float((ss[:, 0:3] * wts[:, 0:3]).sum() + (ss[:, 3:5] ** 2).sum())
+
+    hd = 1e-5
+    dd = (L(x + hd * v) - L(x - hd * v)) / (2 * hd)
+    gv = float((g * v).sum())
+    assert abs(dd - gv) <= 1e-6 * abs(gv) + 1e-12, (dd, gv)

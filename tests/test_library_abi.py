@@ -41,7 +41,7 @@ def test_host_only_entry_points():
     b16 = nc.workspace_bytes(p)
     assert b16 > 0
     p64 = nc.default_problem(64, 32, 64)
-    assert nc.workspace_bytes(p64) > 50 * b16
+    assert nc.workspace_bytes(p64) > 30 * b16
     pm = nc.default_problem(64, 32, 64, precision=nc.NC_MIXED)
     assert nc.workspace_bytes(pm) < nc.workspace_bytes(p64)
     bad = nc.default_problem(16, 8, 16, krylov_restart=0)
