@@ -25,6 +25,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = {4: 157.3, 8: 78.6}     # MI355X vector peaks, float32 and float64
+
+# Flops of one operator launch per finest-grid element and node: the element
+# linearisation (279) plus the element apply, and the node-level assembly and finishing.
+# The element figures are counted on the element code by tests/native/flop_count.cpp
+# (checked by tests/test_flop_count.py).
+FLOPS_PER_ELEM = {"jv5": 279 + 711, "jtw5": 279 + 758, "smooth": 279 + 524, "smooth_T": 279 + 593,
+                  "pt_residual": 279 + 524}
+FLOPS_PER_NODE = {"jv5": 47, "jtw5": 23, "smooth": 26, "smooth_T": 26, "pt_residual": 16}
+
+# kernel symbol of each timed class (tile template arguments elided)
+KERNEL_NAMES = {
+    "jv5": "zmarch_kernel<JvOp<{t},5,0>,..> (five-field J v)",
+    "jtw5": "zmarch_kernel<JtwOp<{t},5,0>,..> (five-field J^T w)",
+    "smooth": "zmarch_kernel<JvOp<{t},2,2>,..,1> (finest-grid block-Jacobi sweep)",
+    "smooth_T": "zmarch_kernel<JtwOp<{t},2,2>,..,1> (finest-grid transposed block-Jacobi sweep)",
+    "smooth_coarse": "zmarch_kernel<JvOp/JtwOp<{t},2,2>,..,0> (block-Jacobi sweeps, coarse levels)",
+    "pt_residual": "zmarch_kernel<JvOp/JtwOp<{t},2,1>,..> (multigrid residual)",
+    "mdot": "mdot_kernel<{t}> (FGMRES multi-dot)",
+    "maxpy": "maxpy_kernel<{t}> (FGMRES multi-axpy)",
+    "transfer": "restrict/prolong/diag_scale kernels (grid transfers)",
+}
 
 
 def parse():
@@ -182,6 +204,7 @@ def main():
     torch.cuda.synchronize()
     t_step_timed = (time.perf_counter() - t0) / args.steps
     classes = sol.timing()
+    sol.timing_bytes = sol.timing(with_bytes=True)
     sol.set_timing(False)
     log(args, "kernel classes (ms, launches) over the instrumented steps:",
         {k: (round(v[0], 2), v[1]) for k, v in classes.items() if v[1]})
@@ -201,20 +224,38 @@ def main():
     bytes_jv = (N * (5 + 5 + 2) + E * 2) * sz
     bytes_jv64 = (N * (5 + 5 + 2) + E * 2) * 8
     dofs = 5 * N
-    # dominant operator kernel of the solve.  Algorithmic bytes per launch, per node and
-    # element of the finest grid: five-field applies read v (5) and the (P, T) state (2)
-    # and write y (5); a finest-grid smoothing sweep reads x (2), b (2), the 2x2 block
-    # inverse (4) and the state (2) and writes x' (2); both read (k, kappa) per element.
-    ops = {"jv5": "zmarch_kernel<JvOp<{t},5,0>,33,17,1> (five-field J v)",
-           "jtw5": "zmarch_kernel<JtwOp<{t},5,0>,33,17,1> (five-field J^T w)",
-           "smooth": "zmarch_kernel<JvOp<{t},2,2>,33,17,1> (finest-grid block-Jacobi sweep, J)",
-           "smooth_T": "zmarch_kernel<JtwOp<{t},2,2>,33,17,1> (finest-grid block-Jacobi sweep, J^T)"}
-    dom = max(ops, key=lambda k: classes[k][0])
-    dom_ms, dom_n = classes[dom]
+    # dominant kernel class of the solve (by summed HIP-event time) and its roofline:
+    # achieved = the class's algorithmic bytes (library accounting: inputs read once,
+    # outputs written once) / its summed launch time
+    classes_b = sol.timing_bytes
+    dom = max(classes_b, key=lambda k: classes_b[k][0])
+    dom_ms, dom_n, dom_bytes = classes_b[dom]
     t_dom = dom_ms / max(dom_n, 1) * 1e-3
-    bytes_dom = (N * 12 + E * 2) * sz
-    ach = bytes_dom / t_dom / 1e9
-    share = dom_ms / max(1e-9, sum(v[0] for v in classes.values()))
+    ach = dom_bytes / (dom_ms * 1e-3) / 1e9
+    share = dom_ms / max(1e-9, sum(v[0] for v in classes_b.values()))
+    roof = {
+        "kernel": KERNEL_NAMES.get(dom, dom).format(t="float" if mixed else "double"),
+        "bound": "hbm",
+        "achieved": round(ach, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(ach / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "class": dom,
+        "launch_us": round(t_dom * 1e6, 2),
+        "launches": dom_n,
+        "bytes_per_launch": round(dom_bytes / max(dom_n, 1)),
+        "share_of_kernel_time": round(share, 3),
+        "timed_step_ms": round(t_step_timed * 1e3, 3),
+    }
+    if dom in FLOPS_PER_ELEM:
+        # arithmetic side of the operator kernels: exact flops of the element and node
+        # arithmetic (counted on the element code itself) against the vector peak
+        fl = FLOPS_PER_ELEM[dom] * E + FLOPS_PER_NODE[dom] * N
+        peak = VALU_PEAK_TFLOPS[sz]
+        roof["alu"] = {"achieved_tflops": round(fl / t_dom / 1e12, 2), "peak_tflops": peak,
+                       "frac": round(fl / t_dom / 1e12 / peak, 4), "flops_per_launch": fl,
+                       "flops_per_byte": round(fl / (dom_bytes / max(dom_n, 1)), 2)}
     result = {
         "metric": "state+adjoint solve s at 1M elems",
         "value": round(t_step, 5),
@@ -239,20 +280,7 @@ def main():
             "dofs": dofs,
             "parallelism": "single GPU",
         },
-        "roofline": {
-            "kernel": ops[dom].format(t="float" if mixed else "double"),
-            "bound": "hbm",
-            "achieved": round(ach, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "launch_us": round(t_dom * 1e6, 2),
-            "launches": dom_n,
-            "bytes_per_launch": bytes_dom,
-            "share_of_kernel_time": round(share, 3),
-            "timed_step_ms": round(t_step_timed * 1e3, 3),
-        },
+        "roofline": roof,
         "kernel_classes_ms": {k: round(v[0] / args.steps, 3) for k, v in classes.items() if v[1]},
         "operator": {
             "jv_working_precision_us": round(t_jv * 1e6, 2),

@@ -150,15 +150,17 @@ int    nc_sensitivity(nc_ctx* ctx, const double* s_dev, const double* lam_dev, d
 /* Optional per-context timing of the solver's kernels with HIP events on the context's
  * stream (a tracing aid; adds one event pair per timed launch).  nc_set_timing(ctx, 1)
  * creates the events (once) and zeroes the counters; 0 turns timing off.
- * nc_get_timing synchronises, then fills ms[k] (summed milliseconds) and counts[k]
- * (launches) for k < n over the kernel classes 0 residual, 1 five-field J v,
- * 2 five-field J^T w, 3 smoothing sweep on the finest grid, 4 transposed sweep on the
- * finest grid, 5 multigrid residual, 6 node-block diagonal, 7 velocity coupling,
- * 8 grid transfers, 9 coarsest solve, 10 Krylov multi-dot, 11 Krylov multi-axpy,
- * 12 other vector kernels, 13 preconditioner setup, 14 smoothing sweeps on coarser
- * levels; returns the number of classes (15) or an error code. */
+ * nc_get_timing synchronises, then fills ms[k] (summed milliseconds), counts[k]
+ * (launches) and, when bytes is non-NULL, bytes[k] (the algorithmic bytes of those
+ * launches: every input read once, every output written once) for k < n over the kernel
+ * classes 0 residual, 1 five-field J v, 2 five-field J^T w, 3 smoothing sweep on the
+ * finest grid, 4 transposed sweep on the finest grid, 5 multigrid residual, 6 node-block
+ * diagonal, 7 velocity coupling, 8 grid transfers, 9 coarsest solve, 10 Krylov
+ * multi-dot, 11 Krylov multi-axpy, 12 other vector kernels, 13 preconditioner setup,
+ * 14 smoothing sweeps on coarser levels; returns the number of classes (15) or an error
+ * code. */
 int    nc_set_timing(nc_ctx* ctx, int enable);
-int    nc_get_timing(nc_ctx* ctx, double* ms, long* counts, int n);
+int    nc_get_timing(nc_ctx* ctx, double* ms, long* counts, double* bytes, int n);
 
 /* Stand-alone cone filter on an nx*ny*nz element grid (y = F_R x, or F_R^T x when
  * transpose != 0); used to build filtered designs.  Enqueued on stream. */

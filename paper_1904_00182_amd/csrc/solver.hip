@@ -98,9 +98,11 @@ struct nc_ctx {
   bool timing;
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_class;
+  std::vector<double> ev_bytes;
   int ev_used;
   double t_ms[TC_COUNT];
   long t_cnt[TC_COUNT];
+  double t_bytes[TC_COUNT];   // algorithmic bytes moved by the timed launches
 };
 
 namespace {
@@ -114,25 +116,32 @@ void timing_flush(nc_ctx* c) {
     ck(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
     c->t_ms[c->ev_class[k]] += ms;
     c->t_cnt[c->ev_class[k]] += 1;
+    c->t_bytes[c->ev_class[k]] += c->ev_bytes[k];
   }
   c->ev_used = 0;
 }
 
-// RAII bracket around the launches of one kernel class
+// RAII bracket around the launches of one kernel class; `bytes`: the algorithmic bytes
+// the launches must move (inputs read once, outputs written once)
 struct Timed {
   nc_ctx* c;
   int k;
-  Timed(nc_ctx* ctx, int cls) : c(ctx), k(-1) {
+  Timed(nc_ctx* ctx, int cls, double bytes = 0.0) : c(ctx), k(-1) {
     if (!c->timing) return;
     if (c->ev_used == TIMER_EVENTS / 2) timing_flush(c);
     k = c->ev_used++;
     c->ev_class[k] = cls;
+    c->ev_bytes[k] = bytes;
     ck(hipEventRecord(c->ev[2 * k], c->stream));
   }
   ~Timed() {
     if (k >= 0) (void)hipEventRecord(c->ev[2 * k + 1], c->stream);
   }
 };
+
+// node and element counts of a level, for the byte counts of timed launches
+double nn(const Grid& g) { return (double)(g.nx + 1) * (g.ny + 1) * (g.nz + 1); }
+double ne(const Grid& g) { return (double)g.nx * g.ny * g.nz; }
 
 // ------------------------------------------------------------------ setup helpers
 bool valid_problem(const nc_problem* p) {
@@ -277,31 +286,31 @@ void vcycle(nc_ctx* c, int l, bool tr) {
   LevelView<T> v = view<T>(c, l);
   if (l == c->L - 1) {
     if (c->dense) {
-      Timed tm(c, TC_COARSE);
+      Timed tm(c, TC_COARSE, (double)sizeof(T) * ((double)c->ncoarse * c->ncoarse + 2.0 * c->ncoarse));
       launch_dense_apply<T>(st, c->A, c->ncoarse, tr, (const T*)L.b, (T*)L.x);
     } else {
-      { Timed tm(c, TC_TRANSFER); launch_diag_scale<T>(st, L.g, (const T*)L.dinv, tr, om, (const T*)L.b, (T*)L.x); }
+      { Timed tm(c, TC_TRANSFER, sizeof(T) * 8 * nn(L.g)); launch_diag_scale<T>(st, L.g, (const T*)L.dinv, tr, om, (const T*)L.b, (T*)L.x); }
       for (int s = 1; s < 8; ++s) {
-        Timed tm(c, l == 0 ? (tr ? TC_SMOOTH_T : TC_SMOOTH) : TC_SMOOTH_COARSE);
+        Timed tm(c, l == 0 ? (tr ? TC_SMOOTH_T : TC_SMOOTH) : TC_SMOOTH_COARSE, sizeof(T) * (12 * nn(L.g) + 2 * ne(L.g)));
         launch_pt_apply<T>(st, v, tr, MODE_SMOOTH, (const T*)L.x, (const T*)L.b, (T*)L.x2, om, l == 0);
         std::swap(L.x, L.x2);
       }
     }
     return;
   }
-  { Timed tm(c, TC_TRANSFER); launch_diag_scale<T>(st, L.g, (const T*)L.dinv, tr, om, (const T*)L.b, (T*)L.x); }
+  { Timed tm(c, TC_TRANSFER, sizeof(T) * 8 * nn(L.g)); launch_diag_scale<T>(st, L.g, (const T*)L.dinv, tr, om, (const T*)L.b, (T*)L.x); }
   for (int s = 1; s < c->p.smooth_pre; ++s) {
-    Timed tm(c, l == 0 ? (tr ? TC_SMOOTH_T : TC_SMOOTH) : TC_SMOOTH_COARSE);
+    Timed tm(c, l == 0 ? (tr ? TC_SMOOTH_T : TC_SMOOTH) : TC_SMOOTH_COARSE, sizeof(T) * (12 * nn(L.g) + 2 * ne(L.g)));
     launch_pt_apply<T>(st, v, tr, MODE_SMOOTH, (const T*)L.x, (const T*)L.b, (T*)L.x2, om, l == 0);
     std::swap(L.x, L.x2);
   }
-  { Timed tm(c, TC_PT_RESID); launch_pt_apply<T>(st, v, tr, MODE_RESID, (const T*)L.x, (const T*)L.b, (T*)L.r, om, l == 0); }
+  { Timed tm(c, TC_PT_RESID, sizeof(T) * (8 * nn(L.g) + 2 * ne(L.g))); launch_pt_apply<T>(st, v, tr, MODE_RESID, (const T*)L.x, (const T*)L.b, (T*)L.r, om, l == 0); }
   Level& C = c->lev[l + 1];
-  { Timed tm(c, TC_TRANSFER); launch_restrict<T>(st, L.g, C.g, (const T*)L.r, (T*)C.b); }
+  { Timed tm(c, TC_TRANSFER, sizeof(T) * 2 * (nn(L.g) + nn(C.g))); launch_restrict<T>(st, L.g, C.g, (const T*)L.r, (T*)C.b); }
   vcycle<T>(c, l + 1, tr);
-  { Timed tm(c, TC_TRANSFER); launch_prolong_add<T>(st, L.g, C.g, (const T*)C.x, (T*)L.x); }
+  { Timed tm(c, TC_TRANSFER, sizeof(T) * (4 * nn(L.g) + 2 * nn(C.g))); launch_prolong_add<T>(st, L.g, C.g, (const T*)C.x, (T*)L.x); }
   for (int s = 0; s < c->p.smooth_post; ++s) {
-    Timed tm(c, l == 0 ? (tr ? TC_SMOOTH_T : TC_SMOOTH) : TC_SMOOTH_COARSE);
+    Timed tm(c, l == 0 ? (tr ? TC_SMOOTH_T : TC_SMOOTH) : TC_SMOOTH_COARSE, sizeof(T) * (12 * nn(L.g) + 2 * ne(L.g)));
     launch_pt_apply<T>(st, v, tr, MODE_SMOOTH, (const T*)L.x, (const T*)L.b, (T*)L.x2, om, l == 0);
     std::swap(L.x, L.x2);
   }
@@ -316,19 +325,19 @@ void precondition(nc_ctx* c, bool tr, const T* r5, T* z5, const Scale5<T>* rows)
   Level& L0 = c->lev[0];
   LevelView<T> v0 = view<T>(c, 0);
   if (!tr) {
-    { Timed tm(c, TC_VECTOR); launch_extract_pt<T>(st, L0.g, r5, (T*)L0.b, rows); }
+    { Timed tm(c, TC_VECTOR, sizeof(T) * 4 * nn(L0.g)); launch_extract_pt<T>(st, L0.g, r5, (T*)L0.b, rows); }
     vcycle<T>(c, 0, false);
-    { Timed tm(c, TC_UPROJ); launch_uproj<T>(st, v0, (const T*)L0.x, r5, z5, rows); }
+    { Timed tm(c, TC_UPROJ, sizeof(T) * (12 * nn(L0.g) + ne(L0.g))); launch_uproj<T>(st, v0, (const T*)L0.x, r5, z5, rows); }
   } else {
-    { Timed tm(c, TC_UPROJ); launch_uprojT<T>(st, v0, r5, (T*)L0.b, z5, rows); }
+    { Timed tm(c, TC_UPROJ, sizeof(T) * (12 * nn(L0.g) + ne(L0.g))); launch_uprojT<T>(st, v0, r5, (T*)L0.b, z5, rows); }
     vcycle<T>(c, 0, true);
-    { Timed tm(c, TC_VECTOR); launch_scatter_pt<T>(st, L0.g, (const T*)L0.x, r5, z5, rows); }
+    { Timed tm(c, TC_VECTOR, sizeof(T) * 4 * nn(L0.g)); launch_scatter_pt<T>(st, L0.g, (const T*)L0.x, r5, z5, rows); }
   }
 }
 
 template <typename T>
 void apply_op(nc_ctx* c, bool tr, const T* x, T* y, const Scale5<T>* rows) {
-  Timed tm(c, tr ? TC_JTW5 : TC_JV5);
+  Timed tm(c, tr ? TC_JTW5 : TC_JV5, sizeof(T) * (12 * nn(c->lev[0].g) + 2 * ne(c->lev[0].g)));
   if (!tr) launch_jv5<T>(c->stream, view<T>(c, 0), x, y, rows);
   else launch_jtw5<T>(c->stream, view<T>(c, 0), x, y, rows);
 }
@@ -388,16 +397,16 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
       apply_op<T>(c, tr, zj, w, rows);
       // classical Gram-Schmidt, repeated only when the projection removed most of w
       // ("twice is enough" criterion of Kahan and Parlett)
-      { Timed tm(c, TC_MDOT); launch_mdot<T>(st, V, ld, j + 1, w, n, c->part, dres, true); }
-      { Timed tm(c, TC_MAXPY); launch_maxpy<T>(st, V, ld, j + 1, dres, -1.0, w, n, c->part, dres + 2 * MAXC); }
+      { Timed tm(c, TC_MDOT, sizeof(T) * (double)(j + 2) * n); launch_mdot<T>(st, V, ld, j + 1, w, n, c->part, dres, true); }
+      { Timed tm(c, TC_MAXPY, sizeof(T) * (double)(j + 3) * n); launch_maxpy<T>(st, V, ld, j + 1, dres, -1.0, w, n, c->part, dres + 2 * MAXC); }
       fetch(c, dres, 2 * MAXC + 1);
       double hsum[MAXC];
       for (int i = 0; i <= j; ++i) hsum[i] = c->hbuf[i];
       const double wn0 = std::sqrt(std::max(c->hbuf[j + 1], 0.0));
       double hn = c->hbuf[2 * MAXC];
       if (hn < 0.7 * wn0) {
-        { Timed tm(c, TC_MDOT); launch_mdot<T>(st, V, ld, j + 1, w, n, c->part, dres + MAXC, false); }
-        { Timed tm(c, TC_MAXPY); launch_maxpy<T>(st, V, ld, j + 1, dres + MAXC, -1.0, w, n, c->part, dres + 2 * MAXC); }
+        { Timed tm(c, TC_MDOT, sizeof(T) * (double)(j + 2) * n); launch_mdot<T>(st, V, ld, j + 1, w, n, c->part, dres + MAXC, false); }
+        { Timed tm(c, TC_MAXPY, sizeof(T) * (double)(j + 3) * n); launch_maxpy<T>(st, V, ld, j + 1, dres + MAXC, -1.0, w, n, c->part, dres + 2 * MAXC); }
         fetch(c, dres + MAXC, MAXC + 1);   // second projection and the final norm (dres[2 MAXC])
         for (int i = 0; i <= j; ++i) hsum[i] += c->hbuf[i];
         hn = c->hbuf[MAXC];
@@ -538,28 +547,38 @@ int newton(nc_ctx* c, double* s, nc_info* info) {
     if (it == 1) first_its = its;
     if (it >= 2 && its > 2 * first_its + 4) c->hier_valid = false;
     kits += its;
-    // d solves J d = R; the Newton step is -d
+    // d solves J d = R; the Newton step is -d.  Per-field size of the step relative to
+    // the state, taken before the line search.
+    launch_field_norms(st, c->d, s, c->N, c->part, c->dres);
+    fetch(c, c->dres, 10);
+    double step = 0.0, step_pt = 0.0;
+    for (int f = 0; f < 5; ++f) {
+      const double sf = c->hbuf[5 + f], df = c->hbuf[f];
+      const double r = sf > 0 ? df / sf : (df > 0 ? 1.0 : 0.0);
+      step = std::max(step, r);
+      if (f >= 3) step_pt = std::max(step_pt, r);
+    }
+    // a step this small in (P, T) is at the round-off level of the root, where the
+    // residual norm is noise and no longer orders the iterates: it is taken in full
+    const bool tiny = step_pt <= 1e3 * p.newton_step_rtol && relres <= 10.0 * lin_rtol;
     double lam = 1.0, rt = 0.0;
     while (true) {
       launch_axpy(st, -lam, c->d, s, c->strial, c->n5);
-      { Timed tm(c, TC_RESIDUAL); launch_residual(st, L0.g, L0.c64, c->patch, L0.coef64, c->strial, c->tmp5); }
+      { Timed tm(c, TC_RESIDUAL, 8.0 * (10 * nn(L0.g) + 2 * ne(L0.g))); launch_residual(st, L0.g, L0.c64, c->patch, L0.coef64, c->strial, c->tmp5); }
       rt = scaled_norm(c, c->tmp5);
       if (!std::isfinite(rt)) return NC_ENAN;
-      if (rt <= rn || rt <= floor || lam < 1.0 / 64) break;
+      if (rt <= rn || rt <= floor || tiny || lam < 1.0 / 64) break;
       lam *= 0.5;
     }
     ck(hipMemcpyAsync(s, c->strial, sizeof(double) * c->n5, hipMemcpyDeviceToDevice, st));
     std::swap(c->R, c->tmp5);
+    const double rn_prev = rn;
     rn = rt;
-    launch_field_norms(st, c->d, s, c->N, c->part, c->dres);
-    fetch(c, c->dres, 10);
-    double step = 0.0;
-    for (int f = 0; f < 5; ++f) {
-      const double sf = c->hbuf[5 + f];
-      const double df = lam * c->hbuf[f];
-      step = std::max(step, sf > 0 ? df / sf : (df > 0 ? 1.0 : 0.0));
-    }
-    if (lam == 1.0 && (step <= p.newton_step_rtol || rn <= floor)) {
+    // converged: a full step below the step tolerance in every field, a residual at the
+    // floor, or a tiny (P, T) step that no longer halves the residual (the iteration has
+    // stagnated at the float64 round-off of the root; the velocity rows, a small
+    // difference of large pressure and buoyancy terms, sit above the step tolerance there)
+    if (lam == 1.0 && (step <= p.newton_step_rtol || rn <= floor || (tiny && rn > 0.5 * rn_prev))) {
       status = NC_OK;
       ++it;
       break;
@@ -863,23 +882,25 @@ int nc_set_timing(nc_ctx* c, int enable) {
     if (enable && c->ev.empty()) {
       c->ev.resize(TIMER_EVENTS);
       c->ev_class.resize(TIMER_EVENTS / 2);
+      c->ev_bytes.resize(TIMER_EVENTS / 2);
       for (auto& e : c->ev) ck(hipEventCreate(&e));
     }
     if (c->timing) timing_flush(c);
     c->timing = enable != 0 && !c->ev.empty();
     c->ev_used = 0;
-    for (int k = 0; k < TC_COUNT; ++k) { c->t_ms[k] = 0.0; c->t_cnt[k] = 0; }
+    for (int k = 0; k < TC_COUNT; ++k) { c->t_ms[k] = 0.0; c->t_cnt[k] = 0; c->t_bytes[k] = 0.0; }
     return NC_OK;
   });
 }
 
-int nc_get_timing(nc_ctx* c, double* ms, long* counts, int n) {
+int nc_get_timing(nc_ctx* c, double* ms, long* counts, double* bytes, int n) {
   if (!c || !ms || !counts || n < 1) return NC_EINVAL;
   return guarded([&]() {
     timing_flush(c);
     for (int k = 0; k < n; ++k) {
       ms[k] = k < TC_COUNT ? c->t_ms[k] : 0.0;
       counts[k] = k < TC_COUNT ? c->t_cnt[k] : 0;
+      if (bytes) bytes[k] = k < TC_COUNT ? c->t_bytes[k] : 0.0;
     }
     return TC_COUNT;
   });

@@ -94,7 +94,7 @@ def load():
             "nc_sensitivity": (I, [V, V, V, V, V]),
             "nc_cone_filter": (I, [I, I, I, D, V, V, I, V]),
             "nc_set_timing": (I, [V, I]),
-            "nc_get_timing": (I, [V, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long), I]),
+            "nc_get_timing": (I, [V, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D), I]),
         }
         for name, (res, argt) in sig.items():
             f = getattr(lib, name)
@@ -247,14 +247,18 @@ class Solver:
     def set_timing(self, enable=True):
         _check(self.lib.nc_set_timing(self.ctx, 1 if enable else 0), "nc_set_timing")
 
-    def timing(self):
-        """{class: (total ms, launches)} of the kernels timed since set_timing(True)."""
+    def timing(self, with_bytes=False):
+        """{class: (total ms, launches)} of the kernels timed since set_timing(True); with
+        `with_bytes`, {class: (total ms, launches, algorithmic bytes)}."""
         n = len(TIMER_CLASSES)
         ms = (ctypes.c_double * n)()
         cnt = (ctypes.c_long * n)()
-        r = self.lib.nc_get_timing(self.ctx, ms, cnt, n)
+        by = (ctypes.c_double * n)()
+        r = self.lib.nc_get_timing(self.ctx, ms, cnt, by, n)
         if r < 0:
             raise NCError(r, "nc_get_timing")
+        if with_bytes:
+            return {TIMER_CLASSES[k]: (ms[k], cnt[k], by[k]) for k in range(n)}
         return {TIMER_CLASSES[k]: (ms[k], cnt[k]) for k in range(n)}
 
     def sensitivity(self, s, lam, with_gamma=False):
