@@ -31,14 +31,14 @@ VALU_PEAK_TFLOPS = {4: 157.3, 8: 78.6}     # MI355X vector peaks, float32 and fl
 # linearisation (279) plus the element apply, and the node-level assembly and finishing.
 # The element figures are counted on the element code by tests/native/flop_count.cpp
 # (checked by tests/test_flop_count.py).
-FLOPS_PER_ELEM = {"jv5": 279 + 711, "jtw5": 279 + 758, "smooth": 279 + 524, "smooth_T": 279 + 593,
+FLOPS_PER_ELEM = {"jv": 279 + 524, "jtw": 279 + 593, "smooth": 279 + 524, "smooth_T": 279 + 593,
                   "pt_residual": 279 + 524}
-FLOPS_PER_NODE = {"jv5": 47, "jtw5": 23, "smooth": 26, "smooth_T": 26, "pt_residual": 16}
+FLOPS_PER_NODE = {"jv": 16, "jtw": 16, "smooth": 26, "smooth_T": 26, "pt_residual": 16}
 
 # kernel symbol of each timed class (tile template arguments elided)
 KERNEL_NAMES = {
-    "jv5": "zmarch_kernel<JvOp<{t},5,0>,..> (five-field J v)",
-    "jtw5": "zmarch_kernel<JtwOp<{t},5,0>,..> (five-field J^T w)",
+    "jv": "zmarch_kernel<JvOp<{t},2,0>,..,1> (Krylov operator: (P, T) block of J)",
+    "jtw": "zmarch_kernel<JtwOp<{t},2,0>,..,1> (Krylov operator: (P, T) block of J^T)",
     "smooth": "zmarch_kernel<JvOp<{t},2,2>,..,1> (finest-grid block-Jacobi sweep)",
     "smooth_T": "zmarch_kernel<JtwOp<{t},2,2>,..,1> (finest-grid transposed block-Jacobi sweep)",
     "smooth_coarse": "zmarch_kernel<JvOp/JtwOp<{t},2,2>,..,0> (block-Jacobi sweeps, coarse levels)",

@@ -153,7 +153,7 @@ int    nc_sensitivity(nc_ctx* ctx, const double* s_dev, const double* lam_dev, d
  * nc_get_timing synchronises, then fills ms[k] (summed milliseconds), counts[k]
  * (launches) and, when bytes is non-NULL, bytes[k] (the algorithmic bytes of those
  * launches: every input read once, every output written once) for k < n over the kernel
- * classes 0 residual, 1 five-field J v, 2 five-field J^T w, 3 smoothing sweep on the
+ * classes 0 residual, 1 J v and 2 J^T w of the (P, T) Krylov solve, 3 smoothing sweep on the
  * finest grid, 4 transposed sweep on the finest grid, 5 multigrid residual, 6 node-block
  * diagonal, 7 velocity coupling, 8 grid transfers, 9 coarsest solve, 10 Krylov
  * multi-dot, 11 Krylov multi-axpy, 12 other vector kernels, 13 preconditioner setup,

@@ -111,14 +111,20 @@ static void run_zmarch_t(hipStream_t st, const Op& op) {
   const Grid& g = op.g;
   const int tiles_x = ceil_div(g.nx + 1, TX - 1);
   const int tiles_y = ceil_div(g.ny + 1, TY - 1);
-  // z chunks: about `target` workgroups over the device (NC_ZBLOCKS overrides), at least
-  // 4 node planes per chunk
+  // z chunks: about `target` workgroups over the device (NC_ZBLOCKS overrides) with at
+  // least `kzmin` node planes per chunk (NC_KZMIN overrides).  A thread's serial work is
+  // KZ + 1 element layers, so short chunks cut the latency of launches on small grids at
+  // the price of recomputing more halo layers.
   static const int target = [] {
     const char* e = std::getenv("NC_ZBLOCKS");
     return e ? std::max(1, std::atoi(e)) : 1024;
   }();
+  static const int kzmin = [] {
+    const char* e = std::getenv("NC_KZMIN");
+    return e ? std::max(1, std::atoi(e)) : 1;
+  }();
   const int want = std::max(1, target * 256 / (TX * TY) / std::max(1, tiles_x * tiles_y));
-  const int KZ = std::max(4, ceil_div(g.nz + 1, want));
+  const int KZ = std::max(kzmin, ceil_div(g.nz + 1, want));
   const int chunks = ceil_div(g.nz + 1, KZ);
   dim3 grid(tiles_x, tiles_y, chunks), block(TX, TY, 1);
   hipLaunchKernelGGL((zmarch_kernel<Op, TX, TY, FINE>), grid, block, 0, st, op, KZ);
@@ -238,8 +244,8 @@ struct JvOp {
       for (int d = 0; d < 3; ++d) y[5 * n + d] = rs.s[d] * (v[d] + M * x[5 * n + d]);
     }
     if (MODE == MODE_STORE) {
-      y[NF * n + NF - 2] = NF == 5 ? rs.s[3] * ap : ap;
-      y[NF * n + NF - 1] = NF == 5 ? rs.s[4] * at : at;
+      y[NF * n + NF - 2] = rs.s[3] * ap;
+      y[NF * n + NF - 1] = rs.s[4] * at;
     } else {
       const T rp = b[2 * n] - ap, rt = b[2 * n + 1] - at;
       if (MODE == MODE_RESID) {
@@ -308,8 +314,8 @@ struct JtwOp {
       for (int d = 0; d < 3; ++d) y[5 * n + d] = rs.s[d] * M * x[5 * n + d];
     }
     if (MODE == MODE_STORE) {
-      y[NF * n + NF - 2] = NF == 5 ? rs.s[3] * ap : ap;
-      y[NF * n + NF - 1] = NF == 5 ? rs.s[4] * at : at;
+      y[NF * n + NF - 2] = rs.s[3] * ap;
+      y[NF * n + NF - 1] = rs.s[4] * at;
     } else {
       const T rp = b[2 * n] - ap, rt = b[2 * n + 1] - at;
       if (MODE == MODE_RESID) {
@@ -338,6 +344,19 @@ template <typename T>
 void launch_jtw5(hipStream_t st, const LevelView<T>& L, const T* w, T* y, const Scale5<T>* rows) {
   JtwOp<T, 5, MODE_STORE> op{L.g, L.c, L.coef, L.st, w, nullptr, nullptr, y, (T)0, ones_or(rows)};
   run_zmarch(st, op);
+}
+
+// y = D J_PT x (J_PT^T when transposed) on the finest grid: the (P, T) block of the
+// Jacobian, constrained rows and columns the identity, rows scaled by rows->s[3], s[4]
+template <typename T>
+void launch_pt_store(hipStream_t st, const LevelView<T>& L, bool transpose, const T* x, T* y, const Scale5<T>* rows) {
+  if (!transpose) {
+    JvOp<T, 2, MODE_STORE> op{L.g, L.c, L.coef, L.st, x, nullptr, nullptr, y, (T)0, ones_or(rows)};
+    run_zmarch<JvOp<T, 2, MODE_STORE>, 1>(st, op);
+  } else {
+    JtwOp<T, 2, MODE_STORE> op{L.g, L.c, L.coef, L.st, x, nullptr, nullptr, y, (T)0, ones_or(rows)};
+    run_zmarch<JtwOp<T, 2, MODE_STORE>, 1>(st, op);
+  }
 }
 
 template <typename T>
@@ -504,6 +523,7 @@ void launch_uprojT(hipStream_t st, const LevelView<T>& L, const T* r5, T* b_pt, 
   template void launch_jv5<T>(hipStream_t, const LevelView<T>&, const T*, T*, const Scale5<T>*);    \
   template void launch_jtw5<T>(hipStream_t, const LevelView<T>&, const T*, T*, const Scale5<T>*);   \
   template void launch_pt_apply<T>(hipStream_t, const LevelView<T>&, bool, int, const T*, const T*, T*, T, bool); \
+  template void launch_pt_store<T>(hipStream_t, const LevelView<T>&, bool, const T*, T*, const Scale5<T>*);       \
   template void launch_diag_inverse<T>(hipStream_t, const LevelView<T>&, T*);                       \
   template void launch_uproj<T>(hipStream_t, const LevelView<T>&, const T*, const T*, T*, const Scale5<T>*); \
   template void launch_uprojT<T>(hipStream_t, const LevelView<T>&, const T*, T*, T*, const Scale5<T>*);

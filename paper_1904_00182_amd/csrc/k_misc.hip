@@ -14,15 +14,36 @@ static inline int blocks_for(long n, int bs = BS) {
 }
 
 // ------------------------------------------------------------------ transfers
+// Node kernels run on a 2-D grid: blockIdx.y is the node plane k, the x dimension covers
+// the (nx+1)(ny+1) nodes of the plane (one 32-bit division per thread).
+struct PlaneIdx {
+  int i, j, k;
+  bool ok;
+};
+__device__ inline PlaneIdx plane_idx(const Grid& g) {
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int row = g.nx + 1;
+  PlaneIdx r;
+  r.k = (int)blockIdx.y;
+  r.j = p / row;
+  r.i = p - r.j * row;
+  r.ok = r.j <= g.ny;
+  return r;
+}
+static inline dim3 plane_grid(const Grid& g, int bs) {
+  return dim3((unsigned)ceil_div((long)(g.nx + 1) * (g.ny + 1), bs), (unsigned)(g.nz + 1));
+}
+
 // Restriction by the transpose of trilinear prolongation (full weighting with weights
-// 1, 1/2, 1/4, 1/8), constrained coarse dofs set to zero.  One thread per coarse node.
+// 1, 1/2, 1/4, 1/8), constrained coarse dofs set to zero; one thread per coarse node.
+// With dinv, also the first damped block-Jacobi step of the coarse level from a zero
+// guess, x = omega D^-1 b (D^-T b when transposed).
 template <typename T>
-__global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf, T* __restrict__ bc) {
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= coarse.nodes()) return;
-  const int I = (int)(n % (coarse.nx + 1));
-  const int J = (int)((n / (coarse.nx + 1)) % (coarse.ny + 1));
-  const int K = (int)(n / ((long)(coarse.nx + 1) * (coarse.ny + 1)));
+__global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf, T* __restrict__ bc,
+                                const T* __restrict__ dinv, int transpose, T omega, T* __restrict__ xc) {
+  const PlaneIdx q = plane_idx(coarse);
+  if (!q.ok) return;
+  const int I = q.i, J = q.j, K = q.k;
   double sp = 0.0, stt = 0.0;
   for (int dk = -1; dk <= 1; ++dk) {
     const int k = 2 * K + dk;
@@ -36,36 +57,42 @@ __global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf
         const int i = 2 * I + di;
         if (i < 0 || i > fine.nx) continue;
         const double w = wj * (di == 0 ? 1.0 : 0.5);
-        const long m = fine.node(i, j, k);
+        const int m = fine.node(i, j, k);
         sp += w * (double)rf[2 * m];
         stt += w * (double)rf[2 * m + 1];
       }
     }
   }
-  bc[2 * n] = coarse.pfix(I, J, K) ? (T)0 : (T)sp;
-  bc[2 * n + 1] = coarse.tfix(I, J, K) ? (T)0 : (T)stt;
+  const int n = coarse.node(I, J, K);
+  const T bp = coarse.pfix(I, J, K) ? (T)0 : (T)sp;
+  const T bt = coarse.tfix(I, J, K) ? (T)0 : (T)stt;
+  bc[2 * n] = bp;
+  bc[2 * n + 1] = bt;
+  if (dinv) {
+    const T* D = dinv + 4 * n;
+    xc[2 * n] = omega * (D[0] * bp + D[transpose ? 2 : 1] * bt);
+    xc[2 * n + 1] = omega * (D[transpose ? 1 : 2] * bp + D[3] * bt);
+  }
 }
 
 // Trilinear prolongation added to the fine iterate; one thread per fine node.
 template <typename T>
 __global__ void prolong_kernel(Grid fine, Grid coarse, const T* __restrict__ xc, T* __restrict__ xf) {
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= fine.nodes()) return;
-  const int i = (int)(n % (fine.nx + 1));
-  const int j = (int)((n / (fine.nx + 1)) % (fine.ny + 1));
-  const int k = (int)(n / ((long)(fine.nx + 1) * (fine.ny + 1)));
+  const PlaneIdx q = plane_idx(fine);
+  if (!q.ok) return;
+  const int i = q.i, j = q.j, k = q.k;
   const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
-  const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0, wk = (k & 1) ? 0.5 : 1.0;
+  const double w = ((i & 1) ? 0.5 : 1.0) * ((j & 1) ? 0.5 : 1.0) * ((k & 1) ? 0.5 : 1.0);
   double sp = 0.0, stt = 0.0;
   const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
   for (int c = 0; c < nk; ++c)
     for (int b = 0; b < nj; ++b)
       for (int a = 0; a < ni; ++a) {
-        const long m = coarse.node(a ? i1 : i0, b ? j1 : j0, c ? k1 : k0);
-        const double w = wi * wj * wk;
+        const int m = coarse.node(a ? i1 : i0, b ? j1 : j0, c ? k1 : k0);
         sp += w * (double)xc[2 * m];
         stt += w * (double)xc[2 * m + 1];
       }
+  const int n = fine.node(i, j, k);
   if (!fine.pfix(i, j, k)) xf[2 * n] += (T)sp;
   if (!fine.tfix(i, j, k)) xf[2 * n + 1] += (T)stt;
 }
@@ -100,12 +127,14 @@ __global__ void average_coef_kernel(Grid fine, Grid coarse, const T* __restrict_
 }
 
 template <typename T>
-void launch_restrict(hipStream_t st, const Grid& fine, const Grid& coarse, const T* rf, T* bc) {
-  hipLaunchKernelGGL(restrict_kernel<T>, dim3(blocks_for(coarse.nodes())), dim3(BS), 0, st, fine, coarse, rf, bc);
+void launch_restrict(hipStream_t st, const Grid& fine, const Grid& coarse, const T* rf, T* bc, const T* dinv,
+                     bool transpose, T omega, T* xc) {
+  hipLaunchKernelGGL(restrict_kernel<T>, plane_grid(coarse, 128), dim3(128), 0, st, fine, coarse, rf, bc, dinv,
+                     transpose ? 1 : 0, omega, xc);
 }
 template <typename T>
 void launch_prolong_add(hipStream_t st, const Grid& fine, const Grid& coarse, const T* xc, T* xf) {
-  hipLaunchKernelGGL(prolong_kernel<T>, dim3(blocks_for(fine.nodes())), dim3(BS), 0, st, fine, coarse, xc, xf);
+  hipLaunchKernelGGL(prolong_kernel<T>, plane_grid(fine, 256), dim3(256), 0, st, fine, coarse, xc, xf);
 }
 template <typename T>
 void launch_inject_state(hipStream_t st, const Grid& fine, const Grid& coarse, const T* sf, T* sc) {
@@ -237,12 +266,13 @@ __global__ __launch_bounds__(GJ_THREADS) void gauss_jordan_kernel(double* __rest
     }
     for (int r = tid; r < n; r += GJ_THREADS) fcol[r] = (r == k) ? 0.0 : A[(long)r * n + k];
     __syncthreads();
-    const long nn = (long)n * n;
-    for (long t = tid; t < nn; t += GJ_THREADS) {
-      const int r = (int)(t / n), c = (int)(t % n);
+    // rows over waves, columns over lanes
+    for (int r = tid >> 6; r < n; r += GJ_THREADS / 64) {
       if (r == k) continue;
-      const double base = (c == k) ? 0.0 : A[t];
-      A[t] = base - fcol[r] * A[(long)k * n + c];
+      const double f = fcol[r];
+      double* Ar = A + (long)r * n;
+      const double* Ak = A + (long)k * n;
+      for (int c = tid & 63; c < n; c += 64) Ar[c] = (c == k ? 0.0 : Ar[c]) - f * Ak[c];
     }
     __syncthreads();
   }
@@ -260,8 +290,129 @@ __global__ __launch_bounds__(GJ_THREADS) void gauss_jordan_kernel(double* __rest
   }
 }
 
+// The same inversion with the matrix held in registers, for n <= GJS_NMAX: row r belongs
+// to wave r % 16 (slot r / 16), column c to lane c % 64 (slot c / 64).  Each step puts the
+// pivot column and the old rows k and p in LDS; every thread then updates its entries with
+// the operations of gauss_jordan_kernel, in the same order.  The row interchanges are
+// undone as one column permutation when the result is written back.
+constexpr int GJS_QR = 10, GJS_QC = 3, GJS_NMAX = 16 * GJS_QR;   // 64 * GJS_QC >= GJS_NMAX
+__global__ __launch_bounds__(1024) void gauss_jordan_small_kernel(double* __restrict__ A, int n, int* __restrict__ perm) {
+  __shared__ double colk[GJS_NMAX];
+  __shared__ double pivrow[64 * GJS_QC];
+  __shared__ double oldk[64 * GJS_QC];
+  __shared__ int sperm[GJS_NMAX];
+  __shared__ int sidx[GJS_NMAX];
+  __shared__ int sinv[GJS_NMAX];
+  __shared__ int spiv;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double a[GJS_QR][GJS_QC];
+#pragma unroll
+  for (int i = 0; i < GJS_QR; ++i)
+#pragma unroll
+    for (int j = 0; j < GJS_QC; ++j) {
+      const int r = w + 16 * i, c = lane + 64 * j;
+      a[i][j] = (r < n && c < n) ? A[(long)r * n + c] : 0.0;
+    }
+  for (int k = 0; k < n; ++k) {
+    const int jk = k >> 6;
+    if (lane == (k & 63)) {
+#pragma unroll
+      for (int i = 0; i < GJS_QR; ++i) {
+        const int r = w + 16 * i;
+#pragma unroll
+        for (int j = 0; j < GJS_QC; ++j)
+          if (j == jk && r < n) colk[r] = a[i][j];
+      }
+    }
+    __syncthreads();
+    if (w == 0) {
+      double best = -1.0;
+      int bi = k;
+      for (int r = k + lane; r < n; r += 64) {
+        const double v = fabs(colk[r]);
+        if (v > best) { best = v; bi = r; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_down(best, off, 64);
+        const int oi = __shfl_down(bi, off, 64);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if (lane == 0) { spiv = bi; sperm[k] = bi; perm[k] = bi; }
+    }
+    __syncthreads();
+    const int p = spiv;
+    if (w == (p & 15) || w == (k & 15)) {
+#pragma unroll
+      for (int i = 0; i < GJS_QR; ++i) {
+        const int r = w + 16 * i;
+#pragma unroll
+        for (int j = 0; j < GJS_QC; ++j) {
+          if (r == p) pivrow[lane + 64 * j] = a[i][j];
+          if (r == k) oldk[lane + 64 * j] = a[i][j];
+        }
+      }
+    }
+    __syncthreads();
+    const double ipv = 1.0 / pivrow[k];
+    const double fk = oldk[k];
+    double pr[GJS_QC];
+#pragma unroll
+    for (int j = 0; j < GJS_QC; ++j) {
+      const int c = lane + 64 * j;
+      pr[j] = c < n ? (c == k ? 1.0 : pivrow[c]) * ipv : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < GJS_QR; ++i) {
+      const int r = w + 16 * i;
+      const double fr = r < n ? colk[r] : 0.0;
+#pragma unroll
+      for (int j = 0; j < GJS_QC; ++j) {
+        const int c = lane + 64 * j;
+        a[i][j] = (c == k ? 0.0 : a[i][j]) - fr * pr[j];
+      }
+    }
+    // rows k and p: the scaled pivot row, and the old row k eliminated in row p's place
+    if (w == (p & 15) || w == (k & 15)) {
+#pragma unroll
+      for (int i = 0; i < GJS_QR; ++i) {
+        const int r = w + 16 * i;
+#pragma unroll
+        for (int j = 0; j < GJS_QC; ++j) {
+          const int c = lane + 64 * j;
+          if (r == k) a[i][j] = pr[j];
+          else if (r == p) a[i][j] = (c == k ? 0.0 : oldk[c]) - fk * pr[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // column permutation undoing the interchanges in reverse order: result column j is
+  // column sidx[j] of the eliminated matrix
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < n; ++j) sidx[j] = j;
+    for (int k = n - 1; k >= 0; --k) {
+      const int q = sperm[k], tmp = sidx[k];
+      sidx[k] = sidx[q];
+      sidx[q] = tmp;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < n) sinv[sidx[threadIdx.x]] = threadIdx.x;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < GJS_QR; ++i)
+#pragma unroll
+    for (int j = 0; j < GJS_QC; ++j) {
+      const int r = w + 16 * i, c = lane + 64 * j;
+      if (r < n && c < n) A[(long)r * n + sinv[c]] = a[i][j];
+    }
+}
+
 void launch_gauss_jordan(hipStream_t st, double* A, int n, int* perm) {
-  hipLaunchKernelGGL(gauss_jordan_kernel, dim3(1), dim3(GJ_THREADS), sizeof(double) * n, st, A, n, perm);
+  if (n <= GJS_NMAX)
+    hipLaunchKernelGGL(gauss_jordan_small_kernel, dim3(1), dim3(1024), 0, st, A, n, perm);
+  else
+    hipLaunchKernelGGL(gauss_jordan_kernel, dim3(1), dim3(GJ_THREADS), sizeof(double) * n, st, A, n, perm);
 }
 
 // x = Ainv b (one wave per row) or x = Ainv^T b (one thread per column)
@@ -315,43 +466,65 @@ void launch_pack_state(hipStream_t st, const Grid& g, const double* s5, T* pt) {
   hipLaunchKernelGGL(pack_state_kernel<T>, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g.nodes(), s5, pt);
 }
 
+// Preconditioner input of the (P, T) Krylov solve (see kernels.hpp)
 template <typename T>
-__global__ void extract_pt_kernel(Grid g, const T* __restrict__ r5, T* __restrict__ b, T ip, T it) {
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= g.nodes()) return;
-  const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)), k = (int)(n / ((long)(g.nx + 1) * (g.ny + 1)));
-  b[2 * n] = g.pfix(i, j, k) ? (T)0 : ip * r5[5 * n + 3];
-  b[2 * n + 1] = g.tfix(i, j, k) ? (T)0 : it * r5[5 * n + 4];
+__global__ void pc_in_kernel(Grid g, const T* __restrict__ v, T inv_p, T inv_t, const T* __restrict__ dinv,
+                             int transpose, T omega, T* __restrict__ b, T* __restrict__ x) {
+  const PlaneIdx q = plane_idx(g);
+  if (!q.ok) return;
+  const int n = g.node(q.i, q.j, q.k);
+  const T bp = g.pfix(q.i, q.j, q.k) ? (T)0 : inv_p * v[2 * n];
+  const T bt = g.tfix(q.i, q.j, q.k) ? (T)0 : inv_t * v[2 * n + 1];
+  b[2 * n] = bp;
+  b[2 * n + 1] = bt;
+  const T* D = dinv + 4 * n;
+  x[2 * n] = omega * (D[0] * bp + D[transpose ? 2 : 1] * bt);
+  x[2 * n + 1] = omega * (D[transpose ? 1 : 2] * bp + D[3] * bt);
 }
 template <typename T>
-void launch_extract_pt(hipStream_t st, const Grid& g, const T* r5, T* b, const Scale5<T>* rows) {
-  const T ip = rows ? (T)1 / rows->s[3] : (T)1, it = rows ? (T)1 / rows->s[4] : (T)1;
-  hipLaunchKernelGGL(extract_pt_kernel<T>, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, r5, b, ip, it);
-}
-
-template <typename T>
-__global__ void scatter_pt_kernel(Grid g, const T* __restrict__ x, const T* __restrict__ r5, T* __restrict__ z5, T ip,
-                                  T it) {
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= g.nodes()) return;
-  const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)), k = (int)(n / ((long)(g.nx + 1) * (g.ny + 1)));
-  z5[5 * n + 3] = g.pfix(i, j, k) ? ip * r5[5 * n + 3] : x[2 * n];
-  z5[5 * n + 4] = g.tfix(i, j, k) ? it * r5[5 * n + 4] : x[2 * n + 1];
-}
-template <typename T>
-void launch_scatter_pt(hipStream_t st, const Grid& g, const T* x, const T* r5, T* z5, const Scale5<T>* rows) {
-  const T ip = rows ? (T)1 / rows->s[3] : (T)1, it = rows ? (T)1 / rows->s[4] : (T)1;
-  hipLaunchKernelGGL(scatter_pt_kernel<T>, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, x, r5, z5, ip, it);
+void launch_pc_in(hipStream_t st, const Grid& g, const T* v, T inv_p, T inv_t, const T* dinv, bool transpose,
+                  T omega, T* b, T* x) {
+  hipLaunchKernelGGL(pc_in_kernel<T>, plane_grid(g, 256), dim3(256), 0, st, g, v, inv_p, inv_t, dinv,
+                     transpose ? 1 : 0, omega, b, x);
 }
 
 template <typename T>
-__global__ void scale5_kernel(long nodes, const double* __restrict__ a, T* __restrict__ b, Scale5<double> s) {
-  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < 5 * nodes; t += (long)gridDim.x * blockDim.x)
-    b[t] = (T)(s.s[t % 5] * a[t]);
+__global__ void pack_pt_kernel(long nodes, const double* __restrict__ r5, T* __restrict__ out, double s_p, double s_t) {
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < nodes; n += (long)gridDim.x * blockDim.x) {
+    out[2 * n] = (T)(s_p * r5[5 * n + 3]);
+    out[2 * n + 1] = (T)(s_t * r5[5 * n + 4]);
+  }
 }
 template <typename T>
-void launch_scale5(hipStream_t st, long nodes, const double* a, T* b, Scale5<double> s) {
-  hipLaunchKernelGGL(scale5_kernel<T>, dim3(std::min(blocks_for(5 * nodes), 4096)), dim3(BS), 0, st, nodes, a, b, s);
+void launch_pack_pt(hipStream_t st, long nodes, const double* r5, T* out, double s_p, double s_t) {
+  hipLaunchKernelGGL(pack_pt_kernel<T>, dim3(std::min(blocks_for(nodes), 4096)), dim3(BS), 0, st, nodes, r5, out, s_p,
+                     s_t);
+}
+
+template <typename Ta, typename Tb>
+__global__ void scale2_kernel(long nodes, const Ta* __restrict__ in, Tb* __restrict__ out, double s_p, double s_t) {
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < nodes; n += (long)gridDim.x * blockDim.x) {
+    out[2 * n] = (Tb)(s_p * (double)in[2 * n]);
+    out[2 * n + 1] = (Tb)(s_t * (double)in[2 * n + 1]);
+  }
+}
+template <typename Ta, typename Tb>
+void launch_scale2(hipStream_t st, long nodes, const Ta* in, Tb* out, double s_p, double s_t) {
+  hipLaunchKernelGGL((scale2_kernel<Ta, Tb>), dim3(std::min(blocks_for(nodes), 4096)), dim3(BS), 0, st, nodes, in, out,
+                     s_p, s_t);
+}
+
+template <typename T>
+__global__ void unpack_pt_kernel(Grid g, const T* __restrict__ x, double* __restrict__ out5) {
+  const PlaneIdx q = plane_idx(g);
+  if (!q.ok) return;
+  const int n = g.node(q.i, q.j, q.k);
+  out5[5 * (long)n + 3] = g.pfix(q.i, q.j, q.k) ? 0.0 : (double)x[2 * n];
+  out5[5 * (long)n + 4] = g.tfix(q.i, q.j, q.k) ? 0.0 : (double)x[2 * n + 1];
+}
+template <typename T>
+void launch_unpack_pt(hipStream_t st, const Grid& g, const T* x, double* out5) {
+  hipLaunchKernelGGL(unpack_pt_kernel<T>, plane_grid(g, 256), dim3(256), 0, st, g, x, out5);
 }
 
 __global__ void mask_state_kernel(Grid g, double* __restrict__ s5) {
@@ -435,174 +608,264 @@ __device__ inline double hsum(double2 a, double2 b) { return a.x * b.x + a.y * b
 
 // Multi-dot and multi-axpy of the Krylov solver.
 //
-// Multi-dot: a 2-D grid, grid row c computes partial sums of V[c] . w over the blocks'
-// chunks (plain streaming dot products; w is re-read by every row and stays in the
-// last-level cache).  The last block to finish (counted with a device-wide atomic ticket
-// that it resets) adds the partials in block order, so the result is deterministic and
-// needs no second launch.  Multi-axpy: each thread updates its elements of w with all
-// the vectors (runtime count, one accumulator per element).
-constexpr int MD_BLOCKS = 256;   // blocks per vector in the multi-dot
+// Both kernels split the vectors into one contiguous chunk per block and walk it in
+// sub-tiles of KBS x KT<T>::U 16-byte vectors.  The multi-dot keeps the sub-tile of w in
+// registers and streams the basis vectors in groups of KG (KG x KT<T>::U loads in flight per
+// thread), so w and every basis vector are read once; each wave reduces its partial dot
+// products and its lane 0 adds them to the wave's own row of LDS sums (no barrier between
+// groups); the block adds the wave rows in order at the end.  Full sub-tiles take
+// unguarded vector loads, so the loads of a group are all in flight together.  A second,
+// one-block launch adds the per-block sums in block order, so results are deterministic;
+// the launch boundary makes the partials visible across the chip's L2 caches (a
+// device-scope fence per block, with the atomic ticket of a last-block scheme, costs far
+// more here).  The multi-axpy updates its sub-tile of w with all basis vectors in float64
+// and writes it back once, with the norm of the result reduced the same way.
+constexpr int KBS = 512;   // threads per block
+// 16-byte vectors per thread and sub-tile: 4096 elements per sub-tile in either precision
+template <typename T>
+struct KT {
+  static constexpr int U = sizeof(T) == 4 ? 2 : 4;
+};
+constexpr int KG = 4;      // basis vectors per group
+constexpr int KB_MAX = RED_BLOCKS / 4;   // blocks; partials of column c at part[c * RED_BLOCKS + b]
 
-__device__ inline void last_block_sum(const double* part, int nblk, int cnt, double* out, unsigned* ticket,
-                                      int do_sqrt, int nb_total) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == (unsigned)(nb_total - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // BS threads: (column c, 8 lanes); each lane sums a strided subset, then the 8 lanes
-  // combine in a fixed pattern
-  for (int c0 = 0; c0 < cnt; c0 += BS / 8) {
-    const int c = c0 + (threadIdx.x >> 3), sub = threadIdx.x & 7;
+// out[c] = sum over b < nblk of part[c * stride + b] for c < ncol, in a fixed order
+// (sqrt of the column sum for c >= sqrt_from).  One block: (column, 16 lanes), each lane
+// with 8 independent loads in flight.
+__global__ __launch_bounds__(KBS) void reduce_cols_kernel(const double* __restrict__ part, long stride, int nblk,
+                                                          int ncol, int sqrt_from, double* __restrict__ out) {
+  constexpr int LN = 16;
+  for (int c0 = 0; c0 < ncol; c0 += KBS / LN) {
+    const int c = c0 + (int)(threadIdx.x / LN), sub = threadIdx.x % LN;
     double s = 0.0;
-    if (c < cnt) {
-      double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    if (c < ncol) {
+      const double* pc = part + (long)c * stride;
+      double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       int b = sub;
-      for (; b + 24 < nblk; b += 32) {
-        s0 += part[(long)c * MD_BLOCKS + b];
-        s1 += part[(long)c * MD_BLOCKS + b + 8];
-        s2 += part[(long)c * MD_BLOCKS + b + 16];
-        s3 += part[(long)c * MD_BLOCKS + b + 24];
+      for (; b + 7 * LN < nblk; b += 8 * LN) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] += pc[b + q * LN];
       }
-      for (; b < nblk; b += 8) s0 += part[(long)c * MD_BLOCKS + b];
-      s = (s0 + s1) + (s2 + s3);
+      for (; b < nblk; b += LN) a[0] += pc[b];
+      s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
-    s += __shfl_down(s, 4, 8);
-    s += __shfl_down(s, 2, 8);
-    s += __shfl_down(s, 1, 8);
-    if (sub == 0 && c < cnt) out[c] = do_sqrt ? sqrt(s) : s;
+#pragma unroll
+    for (int off = LN / 2; off > 0; off >>= 1) s += __shfl_down(s, off, LN);
+    if (sub == 0 && c < ncol) out[c] = c >= sqrt_from ? sqrt(s) : s;
   }
-  if (threadIdx.x == 0) *ticket = 0u;
 }
 
-// part[c][block] = partial sum of V[c] . w (c = blockIdx.y; row cnt of the grid, if
-// present, computes w . w)
-template <typename T>
-__global__ __launch_bounds__(BS) void mdot_kernel(const T* __restrict__ V, long ld, int cnt, const T* __restrict__ w,
-                                                  long n, double* __restrict__ part, double* __restrict__ out,
-                                                  unsigned* __restrict__ ticket) {
+// 16-byte vector idx of p: a plain vector load when FULL (the caller has checked that the
+// whole sub-tile lies below lim <= n / W), else zero-filled at and past lim and n.
+template <bool FULL, typename T>
+__device__ inline typename Vec16<T>::type load16(const T* __restrict__ p, long idx, long lim, long nv, long n) {
   using V16 = typename Vec16<T>::type;
   constexpr int VW = Vec16<T>::W;
-  __shared__ double red[BS / 64];
-  const int c = blockIdx.y;
-  const T* v = c < cnt ? V + c * ld : w;
-  double acc = 0.0;
-  const long nv = n / VW;
-  const V16* w4 = reinterpret_cast<const V16*>(w);
-  const V16* v4 = reinterpret_cast<const V16*>(v);
-  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < nv; t += (long)gridDim.x * BS) acc += hsum(v4[t], w4[t]);
-  if (blockIdx.x == 0)
-    for (long t = nv * VW + threadIdx.x; t < n; t += BS) acc += (double)v[t] * (double)w[t];
-  acc = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w2 = 0; w2 < BS / 64; ++w2) s += red[w2];
-    part[(long)c * MD_BLOCKS + blockIdx.x] = s;
+  if (FULL || (idx < nv && idx < lim)) return reinterpret_cast<const V16*>(p)[idx];
+  V16 r;
+  T* pr = reinterpret_cast<T*>(&r);
+#pragma unroll
+  for (int q = 0; q < VW; ++q) {
+    const long e = idx * VW + q;
+    pr[q] = (idx < lim && e < n) ? p[e] : (T)0;
   }
-  last_block_sum(part, gridDim.x, gridDim.y, out, ticket, 0, gridDim.x * gridDim.y);
+  return r;
 }
 
-static inline int md_blocks(long n, int vw) {
-  const long b = (n / vw + BS - 1) / BS;
-  return (int)std::max<long>(1, std::min<long>(b, MD_BLOCKS));
+// Contiguous chunk of 16-byte vectors of block b: [beg, end)
+__device__ inline void block_chunk(long nvt, long& beg, long& end) {
+  const long per = (nvt + gridDim.x - 1) / gridDim.x;
+  beg = (long)blockIdx.x * per;
+  end = beg + per < nvt ? beg + per : nvt;
 }
 
-// out[0..cnt-1] = V[c] . w; with `with_norm` also out[cnt] = w . w
+// One sub-tile of the multi-dot: lane 0 of each wave adds the wave's partial dot products
+// to its own row of wpart (fixed order, no barrier).
+template <bool FULL, typename T>
+__device__ inline void mdot_subtile(const T* __restrict__ V, long ld, int cnt, int ncol, const T* __restrict__ w,
+                                    long base, long end, long nv, long n, double (*wpart)[MAXC + 1]) {
+  using V16 = typename Vec16<T>::type;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  V16 wt[KT<T>::U];
+#pragma unroll
+  for (int u = 0; u < KT<T>::U; ++u) wt[u] = load16<FULL>(w, base + u * KBS + threadIdx.x, end, nv, n);
+  for (int c0 = 0; c0 < ncol; c0 += KG) {
+    V16 vt[KG][KT<T>::U];
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      const int c = c0 + g < cnt ? c0 + g : -1;   // -1: the norm column or unused
+      const T* v = c >= 0 ? V + (long)c * ld : w;
+#pragma unroll
+      for (int u = 0; u < KT<T>::U; ++u) vt[g][u] = load16<FULL>(v, base + u * KBS + threadIdx.x, end, nv, n);
+    }
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < KT<T>::U; ++u) s += hsum(vt[g][u], wt[u]);
+      s = wave_sum(s);
+      if (lane == 0 && c0 + g < ncol) wpart[wv][c0 + g] += s;
+    }
+  }
+}
+
+// out[c] = V[c] . w for c < cnt; with `with_norm` also out[cnt] = w . w
+template <typename T>
+__global__ __launch_bounds__(KBS) __attribute__((amdgpu_waves_per_eu(4))) void mdot_kernel(
+    const T* __restrict__ V, long ld, int cnt, const T* __restrict__ w, long n, int with_norm,
+    double* __restrict__ part) {
+  constexpr int VW = Vec16<T>::W;
+  __shared__ double wpart[KBS / 64][MAXC + 1];
+  const int ncol = cnt + with_norm;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int c = 0; c <= MAXC; ++c) wpart[wv][c] = 0.0;
+  const long nv = n / VW, nvt = (n + VW - 1) / VW;
+  long beg, end;
+  block_chunk(nvt, beg, end);
+  const long lim = end < nv ? end : nv;
+  for (long base = beg; base < end; base += (long)KBS * KT<T>::U) {
+    if (base + (long)KBS * KT<T>::U <= lim) mdot_subtile<true>(V, ld, cnt, ncol, w, base, end, nv, n, wpart);
+    else mdot_subtile<false>(V, ld, cnt, ncol, w, base, end, nv, n, wpart);
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < ncol) {
+    double s = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < KBS / 64; ++w2) s += wpart[w2][threadIdx.x];
+    part[(long)threadIdx.x * RED_BLOCKS + blockIdx.x] = s;
+  }
+}
+
+// blocks for streaming n elements: at least one 16-byte vector per thread, at most KB_MAX
+template <typename T>
+static int stream_blocks(long n) {
+  const long nvt = (n + Vec16<T>::W - 1) / Vec16<T>::W;
+  return (int)std::max<long>(1, std::min<long>(KB_MAX, (nvt + KBS - 1) / KBS));
+}
+
 template <typename T>
 void launch_mdot(hipStream_t st, const T* V, long ld, int cnt, const T* w, long n, double* part, double* out,
                  bool with_norm) {
-  const int nb = md_blocks(n, Vec16<T>::W);
-  unsigned* ticket = reinterpret_cast<unsigned*>(part + RED_BLOCKS * MAXC);
-  hipLaunchKernelGGL(mdot_kernel<T>, dim3(nb, cnt + (with_norm ? 1 : 0)), dim3(BS), 0, st, V, ld, cnt, w, n, part,
-                     out, ticket);
+  const int nb = stream_blocks<T>(n);
+  const int ncol = cnt + (with_norm ? 1 : 0);
+  hipLaunchKernelGGL(mdot_kernel<T>, dim3(nb), dim3(KBS), 0, st, V, ld, cnt, w, n, with_norm ? 1 : 0, part);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(KBS), 0, st, part, (long)RED_BLOCKS, nb, ncol, ncol, out);
 }
 
-// out[c] = sum over blocks of part[b][c] in a fixed order; sqrt if do_sqrt.
+// out[c] = sum over blocks of part[b][c] in a fixed order; sqrt if do_sqrt.  One block of
+// 1024 threads: (column, 32 lanes), each lane with 8 independent loads in flight.
 __global__ __launch_bounds__(1024) void reduce_parts_kernel(const double* __restrict__ part, int nblk, int cnt,
                                                             double* __restrict__ out, int do_sqrt) {
   const int c = threadIdx.x >> 5, sub = threadIdx.x & 31;
-  double s0 = 0, s1 = 0;
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (c < cnt) {
     int b = sub;
-    for (; b + 32 < nblk; b += 64) {
-      s0 += part[b * MAXC + c];
-      s1 += part[(b + 32) * MAXC + c];
+    for (; b + 7 * 32 < nblk; b += 8 * 32) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] += part[(b + q * 32) * MAXC + c];
     }
-    for (; b < nblk; b += 32) s0 += part[b * MAXC + c];
+    for (; b < nblk; b += 32) a[0] += part[b * MAXC + c];
   }
-  double s = s0 + s1;
+  double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   for (int off = 16; off > 0; off >>= 1) s += __shfl_down(s, off, 32);
   if (sub == 0 && c < cnt) out[c] = do_sqrt ? sqrt(s) : s;
 }
 
-constexpr int AX_BLOCKS = 1024;
-
-template <typename T>
-__global__ __launch_bounds__(BS) void maxpy_kernel(const T* __restrict__ V, long ld, int cnt, const double* __restrict__ h,
-                                                   double sign, T* __restrict__ w, long n, double* __restrict__ part,
-                                                   double* __restrict__ nrm_out, unsigned* __restrict__ ticket) {
+// One sub-tile of the multi-axpy; returns the partial sum of squares of the result.
+template <bool FULL, typename T>
+__device__ inline double maxpy_subtile(const T* __restrict__ V, long ld, int cnt, const double* hs, T* __restrict__ w,
+                                       long base, long end, long nv, long n) {
   using V16 = typename Vec16<T>::type;
   constexpr int VW = Vec16<T>::W;
-  __shared__ double hs[MAXC];
-  __shared__ double red[BS / 64];
-  if (threadIdx.x < cnt) hs[threadIdx.x] = sign * h[threadIdx.x];
-  __syncthreads();
-  double nrm = 0.0;
-  const long nv = n / VW;
-  V16* w4 = reinterpret_cast<V16*>(w);
-  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < nv; t += (long)gridDim.x * BS) {
-    V16 wv = w4[t];
-    double a[VW];
-    T* po = reinterpret_cast<T*>(&wv);
+  double a[KT<T>::U][VW];
 #pragma unroll
-    for (int q = 0; q < VW; ++q) a[q] = (double)po[q];
-#pragma unroll 4
-    for (int c = 0; c < cnt; ++c) {
-      const V16 vv = reinterpret_cast<const V16*>(V + c * ld)[t];
-      const T* pv = reinterpret_cast<const T*>(&vv);
+  for (int u = 0; u < KT<T>::U; ++u) {
+    const V16 wv = load16<FULL>(w, base + u * KBS + threadIdx.x, end, nv, n);
+    const T* pw = reinterpret_cast<const T*>(&wv);
 #pragma unroll
-      for (int q = 0; q < VW; ++q) a[q] += hs[c] * (double)pv[q];
+    for (int q = 0; q < VW; ++q) a[u][q] = (double)pw[q];
+  }
+  for (int c0 = 0; c0 < cnt; c0 += KG) {
+    V16 vt[KG][KT<T>::U];
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      const T* v = V + (long)(c0 + g < cnt ? c0 + g : c0) * ld;   // unused rows re-read row c0 (weight 0)
+#pragma unroll
+      for (int u = 0; u < KT<T>::U; ++u) vt[g][u] = load16<FULL>(v, base + u * KBS + threadIdx.x, end, nv, n);
     }
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      const double hc = c0 + g < cnt ? hs[c0 + g] : 0.0;
+#pragma unroll
+      for (int u = 0; u < KT<T>::U; ++u) {
+        const T* pv = reinterpret_cast<const T*>(&vt[g][u]);
+#pragma unroll
+        for (int q = 0; q < VW; ++q) a[u][q] += hc * (double)pv[q];
+      }
+    }
+  }
+  double nrm = 0.0;
+#pragma unroll
+  for (int u = 0; u < KT<T>::U; ++u) {
+    const long idx = base + u * KBS + threadIdx.x;
+    V16 wv;
+    T* pw = reinterpret_cast<T*>(&wv);
 #pragma unroll
     for (int q = 0; q < VW; ++q) {
-      po[q] = (T)a[q];
-      nrm += (double)po[q] * (double)po[q];
+      pw[q] = (T)a[u][q];
+      nrm += (double)pw[q] * (double)pw[q];
     }
-    w4[t] = wv;
-  }
-  if (blockIdx.x == 0) {
-    for (long t = nv * VW + threadIdx.x; t < n; t += BS) {
-      double v = (double)w[t];
-      for (int c = 0; c < cnt; ++c) v += hs[c] * (double)V[c * ld + t];
-      const T vt = (T)v;
-      w[t] = vt;
-      nrm += (double)vt * (double)vt;
+    if (FULL || (idx < nv && idx < end)) {
+      reinterpret_cast<V16*>(w)[idx] = wv;
+    } else if (idx < end) {
+#pragma unroll
+      for (int q = 0; q < VW; ++q)
+        if (idx * VW + q < n) w[idx * VW + q] = pw[q];
     }
   }
-  if (nrm_out) {
+  return nrm;
+}
+
+// w += sign * sum_c h[c] V[c]; with nrm_out also nrm_out[0] = |w| (after the update)
+template <typename T>
+__global__ __launch_bounds__(KBS) __attribute__((amdgpu_waves_per_eu(4))) void maxpy_kernel(
+    const T* __restrict__ V, long ld, int cnt, const double* __restrict__ h, double sign, T* __restrict__ w, long n,
+    double* __restrict__ part) {
+  constexpr int VW = Vec16<T>::W;
+  __shared__ double hs[MAXC];
+  __shared__ double red[KBS / 64];
+  if ((int)threadIdx.x < cnt) hs[threadIdx.x] = sign * h[threadIdx.x];
+  __syncthreads();
+  const long nv = n / VW, nvt = (n + VW - 1) / VW;
+  long beg, end;
+  block_chunk(nvt, beg, end);
+  const long lim = end < nv ? end : nv;
+  double nrm = 0.0;
+  for (long base = beg; base < end; base += (long)KBS * KT<T>::U) {
+    if (base + (long)KBS * KT<T>::U <= lim) nrm += maxpy_subtile<true>(V, ld, cnt, hs, w, base, end, nv, n);
+    else nrm += maxpy_subtile<false>(V, ld, cnt, hs, w, base, end, nv, n);
+  }
+  if (part) {
     const double s = wave_sum(nrm);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
       double tot = 0.0;
-      for (int w2 = 0; w2 < BS / 64; ++w2) tot += red[w2];
+      for (int w2 = 0; w2 < KBS / 64; ++w2) tot += red[w2];
       part[blockIdx.x] = tot;
     }
-    last_block_sum(part, gridDim.x, 1, nrm_out, ticket, 1, gridDim.x);
   }
 }
 
 template <typename T>
 void launch_maxpy(hipStream_t st, const T* V, long ld, int cnt, const double* h, double sign, T* w, long n, double* part,
                   double* nrm_out) {
-  const long b = (n / Vec16<T>::W + BS - 1) / BS;
-  const int nb = (int)std::max<long>(1, std::min<long>(b, AX_BLOCKS));
-  unsigned* ticket = reinterpret_cast<unsigned*>(part + RED_BLOCKS * MAXC);
-  hipLaunchKernelGGL(maxpy_kernel<T>, dim3(nb), dim3(BS), 0, st, V, ld, cnt, h, sign, w, n, part, nrm_out, ticket);
+  const int nb = stream_blocks<T>(n);
+  hipLaunchKernelGGL(maxpy_kernel<T>, dim3(nb), dim3(KBS), 0, st, V, ld, cnt, h, sign, w, n,
+                     nrm_out ? part : nullptr);
+  if (nrm_out)
+    hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(KBS), 0, st, part, (long)RED_BLOCKS, nb, 1, 0, nrm_out);
 }
 
 template <typename T>
@@ -846,16 +1109,16 @@ void launch_objective_grad(hipStream_t st, const Grid& g, const Patch& patch, do
 
 // ------------------------------------------------------------------ instantiations
 #define NC_INST(T)                                                                                   \
-  template void launch_restrict<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);            \
+  template void launch_restrict<T>(hipStream_t, const Grid&, const Grid&, const T*, T*, const T*, bool, T, T*); \
   template void launch_prolong_add<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);         \
   template void launch_inject_state<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);        \
   template void launch_average_coef<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);        \
   template void launch_coarse_assemble<T>(hipStream_t, const LevelView<T>&, double*, double*);      \
   template void launch_dense_apply<T>(hipStream_t, const double*, int, bool, const T*, T*);         \
   template void launch_pack_state<T>(hipStream_t, const Grid&, const double*, T*);                  \
-  template void launch_extract_pt<T>(hipStream_t, const Grid&, const T*, T*, const Scale5<T>*);     \
-  template void launch_scatter_pt<T>(hipStream_t, const Grid&, const T*, const T*, T*, const Scale5<T>*); \
-  template void launch_scale5<T>(hipStream_t, long, const double*, T*, Scale5<double>);             \
+  template void launch_pc_in<T>(hipStream_t, const Grid&, const T*, T, T, const T*, bool, T, T*, T*); \
+  template void launch_pack_pt<T>(hipStream_t, long, const double*, T*, double, double);             \
+  template void launch_unpack_pt<T>(hipStream_t, const Grid&, const T*, double*);                    \
   template void launch_mdot<T>(hipStream_t, const T*, long, int, const T*, long, double*, double*, bool); \
   template void launch_maxpy<T>(hipStream_t, const T*, long, int, const double*, double, T*, long, double*, double*); \
   template void launch_scale_inv<T>(hipStream_t, const double*, const T*, T*, long);                \
@@ -869,5 +1132,8 @@ template void launch_convert<double, float>(hipStream_t, const double*, float*, 
 template void launch_convert<float, double>(hipStream_t, const float*, double*, long, double);
 template void launch_convert<double, double>(hipStream_t, const double*, double*, long, double);
 template void launch_convert<float, float>(hipStream_t, const float*, float*, long, double);
+template void launch_scale2<double, float>(hipStream_t, long, const double*, float*, double, double);
+template void launch_scale2<float, double>(hipStream_t, long, const float*, double*, double, double);
+template void launch_scale2<double, double>(hipStream_t, long, const double*, double*, double, double);
 
 }  // namespace nc

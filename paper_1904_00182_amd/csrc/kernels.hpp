@@ -18,6 +18,10 @@ void launch_jv5(hipStream_t st, const LevelView<T>& L, const T* x, T* y, const S
 // y = J~^T w (five fields) (row a5)
 template <typename T>
 void launch_jtw5(hipStream_t st, const LevelView<T>& L, const T* w, T* y, const Scale5<T>* rows = nullptr);
+// y = D A x on the finest grid, A the (P, T) block of J~ (A^T when transposed), D the
+// row scales rows->s[3], s[4] (identity when null): the operator of the Krylov solve
+template <typename T>
+void launch_pt_store(hipStream_t st, const LevelView<T>& L, bool transpose, const T* x, T* y, const Scale5<T>* rows);
 // Two-field (P, T) operator of a multigrid level: y = A x, r = b - A x, or one damped
 // block-Jacobi sweep y = x + omega D^-1 (b - A x); transpose selects A^T.
 template <typename T>
@@ -37,7 +41,10 @@ void launch_uprojT(hipStream_t st, const LevelView<T>& L, const T* r5, T* b_pt, 
 
 // ---- multigrid transfers and setup
 template <typename T>
-void launch_restrict(hipStream_t st, const Grid& fine, const Grid& coarse, const T* rf, T* bc);
+// bc = P^T rf (constrained coarse dofs zero); with dinv also xc = omega D^-1 bc (D^-T when
+// transposed), the first block-Jacobi step of the coarse level from a zero guess
+void launch_restrict(hipStream_t st, const Grid& fine, const Grid& coarse, const T* rf, T* bc, const T* dinv,
+                     bool transpose, T omega, T* xc);
 template <typename T>
 void launch_prolong_add(hipStream_t st, const Grid& fine, const Grid& coarse, const T* xc, T* xf);
 template <typename T>
@@ -56,13 +63,20 @@ void launch_dense_apply(hipStream_t st, const double* Ainv, int n, bool transpos
 // ---- state / vector helpers
 template <typename T>
 void launch_pack_state(hipStream_t st, const Grid& g, const double* s5, T* pt);           // (P, T) of s
+// Preconditioner input of the (P, T) Krylov solve: b = v / (s_P, s_T) (row scales undone;
+// constrained dofs 0) and the first damped block-Jacobi step x = omega D^-1 b (D^-T)
 template <typename T>
-void launch_extract_pt(hipStream_t st, const Grid& g, const T* r5, T* b, const Scale5<T>* rows = nullptr);  // masked
+void launch_pc_in(hipStream_t st, const Grid& g, const T* v, T inv_p, T inv_t, const T* dinv, bool transpose,
+                  T omega, T* b, T* x);
+// out[n][f] = s_f * r5[n][3 + f] (the (P, T) entries of a five-field float64 vector)
 template <typename T>
-void launch_scatter_pt(hipStream_t st, const Grid& g, const T* x, const T* r5, T* z5,
-                       const Scale5<T>* rows = nullptr);                                  // z_PT = x, z_c = r_c
+void launch_pack_pt(hipStream_t st, long nodes, const double* r5, T* out, double s_p, double s_t);
+// out[n][f] = s_f * in[n][f] for two-field vectors, converting precision
+template <typename Ta, typename Tb>
+void launch_scale2(hipStream_t st, long nodes, const Ta* in, Tb* out, double s_p, double s_t);
+// out5[n][3 + f] = x[n][f] (free dofs) or 0 (constrained dofs); velocity entries untouched
 template <typename T>
-void launch_scale5(hipStream_t st, long nodes, const double* a, T* b, Scale5<double> s);   // b = s_f a_f
+void launch_unpack_pt(hipStream_t st, const Grid& g, const T* x, double* out5);
 void launch_mask_state(hipStream_t st, const Grid& g, double* s5);                       // constrained -> 0
 template <typename Ta, typename Tb>
 void launch_convert(hipStream_t st, const Ta* a, Tb* b, long n, double scale);           // b = scale * a
@@ -73,8 +87,8 @@ void launch_diag_scale(hipStream_t st, const Grid& g, const T* dinv, bool transp
 template <typename T>
 void launch_rsub(hipStream_t st, const T* b, T* out, long n);                          // out = b - out
 
-// ---- reductions (deterministic: fixed grid, fixed order).  `part` must hold
-// RED_BLOCKS * MAXC doubles followed by one zero-initialised unsigned ticket.
+// ---- reductions (deterministic: fixed grid, fixed order).  `part` is a scratch array of
+// RED_BLOCKS * MAXC doubles for the per-block partial sums.
 constexpr int RED_BLOCKS = 2048;
 constexpr int MAXC = 32;
 // out[c] = V[c] . w for c < cnt (and out[cnt] = w . w when with_norm)

@@ -53,7 +53,7 @@ struct HipError {
 
 // Kernel classes of the per-context event timer (nc_set_timing / nc_get_timing).
 enum TimerClass {
-  TC_RESIDUAL = 0, TC_JV5, TC_JTW5, TC_SMOOTH, TC_SMOOTH_T, TC_PT_RESID, TC_DIAG, TC_UPROJ, TC_TRANSFER,
+  TC_RESIDUAL = 0, TC_JV, TC_JTW, TC_SMOOTH, TC_SMOOTH_T, TC_PT_RESID, TC_DIAG, TC_UPROJ, TC_TRANSFER,
   TC_COARSE, TC_MDOT, TC_MAXPY, TC_VECTOR, TC_SETUP, TC_SMOOTH_COARSE, TC_COUNT
 };
 constexpr int TIMER_EVENTS = 8192;
@@ -72,7 +72,7 @@ struct nc_ctx {
   Level lev[MAXLEV];
   Patch patch;
   long N, E, n5;
-  long ld;               // stride between Krylov vectors (n5 rounded up to 64 for aligned vector loads)
+  long ld;               // stride between Krylov vectors (2N rounded up to 64 for aligned vector loads)
   int m;                 // Krylov restart length
   // design chain
   double *gamma, *dk, *dkap, *ftmp, *sens;
@@ -88,6 +88,7 @@ struct nc_ctx {
   double* hbuf;          // pinned host mirror of dres
   // float64 Newton / adjoint vectors
   double *R, *d, *strial, *ra, *tmp5;
+  double* pt64;          // float64 (P, T) vector of the reduced solves
   // per-field row equilibration of the five-field system inside FGMRES
   Scale5<double> rows64;
   Scale5<float> rows32;
@@ -210,12 +211,13 @@ size_t carve(nc_ctx* c, char* base) {
   c->emats = cv.take<double>(c->dense ? gc.elems() * 256 : 1);
   c->A = cv.take<double>(c->dense ? 2 * (size_t)c->ncoarse * c->ncoarse : 1);   // inverse and its transpose
   c->perm = cv.take<int>(c->dense ? c->ncoarse : 1);
-  c->ld = (c->n5 + 63) / 64 * 64;
+  c->ld = (2 * c->N + 63) / 64 * 64;   // Krylov vectors: the (P, T) system
   c->V = cv.take<char>((size_t)(c->m + 1) * c->ld * rs);
   c->Z = cv.take<char>((size_t)c->m * c->ld * rs);
-  c->kx = cv.take<char>(c->n5 * rs);
-  c->kb = cv.take<char>(c->n5 * rs);
-  c->part = cv.take<double>(RED_BLOCKS * MAXC + 8);   // partials + last-block ticket
+  c->kx = cv.take<char>(2 * c->N * rs);
+  c->kb = cv.take<char>(2 * c->N * rs);
+  c->pt64 = cv.take<double>(2 * c->N);
+  c->part = cv.take<double>(RED_BLOCKS * MAXC);   // per-block partial sums of the reductions
   c->dres = cv.take<double>(4 * MAXC);
   c->R = cv.take<double>(c->n5);
   c->d = cv.take<double>(c->n5);
@@ -278,68 +280,84 @@ void linearize(nc_ctx* c, const double* s, bool levels) {
 }
 
 // ------------------------------------------------------------------ V-cycle
+// x_ready: L.x already holds the first damped block-Jacobi step from a zero guess (fused
+// into the restriction that produced L.b).
 template <typename T>
-void vcycle(nc_ctx* c, int l, bool tr) {
+void vcycle(nc_ctx* c, int l, bool tr, bool x_ready = false) {
   hipStream_t st = c->stream;
   Level& L = c->lev[l];
   const T om = (T)c->p.smooth_omega;
   LevelView<T> v = view<T>(c, l);
+  const double sweep_bytes = sizeof(T) * (12 * nn(L.g) + 2 * ne(L.g));
+  const int sweep_class = l == 0 ? (tr ? TC_SMOOTH_T : TC_SMOOTH) : TC_SMOOTH_COARSE;
+  auto first_step = [&]() {
+    if (x_ready) return;
+    Timed tm(c, TC_TRANSFER, sizeof(T) * 8 * nn(L.g));
+    launch_diag_scale<T>(st, L.g, (const T*)L.dinv, tr, om, (const T*)L.b, (T*)L.x);
+  };
+  auto sweep = [&]() {
+    Timed tm(c, sweep_class, sweep_bytes);
+    launch_pt_apply<T>(st, v, tr, MODE_SMOOTH, (const T*)L.x, (const T*)L.b, (T*)L.x2, om, l == 0);
+    std::swap(L.x, L.x2);
+  };
   if (l == c->L - 1) {
     if (c->dense) {
       Timed tm(c, TC_COARSE, (double)sizeof(T) * ((double)c->ncoarse * c->ncoarse + 2.0 * c->ncoarse));
       launch_dense_apply<T>(st, c->A, c->ncoarse, tr, (const T*)L.b, (T*)L.x);
     } else {
-      { Timed tm(c, TC_TRANSFER, sizeof(T) * 8 * nn(L.g)); launch_diag_scale<T>(st, L.g, (const T*)L.dinv, tr, om, (const T*)L.b, (T*)L.x); }
-      for (int s = 1; s < 8; ++s) {
-        Timed tm(c, l == 0 ? (tr ? TC_SMOOTH_T : TC_SMOOTH) : TC_SMOOTH_COARSE, sizeof(T) * (12 * nn(L.g) + 2 * ne(L.g)));
-        launch_pt_apply<T>(st, v, tr, MODE_SMOOTH, (const T*)L.x, (const T*)L.b, (T*)L.x2, om, l == 0);
-        std::swap(L.x, L.x2);
-      }
+      first_step();
+      for (int s = 1; s < 8; ++s) sweep();
     }
     return;
   }
-  { Timed tm(c, TC_TRANSFER, sizeof(T) * 8 * nn(L.g)); launch_diag_scale<T>(st, L.g, (const T*)L.dinv, tr, om, (const T*)L.b, (T*)L.x); }
-  for (int s = 1; s < c->p.smooth_pre; ++s) {
-    Timed tm(c, l == 0 ? (tr ? TC_SMOOTH_T : TC_SMOOTH) : TC_SMOOTH_COARSE, sizeof(T) * (12 * nn(L.g) + 2 * ne(L.g)));
-    launch_pt_apply<T>(st, v, tr, MODE_SMOOTH, (const T*)L.x, (const T*)L.b, (T*)L.x2, om, l == 0);
-    std::swap(L.x, L.x2);
-  }
+  first_step();
+  for (int s = 1; s < c->p.smooth_pre; ++s) sweep();
   { Timed tm(c, TC_PT_RESID, sizeof(T) * (8 * nn(L.g) + 2 * ne(L.g))); launch_pt_apply<T>(st, v, tr, MODE_RESID, (const T*)L.x, (const T*)L.b, (T*)L.r, om, l == 0); }
   Level& C = c->lev[l + 1];
-  { Timed tm(c, TC_TRANSFER, sizeof(T) * 2 * (nn(L.g) + nn(C.g))); launch_restrict<T>(st, L.g, C.g, (const T*)L.r, (T*)C.b); }
-  vcycle<T>(c, l + 1, tr);
-  { Timed tm(c, TC_TRANSFER, sizeof(T) * (4 * nn(L.g) + 2 * nn(C.g))); launch_prolong_add<T>(st, L.g, C.g, (const T*)C.x, (T*)L.x); }
-  for (int s = 0; s < c->p.smooth_post; ++s) {
-    Timed tm(c, l == 0 ? (tr ? TC_SMOOTH_T : TC_SMOOTH) : TC_SMOOTH_COARSE, sizeof(T) * (12 * nn(L.g) + 2 * ne(L.g)));
-    launch_pt_apply<T>(st, v, tr, MODE_SMOOTH, (const T*)L.x, (const T*)L.b, (T*)L.x2, om, l == 0);
-    std::swap(L.x, L.x2);
+  // the coarse level's first smoothing step rides along with the restriction, except on a
+  // coarsest level solved by the dense inverse
+  const bool fuse = !(l + 1 == c->L - 1 && c->dense);
+  {
+    Timed tm(c, TC_TRANSFER, sizeof(T) * (2 * nn(L.g) + (fuse ? 8 : 2) * nn(C.g)));
+    launch_restrict<T>(st, L.g, C.g, (const T*)L.r, (T*)C.b, fuse ? (const T*)C.dinv : nullptr, tr, om, (T*)C.x);
   }
+  vcycle<T>(c, l + 1, tr, fuse);
+  { Timed tm(c, TC_TRANSFER, sizeof(T) * (4 * nn(L.g) + 2 * nn(C.g))); launch_prolong_add<T>(st, L.g, C.g, (const T*)C.x, (T*)L.x); }
+  for (int s = 0; s < c->p.smooth_post; ++s) sweep();
 }
 
-// z = P^-1 r for the block-triangular Jacobian: multigrid on the (P, T) block and exact
-// back-substitution of the lumped-mass velocity rows.
-// r5 is a residual of the row-scaled system D A x = D b when `rows` is given.
+// Block-Jacobi sweeps on the finest level after its first damped step (each swaps x, x2).
+int level0_swaps(const nc_ctx* c) {
+  if (c->L == 1) return c->dense ? 0 : 7;
+  return std::max(0, c->p.smooth_pre - 1) + c->p.smooth_post;
+}
+
+// z = M^-1 v for the row-scaled (P, T) system D A (A^T when tr): one multigrid V-cycle
+// on D^-1 v (rows = null: no scaling).  The finest level's iterate buffers are routed so
+// that the cycle's result ends in z.
 template <typename T>
-void precondition(nc_ctx* c, bool tr, const T* r5, T* z5, const Scale5<T>* rows) {
+void precondition_pt(nc_ctx* c, bool tr, const T* v, T* z, const Scale5<T>* rows) {
   hipStream_t st = c->stream;
   Level& L0 = c->lev[0];
-  LevelView<T> v0 = view<T>(c, 0);
-  if (!tr) {
-    { Timed tm(c, TC_VECTOR, sizeof(T) * 4 * nn(L0.g)); launch_extract_pt<T>(st, L0.g, r5, (T*)L0.b, rows); }
-    vcycle<T>(c, 0, false);
-    { Timed tm(c, TC_UPROJ, sizeof(T) * (12 * nn(L0.g) + ne(L0.g))); launch_uproj<T>(st, v0, (const T*)L0.x, r5, z5, rows); }
-  } else {
-    { Timed tm(c, TC_UPROJ, sizeof(T) * (12 * nn(L0.g) + ne(L0.g))); launch_uprojT<T>(st, v0, r5, (T*)L0.b, z5, rows); }
-    vcycle<T>(c, 0, true);
-    { Timed tm(c, TC_VECTOR, sizeof(T) * 4 * nn(L0.g)); launch_scatter_pt<T>(st, L0.g, (const T*)L0.x, r5, z5, rows); }
+  void* const xo = L0.x;
+  void* const x2o = L0.x2;
+  if (level0_swaps(c) % 2 == 0) L0.x = z;
+  else L0.x2 = z;
+  const T ip = rows ? (T)1 / rows->s[3] : (T)1, it = rows ? (T)1 / rows->s[4] : (T)1;
+  {
+    Timed tm(c, TC_VECTOR, sizeof(T) * 10 * nn(L0.g));
+    launch_pc_in<T>(st, L0.g, v, ip, it, (const T*)L0.dinv, tr, (T)c->p.smooth_omega, (T*)L0.b, (T*)L0.x);
   }
+  vcycle<T>(c, 0, tr, true);
+  L0.x = xo;
+  L0.x2 = x2o;
 }
 
+// y = D A x (A^T when tr), the operator of the (P, T) Krylov solve
 template <typename T>
-void apply_op(nc_ctx* c, bool tr, const T* x, T* y, const Scale5<T>* rows) {
-  Timed tm(c, tr ? TC_JTW5 : TC_JV5, sizeof(T) * (12 * nn(c->lev[0].g) + 2 * ne(c->lev[0].g)));
-  if (!tr) launch_jv5<T>(c->stream, view<T>(c, 0), x, y, rows);
-  else launch_jtw5<T>(c->stream, view<T>(c, 0), x, y, rows);
+void apply_pt(nc_ctx* c, bool tr, const T* x, T* y, const Scale5<T>* rows) {
+  Timed tm(c, tr ? TC_JTW : TC_JV, sizeof(T) * (6 * nn(c->lev[0].g) + 2 * ne(c->lev[0].g)));
+  launch_pt_store<T>(c->stream, view<T>(c, 0), tr, x, y, rows);
 }
 
 template <typename T>
@@ -363,13 +381,14 @@ void compute_row_scales(nc_ctx* c) {
 }
 
 // ------------------------------------------------------------------ flexible GMRES
-// Solves Op x = b (Op = J~ or J~^T) from x = 0 with right preconditioning; classical
-// Gram-Schmidt with one re-orthogonalisation; Hessenberg least squares on the host.
+// Solves D A x = b (A the (P, T) block of J~, A^T when tr, D the P and T row scales) from
+// x = 0 with right preconditioning; classical Gram-Schmidt, repeated when the projection
+// removed most of the vector; Hessenberg least squares on the host.
 template <typename T>
 int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double* relres) {
   hipStream_t st = c->stream;
   const Scale5<T>* rows = row_scales<T>(c);
-  const long n = c->n5, ld = c->ld;
+  const long n = 2 * c->N, ld = c->ld;
   const int m = c->m;
   T* V = (T*)c->V;
   T* Z = (T*)c->Z;
@@ -393,8 +412,8 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
       T* vj = V + (long)j * ld;
       T* w = V + (long)(j + 1) * ld;
       T* zj = Z + (long)j * ld;
-      precondition<T>(c, tr, vj, zj, rows);
-      apply_op<T>(c, tr, zj, w, rows);
+      precondition_pt<T>(c, tr, vj, zj, rows);
+      apply_pt<T>(c, tr, zj, w, rows);
       // classical Gram-Schmidt, repeated only when the projection removed most of w
       // ("twice is enough" criterion of Kahan and Parlett)
       { Timed tm(c, TC_MDOT, sizeof(T) * (double)(j + 2) * n); launch_mdot<T>(st, V, ld, j + 1, w, n, c->part, dres, true); }
@@ -447,7 +466,7 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
     launch_maxpy<T>(st, Z, ld, jend, dres + 3 * MAXC, 1.0, x, n, c->part, nullptr);
     if (done) break;
     // restart from the true residual
-    apply_op<T>(c, tr, x, V, rows);
+    apply_pt<T>(c, tr, x, V, rows);
     launch_rsub<T>(st, b, V, n);
     launch_norm<T>(st, V, n, c->part, dres);
     fetch(c, dres, 1);
@@ -460,33 +479,59 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
   return total;
 }
 
-// Linear solve Op x = b with a float64 right-hand side and solution, in the working
-// precision, on the row-equilibrated system (D Op) x = D b.
-int linear_solve(nc_ctx* c, bool tr, const double* b, double* x, double rtol, double* relres) {
+// Solve of J~ d = r (J~^T d = r when tr) for five-field float64 r and d.  The P and T rows
+// of J~ do not involve the velocity, so the velocity rows are eliminated exactly: the
+// (P, T) system is solved in the working precision -- by FGMRES on the row-scaled system
+// (krylov) or by one V-cycle (an error estimate) -- and the velocity part follows by
+// back-substitution through the lumped mass in float64:
+//   J~ d = r:    A d_PT = r_PT,               d_u = M^-1 (r_u - C d_PT)
+//   J~^T d = r:  d_u = M^-1 r_u,              A^T d_PT = r_PT - C^T d_u
+template <typename T>
+int reduced_solve(nc_ctx* c, bool tr, const double* r, double* d, bool krylov, double rtol, double* relres) {
   hipStream_t st = c->stream;
-  const int maxit = c->p.krylov_maxit;
-  if (c->mixed) {
-    launch_scale5<float>(st, c->N, b, (float*)c->kb, c->rows64);
-    const int its = fgmres<float>(c, tr, (const float*)c->kb, (float*)c->kx, rtol, maxit, relres);
-    launch_convert<float, double>(st, (const float*)c->kx, x, c->n5, 1.0);
-    return its;
+  const Level& L0 = c->lev[0];
+  const LevelView<double> v64 = view<double>(c, 0);
+  const double sp = krylov ? c->rows64.s[3] : 1.0, stt = krylov ? c->rows64.s[4] : 1.0;
+  T* kb = (T*)c->kb;
+  T* kx = (T*)c->kx;
+  const double ubytes = 8.0 * (12 * nn(L0.g) + ne(L0.g));
+  const double vbytes = (8.0 + sizeof(T)) * 2 * nn(L0.g);
+  if (!tr) {
+    Timed tm(c, TC_VECTOR, vbytes);
+    launch_pack_pt<T>(st, c->N, r, kb, sp, stt);
+  } else {
+    { Timed tm(c, TC_UPROJ, ubytes); launch_uprojT<double>(st, v64, r, c->pt64, d, nullptr); }
+    { Timed tm(c, TC_VECTOR, vbytes); launch_scale2<double, T>(st, c->N, c->pt64, kb, sp, stt); }
   }
-  launch_scale5<double>(st, c->N, b, (double*)c->kb, c->rows64);
-  return fgmres<double>(c, tr, (const double*)c->kb, x, rtol, maxit, relres);
+  int its = 0;
+  if (krylov) {
+    its = fgmres<T>(c, tr, kb, kx, rtol, c->p.krylov_maxit, relres);
+    if (its < 0) return its;
+  } else {
+    precondition_pt<T>(c, tr, kb, kx, nullptr);
+  }
+  if (!tr) {
+    { Timed tm(c, TC_VECTOR, vbytes); launch_scale2<T, double>(st, c->N, kx, c->pt64, 1.0, 1.0); }
+    { Timed tm(c, TC_UPROJ, ubytes); launch_uproj<double>(st, v64, c->pt64, r, d, nullptr); }
+  } else {
+    Timed tm(c, TC_VECTOR, vbytes);
+    launch_unpack_pt<T>(st, L0.g, kx, d);
+  }
+  return its;
 }
 
-// Per-field error estimate of an approximate solution: e = P^-1 r (one preconditioner
-// application), returns max_f |e_f| / |x_f| over the fields with |x_f| > 0.
+int linear_solve(nc_ctx* c, bool tr, const double* r, double* d, double rtol, double* relres) {
+  return c->mixed ? reduced_solve<float>(c, tr, r, d, true, rtol, relres)
+                  : reduced_solve<double>(c, tr, r, d, true, rtol, relres);
+}
+
+// Per-field error estimate of an approximate solution: e = one V-cycle solve of the
+// residual r, returns max_f |e_f| / |x_f| over the fields with |x_f| > 0.
 double error_estimate(nc_ctx* c, bool tr, const double* r, const double* x) {
-  hipStream_t st = c->stream;
-  if (c->mixed) {
-    launch_convert<double, float>(st, r, (float*)c->kb, c->n5, 1.0);
-    precondition<float>(c, tr, (const float*)c->kb, (float*)c->kx, nullptr);
-    launch_convert<float, double>(st, (const float*)c->kx, c->tmp5, c->n5, 1.0);
-  } else {
-    precondition<double>(c, tr, r, c->tmp5, nullptr);
-  }
-  launch_field_norms(st, c->tmp5, x, c->N, c->part, c->dres);
+  double dummy = 0.0;
+  if (c->mixed) reduced_solve<float>(c, tr, r, c->tmp5, false, 0.0, &dummy);
+  else reduced_solve<double>(c, tr, r, c->tmp5, false, 0.0, &dummy);
+  launch_field_norms(c->stream, c->tmp5, x, c->N, c->part, c->dres);
   fetch(c, c->dres, 10);
   double worst = 0.0;
   for (int f = 0; f < 5; ++f)
@@ -731,7 +776,6 @@ int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stre
     c->hier_valid = false;
     c->timing = false;
     c->ev_used = 0;
-    ck(hipMemsetAsync(c->part + RED_BLOCKS * MAXC, 0, 8 * sizeof(double), c->stream));
     if (hipHostMalloc((void**)&c->hbuf, sizeof(double) * 4 * MAXC, hipHostMallocDefault) != hipSuccess) {
       delete c;
       return NC_EHIP;

@@ -23,7 +23,7 @@ EXPORTED = [
     "nc_solve_adjoint", "nc_sensitivity", "nc_cone_filter", "nc_set_timing", "nc_get_timing",
 ]
 
-TIMER_CLASSES = ["residual", "jv5", "jtw5", "smooth", "smooth_T", "pt_residual", "diag", "uproj", "transfer",
+TIMER_CLASSES = ["residual", "jv", "jtw", "smooth", "smooth_T", "pt_residual", "diag", "uproj", "transfer",
                  "coarse", "mdot", "maxpy", "vector", "setup", "smooth_coarse"]
 
 

@@ -25,8 +25,8 @@ def counts():
 def test_bench_flop_constants_match_element_code():
     import bench
     c = counts()
-    assert bench.FLOPS_PER_ELEM["jv5"] == c["lin"] + c["jv5"]
-    assert bench.FLOPS_PER_ELEM["jtw5"] == c["lin"] + c["jtw5"]
+    assert bench.FLOPS_PER_ELEM["jv"] == c["lin"] + c["jv2"]
+    assert bench.FLOPS_PER_ELEM["jtw"] == c["lin"] + c["jtw2"]
     assert bench.FLOPS_PER_ELEM["smooth"] == c["lin"] + c["jv2"]
     assert bench.FLOPS_PER_ELEM["smooth_T"] == c["lin"] + c["jtw2"]
     assert bench.FLOPS_PER_ELEM["pt_residual"] == c["lin"] + c["jv2"]
