@@ -9,9 +9,10 @@ refinement) and the sensitivities through RAMP and the filter.  Inputs are resid
 HBM before the timed region.
 
 Printed: one JSON line with the step time (the metric is "state+adjoint solve s at 1M
-elems", lower is better), the live HIP-event timing of the dominant operator kernel
-against the HBM roofline, operator GDoF/s, and the float64 CPU oracle timed on a small
-sample of the same workload on this host.
+elems", lower is better), the roofline of the dominant kernel from live HIP-event timing
+on the solver's stream (vector-ALU bound for the operator kernels, HBM bound for the
+streaming ones), operator GDoF/s, and the float64 CPU oracle timed on a small sample of
+the same workload on this host.  --report FILE adds the extended measurements.
 """
 
 import argparse
@@ -35,18 +36,49 @@ FLOPS_PER_ELEM = {"jv": 279 + 524, "jtw": 279 + 593, "smooth": 279 + 524, "smoot
                   "pt_residual": 279 + 524}
 FLOPS_PER_NODE = {"jv": 16, "jtw": 16, "smooth": 26, "smooth_T": 26, "pt_residual": 16}
 
-# kernel symbol of each timed class (tile template arguments elided)
+# timed classes that are one kernel at one grid size, their kernel symbols (tile template
+# arguments elided) and the pattern of their names in rocprofv3 output
+SINGLE_KERNEL_CLASSES = ("smooth", "smooth_T", "pt_residual", "jv", "jtw", "mdot", "maxpy")
 KERNEL_NAMES = {
     "jv": "zmarch_kernel<JvOp<{t},2,0>,..,1> (Krylov operator: (P, T) block of J)",
     "jtw": "zmarch_kernel<JtwOp<{t},2,0>,..,1> (Krylov operator: (P, T) block of J^T)",
     "smooth": "zmarch_kernel<JvOp<{t},2,2>,..,1> (finest-grid block-Jacobi sweep)",
     "smooth_T": "zmarch_kernel<JtwOp<{t},2,2>,..,1> (finest-grid transposed block-Jacobi sweep)",
-    "smooth_coarse": "zmarch_kernel<JvOp/JtwOp<{t},2,2>,..,0> (block-Jacobi sweeps, coarse levels)",
-    "pt_residual": "zmarch_kernel<JvOp/JtwOp<{t},2,1>,..> (multigrid residual)",
+    "pt_residual": "zmarch_kernel<JvOp/JtwOp<{t},2,1>,..,1> (finest-grid multigrid residual)",
     "mdot": "mdot_kernel<{t}> (FGMRES multi-dot)",
     "maxpy": "maxpy_kernel<{t}> (FGMRES multi-axpy)",
-    "transfer": "restrict/prolong/diag_scale kernels (grid transfers)",
 }
+PROFILE_NAMES = {
+    "jv": r"zmarch_kernel<JvOp<{t}, 2, 0>, \d+, \d+, 1>", "jtw": r"zmarch_kernel<JtwOp<{t}, 2, 0>, \d+, \d+, 1>",
+    "smooth": r"zmarch_kernel<JvOp<{t}, 2, 2>, \d+, \d+, 1>", "smooth_T": r"zmarch_kernel<JtwOp<{t}, 2, 2>, \d+, \d+, 1>",
+    "pt_residual": r"zmarch_kernel<JvOp<{t}, 2, 1>, \d+, \d+, 1>", "mdot": r"mdot_kernel<{t}>", "maxpy": r"maxpy_kernel<{t}>",
+}
+# kernel sources whose hash must match the one recorded with the counter runs
+KERNEL_SOURCES = ["paper_1904_00182_amd/csrc/k_misc.hip", "paper_1904_00182_amd/csrc/k_apply.hip",
+                  "paper_1904_00182_amd/csrc/element.hpp", "paper_1904_00182_amd/csrc/common.hpp",
+                  "paper_1904_00182_amd/csrc/kernels.hpp"]
+
+
+def measured_traffic(cls, tname):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) of the class's kernel from
+    the committed counter summary, or None when there is none or the kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_cavity128x64x128_mixed.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest():
+        return None
+    pat = re.compile(PROFILE_NAMES[cls].format(t=tname) + "$")
+    for name, v in rec["kernels"].items():
+        if pat.match(name):
+            return round(v["fetch_bytes"] + v["write_bytes"])
+    return None
 
 
 def parse():
@@ -59,6 +91,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-grid", default="20,10,20")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--report", default=None,
+                    help="also write extended measurements (operator sweep, float64 baseline, warm re-solve, "
+                         "oracle phases, serving) as JSON to this file")
+    ap.add_argument("--report-requests", type=int, default=128)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (a kernel of known traffic for counter scaling)")
     return ap.parse_args()
@@ -131,6 +167,134 @@ def cpu_baseline(args, E_target):
         "host_cores_available": len(os.sched_getaffinity(0)),
         "phases_s": {k: round(v, 3) for k, v in m.timing.items()},
     }
+
+
+def _rel(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / max(float(torch.linalg.vector_norm(b)), 1e-300))
+
+
+def report(args, path):
+    """Extended measurements of the path, written as JSON: operator throughput per grid
+    (rotating and cache-resident buffers, float32 and float64), the float64 and mixed
+    solves at 128 x 64 x 128 with their difference, a warm-started re-solve after a 1 %
+    design perturbation, the oracle's phases beside the GPU solve at small sizes, and the
+    serving trace."""
+    import numpy as np
+    import torch
+    from paper_1904_00182_amd import inputs, nc, serve, workloads
+    dev = "cuda:0"
+    out = {}
+
+    def sync_time(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, r
+
+    # 1. five-field Jacobian apply throughput per grid
+    rows = []
+    for grid in ((16, 8, 16), (32, 16, 32), (64, 32, 64), (96, 48, 96), (128, 64, 128)):
+        p = workloads.problem(grid, 1e4, nc.NC_MIXED)
+        sol = nc.Solver(p, dev)
+        sol.set_design(workloads.design(grid, "blobs", 2, dev))
+        s = sol.solve_state()
+        sol.linearize(s)
+        N, E = sol.N, sol.E
+        for dt, sz in ((torch.float32, 4), (torch.float64, 8)):
+            rot = max(2, int(2 * 512e6 / (2 * 5 * N * sz)))
+            for tr in (False, True):
+                for label, pairs in (("rotating", rot), ("cache_resident", 1)):
+                    t = time_apply(sol, torch, dt, tr, 200, pairs)
+                    rows.append({"grid": list(grid), "dtype": "f32" if sz == 4 else "f64", "op": "JT w" if tr else "J v",
+                                 "buffers": label, "us": round(t * 1e6, 2), "gdofs": round(5 * N / t / 1e9, 2),
+                                 "gdofs_pt": round(2 * N / t / 1e9, 2),
+                                 "hbm_frac": round((12 * N + 2 * E) * sz / t / 1e9 / HBM_PEAK_GBS, 4)})
+        sol.close()
+        log(args, "operator", grid, "done")
+    out["operator"] = rows
+
+    # 2. float64 and mixed solves at 1M elements, and their difference
+    res = {}
+    for name in ("cavity128", "cavity128mixed"):
+        p, x, cfg = workloads.config(name, dev)
+        sol = nc.Solver(p, dev)
+        sol.set_design(x)
+        g = sol.objective_grad()
+
+        def one():
+            s = sol.solve_state()
+            i1 = dict(sol.last_info)
+            lam = sol.solve_adjoint(s, g)
+            i2 = dict(sol.last_info)
+            return s, lam, sol.sensitivity(s, lam), i1, i2
+        t, (s, lam, dfdx, i1, i2) = sync_time(one)
+        res[name] = dict(s=s, lam=lam, dfdx=dfdx)
+        out[name] = {"step_s": round(t, 4), "newton_its": i1["newton_its"], "state_krylov_its": i1["krylov_its"],
+                     "adjoint_krylov_its": i2["krylov_its"], "adjoint_refinements": i2["refine_its"],
+                     "objective": sol.objective(s)}
+        if name == "cavity128mixed":
+            # warm start after a 1 % perturbation of the design
+            gen = inputs.rng(77)
+            x2 = torch.clamp(x + 0.01 * torch.as_tensor(gen.uniform(-1, 1, x.numel()), device=dev), 0, 1)
+            sol.set_design(x2)
+            s_cold = sol.solve_state()
+            ic = dict(sol.last_info)
+
+            def warm():
+                return sol.solve_state(s0=s)
+            tw, _ = sync_time(warm)
+            iw = dict(sol.last_info)
+            tc, _ = sync_time(lambda: sol.solve_state())
+            out["warm_resolve"] = {"perturbation": "x + 0.01 U(-1, 1), clipped to [0, 1]", "cold_state_s": round(tc, 4),
+                                   "cold_newton_its": ic["newton_its"], "warm_state_s": round(tw, 4),
+                                   "warm_newton_its": iw["newton_its"], "warm_krylov_its": iw["krylov_its"]}
+        sol.close()
+        log(args, name, out[name])
+    a, b = res["cavity128mixed"], res["cavity128"]
+    fields = ("u", "v", "w", "P", "T")
+    out["mixed_vs_fp64_rel_l2"] = {
+        **{f"s_{f}": _rel(a["s"][:, k], b["s"][:, k]) for k, f in enumerate(fields)},
+        **{f"lambda_{f}": _rel(a["lam"][:, k], b["lam"][:, k]) for k, f in ((3, "P"), (4, "T"))},
+        "dfdx": _rel(a["dfdx"], b["dfdx"])}
+
+    # 3. oracle phases beside the float64 GPU solve at small sizes
+    import oracle
+    ph = []
+    for grid in ((16, 8, 16), (24, 12, 24), (32, 16, 32)):
+        nx, ny, nz = grid
+        op = oracle.Params(nx, ny, nz, alpha=1e3, kappa_f=0.00513)
+        xo = inputs.noise_design(nx * ny * nz, 0)
+        t0 = time.perf_counter()
+        m = oracle.Model(op, xo)
+        so, _ = m.solve_state()
+        lo = m.solve_adjoint(so, m.dfds())
+        m.sensitivity(so, lo)
+        wall = time.perf_counter() - t0
+        p = workloads.problem(grid, 1e3, nc.NC_FP64)
+        sol = nc.Solver(p, dev)
+        sol.set_design(torch.as_tensor(xo, device=dev))
+        gg = sol.objective_grad()
+
+        def gpu():
+            s = sol.solve_state()
+            lam = sol.solve_adjoint(s, gg)
+            return sol.sensitivity(s, lam)
+        tg, _ = sync_time(gpu, 5)
+        sol.close()
+        ph.append({"grid": list(grid), "oracle_s": round(wall, 3), "oracle_phases_s": {k: round(v, 3) for k, v in m.timing.items()},
+                   "gpu_fp64_s": round(tg, 5)})
+        log(args, "oracle", ph[-1])
+    out["oracle_vs_gpu"] = ph
+    out["host"] = {"cpu_model": _cpu_model(), "cores_available": len(os.sched_getaffinity(0))}
+
+    # 4. serving
+    out["serving"] = serve.run(n=args.report_requests, log=lambda *a: log(args, *a))
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
 
 
 def _cpu_model():
@@ -224,38 +388,34 @@ def main():
     bytes_jv = (N * (5 + 5 + 2) + E * 2) * sz
     bytes_jv64 = (N * (5 + 5 + 2) + E * 2) * 8
     dofs = 5 * N
-    # dominant kernel class of the solve (by summed HIP-event time) and its roofline:
-    # achieved = the class's algorithmic bytes (library accounting: inputs read once,
-    # outputs written once) / its summed launch time
+    # dominant kernel of the solve: the timed class (each one kernel at one grid size) with
+    # the largest summed HIP-event time.  achieved = the class's algorithmic bytes (library
+    # accounting: inputs read once, outputs written once) or flops / its summed launch time.
     classes_b = sol.timing_bytes
-    dom = max(classes_b, key=lambda k: classes_b[k][0])
+    dom = max(SINGLE_KERNEL_CLASSES, key=lambda k: classes_b[k][0])
     dom_ms, dom_n, dom_bytes = classes_b[dom]
     t_dom = dom_ms / max(dom_n, 1) * 1e-3
-    ach = dom_bytes / (dom_ms * 1e-3) / 1e9
     share = dom_ms / max(1e-9, sum(v[0] for v in classes_b.values()))
-    roof = {
-        "kernel": KERNEL_NAMES.get(dom, dom).format(t="float" if mixed else "double"),
-        "bound": "hbm",
-        "achieved": round(ach, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(ach / HBM_PEAK_GBS, 4),
-        "traffic": None,
-        "class": dom,
-        "launch_us": round(t_dom * 1e6, 2),
-        "launches": dom_n,
-        "bytes_per_launch": round(dom_bytes / max(dom_n, 1)),
-        "share_of_kernel_time": round(share, 3),
-        "timed_step_ms": round(t_step_timed * 1e3, 3),
-    }
+    tname = "float" if mixed else "double"
+    gbs = dom_bytes / (dom_ms * 1e-3) / 1e9
+    hbm = {"achieved_gbs": round(gbs, 1), "peak_gbs": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
+           "bytes_per_launch": round(dom_bytes / max(dom_n, 1))}
+    traffic = measured_traffic(dom, tname)
     if dom in FLOPS_PER_ELEM:
-        # arithmetic side of the operator kernels: exact flops of the element and node
-        # arithmetic (counted on the element code itself) against the vector peak
+        # operator kernels are bound by vector ALU issue: exact flops of the
+        # element and node arithmetic, counted on the element code, against the vector peak
         fl = FLOPS_PER_ELEM[dom] * E + FLOPS_PER_NODE[dom] * N
+        ach = fl / t_dom / 1e12
         peak = VALU_PEAK_TFLOPS[sz]
-        roof["alu"] = {"achieved_tflops": round(fl / t_dom / 1e12, 2), "peak_tflops": peak,
-                       "frac": round(fl / t_dom / 1e12 / peak, 4), "flops_per_launch": fl,
-                       "flops_per_byte": round(fl / (dom_bytes / max(dom_n, 1)), 2)}
+        roof = {"bound": "alu", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": traffic,
+                "peak_without_packed_fp32": VALU_PEAK_TFLOPS[8], "frac_without_packed_fp32": round(ach / VALU_PEAK_TFLOPS[8], 4),
+                "flops_per_launch": fl, "hbm": hbm}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "bytes_per_launch": hbm["bytes_per_launch"]}
+    roof.update({"kernel": KERNEL_NAMES[dom].format(t=tname), "class": dom, "launch_us": round(t_dom * 1e6, 2),
+                 "launches": dom_n, "share_of_kernel_time": round(share, 3), "timed_step_ms": round(t_step_timed * 1e3, 3)})
     result = {
         "metric": "state+adjoint solve s at 1M elems",
         "value": round(t_step, 5),
@@ -302,6 +462,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args, E)
+    sol.close()
+    if args.report:
+        report(args, args.report)
     print(json.dumps(result), flush=True)
 
 

@@ -74,8 +74,10 @@ typedef struct nc_problem {
   double krylov_rtol;         /* relative tolerance of each inner linear solve           */
   double adjoint_rtol;        /* relative residual of the adjoint solve                  */
   int    newton_maxit, krylov_restart, krylov_maxit;
-  int    smooth_pre, smooth_post; /* damped block-Jacobi sweeps                          */
+  int    smooth_pre, smooth_post; /* block-Jacobi sweeps before / after the coarse-grid
+                                    correction on the finest level (pre >= 1)             */
   double smooth_omega;        /* block-Jacobi damping                                    */
+  int    smooth_pre_coarse, smooth_post_coarse; /* the same on the coarser levels        */
 } nc_problem;
 
 typedef struct nc_info {
@@ -154,11 +156,11 @@ int    nc_sensitivity(nc_ctx* ctx, const double* s_dev, const double* lam_dev, d
  * (launches) and, when bytes is non-NULL, bytes[k] (the algorithmic bytes of those
  * launches: every input read once, every output written once) for k < n over the kernel
  * classes 0 residual, 1 J v and 2 J^T w of the (P, T) Krylov solve, 3 smoothing sweep on the
- * finest grid, 4 transposed sweep on the finest grid, 5 multigrid residual, 6 node-block
- * diagonal, 7 velocity coupling, 8 grid transfers, 9 coarsest solve, 10 Krylov
- * multi-dot, 11 Krylov multi-axpy, 12 other vector kernels, 13 preconditioner setup,
- * 14 smoothing sweeps on coarser levels; returns the number of classes (15) or an error
- * code. */
+ * finest grid, 4 transposed sweep on the finest grid, 5 multigrid residual on the finest
+ * grid, 6 node-block diagonal, 7 velocity coupling, 8 grid transfers, 9 coarsest solve,
+ * 10 Krylov multi-dot, 11 Krylov multi-axpy, 12 other vector kernels, 13 preconditioner
+ * setup, 14 smoothing sweeps on coarser levels, 15 multigrid residuals on coarser levels;
+ * returns the number of classes (16) or an error code. */
 int    nc_set_timing(nc_ctx* ctx, int enable);
 int    nc_get_timing(nc_ctx* ctx, double* ms, long* counts, double* bytes, int n);
 

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstddef>
 #include <cstdint>
 
@@ -54,5 +55,27 @@ struct Patch {
 };
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Optional timing of the next kernel launch of the calling thread: when start is set, the
+// next launch() records its begin and end into (start, stop) as part of its own dispatch
+// (exact kernel duration, no marker packets around it) and clears the pair.
+struct LaunchTimer {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+inline LaunchTimer& launch_timer() {
+  static thread_local LaunchTimer t;
+  return t;
+}
+
+template <typename F, typename... Args>
+inline void launch(F kernel, dim3 grid, dim3 block, unsigned shm, hipStream_t st, Args... args) {
+  LaunchTimer& lt = launch_timer();
+  if (lt.start) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, st, lt.start, lt.stop, 0, args...);
+    lt.start = lt.stop = nullptr;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
+  }
+}
 
 }  // namespace nc

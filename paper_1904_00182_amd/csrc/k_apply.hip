@@ -18,6 +18,8 @@
 
 namespace nc {
 
+constexpr unsigned NXCD = 8;   // accelerator complex dies of the MI355X
+
 // FINE: 1 for launches on the finest grid, 0 on coarser multigrid levels (the same code;
 // separate instantiations keep the two apart in kernel traces).
 template <class Op, int TX, int TY, int FINE>
@@ -27,9 +29,17 @@ __global__ __launch_bounds__(TX* TY) void zmarch_kernel(const Op op, const int K
   __shared__ T xch[6 * NO * NT];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
   const int nx = op.g.nx, ny = op.g.ny, nz = op.g.nz;
-  const int i = (int)blockIdx.x * (TX - 1) - 1 + tx;
-  const int j = (int)blockIdx.y * (TY - 1) - 1 + ty;
-  const int K0 = (int)blockIdx.z * KZ;
+  // XCD-aware tile order: workgroups are dispatched round-robin over the XCDs by linear id,
+  // so id w runs on XCD w % NXCD; give each XCD one contiguous range of tiles (x fastest,
+  // then y, then z chunks) so that tiles sharing halo nodes share that XCD's L2
+  const unsigned nbx = gridDim.x, nby = gridDim.y, total = nbx * nby * gridDim.z;
+  const unsigned wid = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+  const unsigned per = total / NXCD, rem = total % NXCD, xcd = wid % NXCD, kk = wid / NXCD;
+  const unsigned tile = xcd < rem ? xcd * (per + 1) + kk : rem * (per + 1) + (xcd - rem) * per + kk;
+  const int bx = (int)(tile % nbx), by = (int)((tile / nbx) % nby), bz = (int)(tile / (nbx * nby));
+  const int i = bx * (TX - 1) - 1 + tx;
+  const int j = by * (TY - 1) - 1 + ty;
+  const int K0 = bz * KZ;
   const bool colok = i >= 0 && i < nx && j >= 0 && j < ny;
   const bool owner = tx >= 1 && ty >= 1 && i <= nx && j <= ny;
   const int kbeg = K0 > 0 ? K0 - 1 : 0;
@@ -127,7 +137,7 @@ static void run_zmarch_t(hipStream_t st, const Op& op) {
   const int KZ = std::max(kzmin, ceil_div(g.nz + 1, want));
   const int chunks = ceil_div(g.nz + 1, KZ);
   dim3 grid(tiles_x, tiles_y, chunks), block(TX, TY, 1);
-  hipLaunchKernelGGL((zmarch_kernel<Op, TX, TY, FINE>), grid, block, 0, st, op, KZ);
+  launch((zmarch_kernel<Op, TX, TY, FINE>), grid, block, 0, st, op, KZ);
 }
 
 template <class Op, int FINE = 1>

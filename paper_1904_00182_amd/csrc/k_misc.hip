@@ -44,25 +44,33 @@ __global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf
   const PlaneIdx q = plane_idx(coarse);
   if (!q.ok) return;
   const int I = q.i, J = q.j, K = q.k;
+  // the 27 taps, clamped into the grid with weight 0 outside it, so that every load is
+  // independent of the others
+  int ix[3], jy[3], kz[3];
+  double wx[3], wy[3], wz[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int i = 2 * I + d - 1, j = 2 * J + d - 1, k = 2 * K + d - 1;
+    const double w = d == 1 ? 1.0 : 0.5;
+    ix[d] = min(max(i, 0), fine.nx);
+    jy[d] = min(max(j, 0), fine.ny);
+    kz[d] = min(max(k, 0), fine.nz);
+    wx[d] = (i >= 0 && i <= fine.nx) ? w : 0.0;
+    wy[d] = (j >= 0 && j <= fine.ny) ? w : 0.0;
+    wz[d] = (k >= 0 && k <= fine.nz) ? w : 0.0;
+  }
   double sp = 0.0, stt = 0.0;
-  for (int dk = -1; dk <= 1; ++dk) {
-    const int k = 2 * K + dk;
-    if (k < 0 || k > fine.nz) continue;
-    const double wk = dk == 0 ? 1.0 : 0.5;
-    for (int dj = -1; dj <= 1; ++dj) {
-      const int j = 2 * J + dj;
-      if (j < 0 || j > fine.ny) continue;
-      const double wj = wk * (dj == 0 ? 1.0 : 0.5);
-      for (int di = -1; di <= 1; ++di) {
-        const int i = 2 * I + di;
-        if (i < 0 || i > fine.nx) continue;
-        const double w = wj * (di == 0 ? 1.0 : 0.5);
-        const int m = fine.node(i, j, k);
+#pragma unroll
+  for (int dk = 0; dk < 3; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+      for (int di = 0; di < 3; ++di) {
+        const double w = wz[dk] * wy[dj] * wx[di];
+        const int m = fine.node(ix[di], jy[dj], kz[dk]);
         sp += w * (double)rf[2 * m];
         stt += w * (double)rf[2 * m + 1];
       }
-    }
-  }
   const int n = coarse.node(I, J, K);
   const T bp = coarse.pfix(I, J, K) ? (T)0 : (T)sp;
   const T bt = coarse.tfix(I, J, K) ? (T)0 : (T)stt;
@@ -75,19 +83,26 @@ __global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf
   }
 }
 
-// Trilinear prolongation added to the fine iterate; one thread per fine node.
+// Trilinear prolongation added to the fine iterate; one thread per fine node, the eight
+// coarse taps loaded together (a tap repeated with weight 0 where the fine node lies on a
+// coarse plane).
 template <typename T>
 __global__ void prolong_kernel(Grid fine, Grid coarse, const T* __restrict__ xc, T* __restrict__ xf) {
   const PlaneIdx q = plane_idx(fine);
   if (!q.ok) return;
   const int i = q.i, j = q.j, k = q.k;
   const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
-  const double w = ((i & 1) ? 0.5 : 1.0) * ((j & 1) ? 0.5 : 1.0) * ((k & 1) ? 0.5 : 1.0);
+  const double wi[2] = {(i & 1) ? 0.5 : 1.0, (i & 1) ? 0.5 : 0.0};
+  const double wj[2] = {(j & 1) ? 0.5 : 1.0, (j & 1) ? 0.5 : 0.0};
+  const double wk[2] = {(k & 1) ? 0.5 : 1.0, (k & 1) ? 0.5 : 0.0};
   double sp = 0.0, stt = 0.0;
-  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
-  for (int c = 0; c < nk; ++c)
-    for (int b = 0; b < nj; ++b)
-      for (int a = 0; a < ni; ++a) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const double w = wi[a] * wj[b] * wk[c];
         const int m = coarse.node(a ? i1 : i0, b ? j1 : j0, c ? k1 : k0);
         sp += w * (double)xc[2 * m];
         stt += w * (double)xc[2 * m + 1];
@@ -129,20 +144,20 @@ __global__ void average_coef_kernel(Grid fine, Grid coarse, const T* __restrict_
 template <typename T>
 void launch_restrict(hipStream_t st, const Grid& fine, const Grid& coarse, const T* rf, T* bc, const T* dinv,
                      bool transpose, T omega, T* xc) {
-  hipLaunchKernelGGL(restrict_kernel<T>, plane_grid(coarse, 128), dim3(128), 0, st, fine, coarse, rf, bc, dinv,
+  launch(restrict_kernel<T>, plane_grid(coarse, 128), dim3(128), 0, st, fine, coarse, rf, bc, dinv,
                      transpose ? 1 : 0, omega, xc);
 }
 template <typename T>
 void launch_prolong_add(hipStream_t st, const Grid& fine, const Grid& coarse, const T* xc, T* xf) {
-  hipLaunchKernelGGL(prolong_kernel<T>, plane_grid(fine, 256), dim3(256), 0, st, fine, coarse, xc, xf);
+  launch(prolong_kernel<T>, plane_grid(fine, 256), dim3(256), 0, st, fine, coarse, xc, xf);
 }
 template <typename T>
 void launch_inject_state(hipStream_t st, const Grid& fine, const Grid& coarse, const T* sf, T* sc) {
-  hipLaunchKernelGGL(inject_kernel<T>, dim3(blocks_for(coarse.nodes())), dim3(BS), 0, st, fine, coarse, sf, sc);
+  launch(inject_kernel<T>, dim3(blocks_for(coarse.nodes())), dim3(BS), 0, st, fine, coarse, sf, sc);
 }
 template <typename T>
 void launch_average_coef(hipStream_t st, const Grid& fine, const Grid& coarse, const T* cf, T* cc) {
-  hipLaunchKernelGGL(average_coef_kernel<T>, dim3(blocks_for(coarse.elems())), dim3(BS), 0, st, fine, coarse, cf, cc);
+  launch(average_coef_kernel<T>, dim3(blocks_for(coarse.elems())), dim3(BS), 0, st, fine, coarse, cf, cc);
 }
 
 // ------------------------------------------------------------------ coarsest level
@@ -212,9 +227,9 @@ __global__ void dense_assemble_kernel(Grid g, const double* __restrict__ mats, d
 template <typename T>
 void launch_coarse_assemble(hipStream_t st, const LevelView<T>& L, double* elem_mats, double* A) {
   const long E = L.g.elems();
-  hipLaunchKernelGGL(elem_matrix_kernel<T>, dim3(blocks_for(E * 16)), dim3(BS), 0, st, L, elem_mats);
+  launch(elem_matrix_kernel<T>, dim3(blocks_for(E * 16)), dim3(BS), 0, st, L, elem_mats);
   const long n = 2 * L.g.nodes();
-  hipLaunchKernelGGL(dense_assemble_kernel, dim3(blocks_for(n * n)), dim3(BS), 0, st, L.g, elem_mats, A);
+  launch(dense_assemble_kernel, dim3(blocks_for(n * n)), dim3(BS), 0, st, L.g, elem_mats, A);
 }
 
 // In-place Gauss-Jordan inversion with partial pivoting in one workgroup.
@@ -410,9 +425,9 @@ __global__ __launch_bounds__(1024) void gauss_jordan_small_kernel(double* __rest
 
 void launch_gauss_jordan(hipStream_t st, double* A, int n, int* perm) {
   if (n <= GJS_NMAX)
-    hipLaunchKernelGGL(gauss_jordan_small_kernel, dim3(1), dim3(1024), 0, st, A, n, perm);
+    launch(gauss_jordan_small_kernel, dim3(1), dim3(1024), 0, st, A, n, perm);
   else
-    hipLaunchKernelGGL(gauss_jordan_kernel, dim3(1), dim3(GJ_THREADS), sizeof(double) * n, st, A, n, perm);
+    launch(gauss_jordan_kernel, dim3(1), dim3(GJ_THREADS), sizeof(double) * n, st, A, n, perm);
 }
 
 // x = Ainv b (one wave per row) or x = Ainv^T b (one thread per column)
@@ -440,7 +455,7 @@ __global__ void dense_apply_kernel(const double* __restrict__ Ainv, int n, int t
 template <typename T>
 void launch_dense_apply(hipStream_t st, const double* Ainv, int n, bool transpose, const T* b, T* x) {
   const double* M = transpose ? Ainv + (long)n * n : Ainv;
-  hipLaunchKernelGGL(dense_apply_kernel<T>, dim3(ceil_div((long)n * 64, BS)), dim3(BS), 0, st, M, n, 0, b, x);
+  launch(dense_apply_kernel<T>, dim3(ceil_div((long)n * 64, BS)), dim3(BS), 0, st, M, n, 0, b, x);
 }
 
 __global__ void transpose_kernel(const double* __restrict__ A, double* __restrict__ At, int n) {
@@ -450,7 +465,7 @@ __global__ void transpose_kernel(const double* __restrict__ A, double* __restric
   At[c * n + r] = A[t];
 }
 void launch_dense_transpose(hipStream_t st, const double* A, double* At, int n) {
-  hipLaunchKernelGGL(transpose_kernel, dim3(blocks_for((long)n * n)), dim3(BS), 0, st, A, At, n);
+  launch(transpose_kernel, dim3(blocks_for((long)n * n)), dim3(BS), 0, st, A, At, n);
 }
 
 // ------------------------------------------------------------------ state / vectors
@@ -463,7 +478,7 @@ __global__ void pack_state_kernel(long N, const double* __restrict__ s5, T* __re
 }
 template <typename T>
 void launch_pack_state(hipStream_t st, const Grid& g, const double* s5, T* pt) {
-  hipLaunchKernelGGL(pack_state_kernel<T>, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g.nodes(), s5, pt);
+  launch(pack_state_kernel<T>, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g.nodes(), s5, pt);
 }
 
 // Preconditioner input of the (P, T) Krylov solve (see kernels.hpp)
@@ -484,7 +499,7 @@ __global__ void pc_in_kernel(Grid g, const T* __restrict__ v, T inv_p, T inv_t, 
 template <typename T>
 void launch_pc_in(hipStream_t st, const Grid& g, const T* v, T inv_p, T inv_t, const T* dinv, bool transpose,
                   T omega, T* b, T* x) {
-  hipLaunchKernelGGL(pc_in_kernel<T>, plane_grid(g, 256), dim3(256), 0, st, g, v, inv_p, inv_t, dinv,
+  launch(pc_in_kernel<T>, plane_grid(g, 256), dim3(256), 0, st, g, v, inv_p, inv_t, dinv,
                      transpose ? 1 : 0, omega, b, x);
 }
 
@@ -497,7 +512,7 @@ __global__ void pack_pt_kernel(long nodes, const double* __restrict__ r5, T* __r
 }
 template <typename T>
 void launch_pack_pt(hipStream_t st, long nodes, const double* r5, T* out, double s_p, double s_t) {
-  hipLaunchKernelGGL(pack_pt_kernel<T>, dim3(std::min(blocks_for(nodes), 4096)), dim3(BS), 0, st, nodes, r5, out, s_p,
+  launch(pack_pt_kernel<T>, dim3(std::min(blocks_for(nodes), 4096)), dim3(BS), 0, st, nodes, r5, out, s_p,
                      s_t);
 }
 
@@ -510,7 +525,7 @@ __global__ void scale2_kernel(long nodes, const Ta* __restrict__ in, Tb* __restr
 }
 template <typename Ta, typename Tb>
 void launch_scale2(hipStream_t st, long nodes, const Ta* in, Tb* out, double s_p, double s_t) {
-  hipLaunchKernelGGL((scale2_kernel<Ta, Tb>), dim3(std::min(blocks_for(nodes), 4096)), dim3(BS), 0, st, nodes, in, out,
+  launch((scale2_kernel<Ta, Tb>), dim3(std::min(blocks_for(nodes), 4096)), dim3(BS), 0, st, nodes, in, out,
                      s_p, s_t);
 }
 
@@ -524,7 +539,7 @@ __global__ void unpack_pt_kernel(Grid g, const T* __restrict__ x, double* __rest
 }
 template <typename T>
 void launch_unpack_pt(hipStream_t st, const Grid& g, const T* x, double* out5) {
-  hipLaunchKernelGGL(unpack_pt_kernel<T>, plane_grid(g, 256), dim3(256), 0, st, g, x, out5);
+  launch(unpack_pt_kernel<T>, plane_grid(g, 256), dim3(256), 0, st, g, x, out5);
 }
 
 __global__ void mask_state_kernel(Grid g, double* __restrict__ s5) {
@@ -535,7 +550,7 @@ __global__ void mask_state_kernel(Grid g, double* __restrict__ s5) {
   if (g.tfix(i, j, k)) s5[5 * n + 4] = 0.0;
 }
 void launch_mask_state(hipStream_t st, const Grid& g, double* s5) {
-  hipLaunchKernelGGL(mask_state_kernel, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, s5);
+  launch(mask_state_kernel, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, s5);
 }
 
 template <typename Ta, typename Tb>
@@ -545,7 +560,7 @@ __global__ void convert_kernel(const Ta* __restrict__ a, Tb* __restrict__ b, lon
 }
 template <typename Ta, typename Tb>
 void launch_convert(hipStream_t st, const Ta* a, Tb* b, long n, double scale) {
-  hipLaunchKernelGGL((convert_kernel<Ta, Tb>), dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, a, b, n, scale);
+  launch((convert_kernel<Ta, Tb>), dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, a, b, n, scale);
 }
 
 __global__ void axpy_kernel(double a, const double* __restrict__ x, const double* __restrict__ y, double* __restrict__ out, long n) {
@@ -553,7 +568,7 @@ __global__ void axpy_kernel(double a, const double* __restrict__ x, const double
     out[t] = a * x[t] + y[t];
 }
 void launch_axpy(hipStream_t st, double a, const double* x, const double* y, double* out, long n) {
-  hipLaunchKernelGGL(axpy_kernel, dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, a, x, y, out, n);
+  launch(axpy_kernel, dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, a, x, y, out, n);
 }
 
 
@@ -575,7 +590,7 @@ __global__ void diag_scale_kernel(long N, const T* __restrict__ dinv, int transp
 }
 template <typename T>
 void launch_diag_scale(hipStream_t st, const Grid& g, const T* dinv, bool transpose, T omega, const T* b, T* x) {
-  hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g.nodes(), dinv,
+  launch(diag_scale_kernel<T>, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g.nodes(), dinv,
                      transpose ? 1 : 0, omega, b, x);
 }
 
@@ -587,7 +602,7 @@ __global__ void rsub_kernel(const T* __restrict__ b, T* __restrict__ out, long n
 }
 template <typename T>
 void launch_rsub(hipStream_t st, const T* b, T* out, long n) {
-  hipLaunchKernelGGL(rsub_kernel<T>, dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, b, out, n);
+  launch(rsub_kernel<T>, dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, b, out, n);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -749,8 +764,8 @@ void launch_mdot(hipStream_t st, const T* V, long ld, int cnt, const T* w, long 
                  bool with_norm) {
   const int nb = stream_blocks<T>(n);
   const int ncol = cnt + (with_norm ? 1 : 0);
-  hipLaunchKernelGGL(mdot_kernel<T>, dim3(nb), dim3(KBS), 0, st, V, ld, cnt, w, n, with_norm ? 1 : 0, part);
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(KBS), 0, st, part, (long)RED_BLOCKS, nb, ncol, ncol, out);
+  launch(mdot_kernel<T>, dim3(nb), dim3(KBS), 0, st, V, ld, cnt, w, n, with_norm ? 1 : 0, part);
+  launch(reduce_cols_kernel, dim3(1), dim3(KBS), 0, st, part, (long)RED_BLOCKS, nb, ncol, ncol, out);
 }
 
 // out[c] = sum over blocks of part[b][c] in a fixed order; sqrt if do_sqrt.  One block of
@@ -862,10 +877,10 @@ template <typename T>
 void launch_maxpy(hipStream_t st, const T* V, long ld, int cnt, const double* h, double sign, T* w, long n, double* part,
                   double* nrm_out) {
   const int nb = stream_blocks<T>(n);
-  hipLaunchKernelGGL(maxpy_kernel<T>, dim3(nb), dim3(KBS), 0, st, V, ld, cnt, h, sign, w, n,
+  launch(maxpy_kernel<T>, dim3(nb), dim3(KBS), 0, st, V, ld, cnt, h, sign, w, n,
                      nrm_out ? part : nullptr);
   if (nrm_out)
-    hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(KBS), 0, st, part, (long)RED_BLOCKS, nb, 1, 0, nrm_out);
+    launch(reduce_cols_kernel, dim3(1), dim3(KBS), 0, st, part, (long)RED_BLOCKS, nb, 1, 0, nrm_out);
 }
 
 template <typename T>
@@ -876,7 +891,7 @@ __global__ void scale_inv_kernel(const double* __restrict__ nrm, const T* __rest
 }
 template <typename T>
 void launch_scale_inv(hipStream_t st, const double* nrm, const T* w, T* v, long n) {
-  hipLaunchKernelGGL(scale_inv_kernel<T>, dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, nrm, w, v, n);
+  launch(scale_inv_kernel<T>, dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, nrm, w, v, n);
 }
 
 template <typename T>
@@ -898,8 +913,8 @@ __global__ __launch_bounds__(BS) void norm_kernel(const T* __restrict__ a, long 
 }
 template <typename T>
 void launch_norm(hipStream_t st, const T* a, long n, double* part, double* out) {
-  hipLaunchKernelGGL(norm_kernel<T>, dim3(RED_BLOCKS), dim3(BS), 0, st, a, n, part);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 1);
+  launch(norm_kernel<T>, dim3(RED_BLOCKS), dim3(BS), 0, st, a, n, part);
+  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 1);
 }
 
 __global__ __launch_bounds__(BS) void field_norms_kernel(const double* __restrict__ a, const double* __restrict__ b,
@@ -933,8 +948,8 @@ __global__ __launch_bounds__(BS) void field_norms_kernel(const double* __restric
   }
 }
 void launch_field_norms(hipStream_t st, const double* a, const double* b, long nodes, double* part, double* out) {
-  hipLaunchKernelGGL(field_norms_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, a, b, nodes, part);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 10, out, 1);
+  launch(field_norms_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, a, b, nodes, part);
+  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 10, out, 1);
 }
 
 // ------------------------------------------------------------------ design chain
@@ -986,10 +1001,10 @@ void launch_cone_filter(hipStream_t st, const Grid& g, double radius, const doub
   }
   const int r = (int)ceil(radius);
   if (!transpose) {
-    hipLaunchKernelGGL(cone_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, g, radius, r, x, y, 0);
+    launch(cone_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, g, radius, r, x, y, 0);
   } else {
-    hipLaunchKernelGGL(cone_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, g, radius, r, x, tmp, 1);
-    hipLaunchKernelGGL(cone_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, g, radius, r, tmp, y, 2);
+    launch(cone_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, g, radius, r, x, tmp, 1);
+    launch(cone_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, g, radius, r, tmp, y, 2);
   }
 }
 
@@ -1009,7 +1024,7 @@ __global__ void ramp_kernel(long E, const double* __restrict__ gam, double k_f, 
 }
 void launch_ramp(hipStream_t st, long E, const double* gamma, double k_f, double k_s, double q_c, double kap_f,
                  double kap_s, double q_p, double* coef64, float* coef32, double* dk, double* dkap) {
-  hipLaunchKernelGGL(ramp_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, E, gamma, k_f, k_s, q_c, kap_f, kap_s, q_p,
+  launch(ramp_kernel, dim3(blocks_for(E)), dim3(BS), 0, st, E, gamma, k_f, k_s, q_c, kap_f, kap_s, q_p,
                      coef64, coef32, dk, dkap);
 }
 
@@ -1036,7 +1051,7 @@ __global__ void sensitivity_kernel(Grid g, ElemConst<double> c, const double* __
 }
 void launch_sensitivity(hipStream_t st, const Grid& g, const ElemConst<double>& c, const double* coef,
                         const double* dk, const double* dkap, const double* s5, const double* lam5, double* out) {
-  hipLaunchKernelGGL(sensitivity_kernel, dim3(blocks_for(g.elems())), dim3(BS), 0, st, g, c, coef, dk, dkap, s5, lam5, out);
+  launch(sensitivity_kernel, dim3(blocks_for(g.elems())), dim3(BS), 0, st, g, c, coef, dk, dkap, s5, lam5, out);
 }
 
 // ------------------------------------------------------------------ coefficient means
@@ -1058,8 +1073,8 @@ __global__ __launch_bounds__(BS) void coef_sum_kernel(const double* __restrict__
   }
 }
 void launch_coef_sums(hipStream_t st, const double* coef, long E, double* part, double* out) {
-  hipLaunchKernelGGL(coef_sum_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, coef, E, part);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 2, out, 0);
+  launch(coef_sum_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, coef, E, part);
+  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 2, out, 0);
 }
 
 // ------------------------------------------------------------------ objective
@@ -1084,8 +1099,8 @@ __global__ __launch_bounds__(BS) void objective_kernel(Grid g, Patch pa, const d
   }
 }
 void launch_objective(hipStream_t st, const Grid& g, const Patch& patch, const double* s5, double* part, double* out) {
-  hipLaunchKernelGGL(objective_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, g, patch, s5, part);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 0);
+  launch(objective_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, g, patch, s5, part);
+  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 0);
 }
 
 __global__ void objective_grad_kernel(Grid g, Patch pa, double* __restrict__ g5) {
@@ -1104,7 +1119,7 @@ __global__ void objective_grad_kernel(Grid g, Patch pa, double* __restrict__ g5)
   g5[5 * n + 4] = v;
 }
 void launch_objective_grad(hipStream_t st, const Grid& g, const Patch& patch, double* g5) {
-  hipLaunchKernelGGL(objective_grad_kernel, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, patch, g5);
+  launch(objective_grad_kernel, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, patch, g5);
 }
 
 // ------------------------------------------------------------------ instantiations

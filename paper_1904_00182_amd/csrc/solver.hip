@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -54,7 +55,7 @@ struct HipError {
 // Kernel classes of the per-context event timer (nc_set_timing / nc_get_timing).
 enum TimerClass {
   TC_RESIDUAL = 0, TC_JV, TC_JTW, TC_SMOOTH, TC_SMOOTH_T, TC_PT_RESID, TC_DIAG, TC_UPROJ, TC_TRANSFER,
-  TC_COARSE, TC_MDOT, TC_MAXPY, TC_VECTOR, TC_SETUP, TC_SMOOTH_COARSE, TC_COUNT
+  TC_COARSE, TC_MDOT, TC_MAXPY, TC_VECTOR, TC_SETUP, TC_SMOOTH_COARSE, TC_PT_RESID_COARSE, TC_COUNT
 };
 constexpr int TIMER_EVENTS = 8192;
 
@@ -86,6 +87,8 @@ struct nc_ctx {
   // reductions
   double *part, *dres;
   double* hbuf;          // pinned host mirror of dres
+  double* hslots;        // pinned: one Hessenberg column (h1, h2, norm) per Krylov iteration
+  std::vector<hipEvent_t> kev;   // completion of each Krylov iteration's column copy
   // float64 Newton / adjoint vectors
   double *R, *d, *strial, *ra, *tmp5;
   double* pt64;          // float64 (P, T) vector of the reduced solves
@@ -133,10 +136,18 @@ struct Timed {
     k = c->ev_used++;
     c->ev_class[k] = cls;
     c->ev_bytes[k] = bytes;
+    // bracket the scope; the first kernel launched in it re-records both events inside
+    // its own dispatch (launch_timer), so the class time is that kernel's duration
     ck(hipEventRecord(c->ev[2 * k], c->stream));
+    launch_timer() = LaunchTimer{c->ev[2 * k], c->ev[2 * k + 1]};
   }
   ~Timed() {
-    if (k >= 0) (void)hipEventRecord(c->ev[2 * k + 1], c->stream);
+    if (k < 0) return;
+    LaunchTimer& lt = launch_timer();
+    if (lt.start) {   // no kernel in the scope
+      (void)hipEventRecord(c->ev[2 * k + 1], c->stream);
+      lt = LaunchTimer{};
+    }
   }
 };
 
@@ -151,6 +162,7 @@ bool valid_problem(const nc_problem* p) {
   if (p->mu <= 0 || p->kappa_s <= 0 || p->kappa_f <= 0 || p->k_f <= 0 || p->k_s <= 0) return false;
   if (p->precision != NC_FP64 && p->precision != NC_MIXED) return false;
   if (p->krylov_restart < 1 || p->krylov_restart > MAXC - 2) return false;
+  if (p->smooth_pre < 1 || p->smooth_post < 0 || p->smooth_pre_coarse < 1 || p->smooth_post_coarse < 0) return false;
   return true;
 }
 
@@ -257,12 +269,14 @@ void linearize_levels(nc_ctx* c) {
     else
       launch_inject_state<float>(st, c->lev[l - 1].g, c->lev[l].g, c->lev[l - 1].st32, c->lev[l].st32);
   }
-  Timed tm(c, TC_SETUP);
-  for (int l = 0; l < c->L; ++l) launch_diag_inverse<T>(st, view<T>(c, l), (T*)c->lev[l].dinv);
+  for (int l = 0; l < c->L; ++l) {
+    Timed tm(c, TC_SETUP);
+    launch_diag_inverse<T>(st, view<T>(c, l), (T*)c->lev[l].dinv);
+  }
   if (c->dense) {
-    launch_coarse_assemble<T>(st, view<T>(c, c->L - 1), c->emats, c->A);
-    launch_gauss_jordan(st, c->A, c->ncoarse, c->perm);
-    launch_dense_transpose(st, c->A, c->A + (size_t)c->ncoarse * c->ncoarse, c->ncoarse);
+    { Timed tm(c, TC_SETUP); launch_coarse_assemble<T>(st, view<T>(c, c->L - 1), c->emats, c->A); }
+    { Timed tm(c, TC_SETUP); launch_gauss_jordan(st, c->A, c->ncoarse, c->perm); }
+    { Timed tm(c, TC_SETUP); launch_dense_transpose(st, c->A, c->A + (size_t)c->ncoarse * c->ncoarse, c->ncoarse); }
   }
 }
 
@@ -310,9 +324,11 @@ void vcycle(nc_ctx* c, int l, bool tr, bool x_ready = false) {
     }
     return;
   }
+  const int npre = l == 0 ? c->p.smooth_pre : c->p.smooth_pre_coarse;
+  const int npost = l == 0 ? c->p.smooth_post : c->p.smooth_post_coarse;
   first_step();
-  for (int s = 1; s < c->p.smooth_pre; ++s) sweep();
-  { Timed tm(c, TC_PT_RESID, sizeof(T) * (8 * nn(L.g) + 2 * ne(L.g))); launch_pt_apply<T>(st, v, tr, MODE_RESID, (const T*)L.x, (const T*)L.b, (T*)L.r, om, l == 0); }
+  for (int s = 1; s < npre; ++s) sweep();
+  { Timed tm(c, l == 0 ? TC_PT_RESID : TC_PT_RESID_COARSE, sizeof(T) * (8 * nn(L.g) + 2 * ne(L.g))); launch_pt_apply<T>(st, v, tr, MODE_RESID, (const T*)L.x, (const T*)L.b, (T*)L.r, om, l == 0); }
   Level& C = c->lev[l + 1];
   // the coarse level's first smoothing step rides along with the restriction, except on a
   // coarsest level solved by the dense inverse
@@ -323,7 +339,7 @@ void vcycle(nc_ctx* c, int l, bool tr, bool x_ready = false) {
   }
   vcycle<T>(c, l + 1, tr, fuse);
   { Timed tm(c, TC_TRANSFER, sizeof(T) * (4 * nn(L.g) + 2 * nn(C.g))); launch_prolong_add<T>(st, L.g, C.g, (const T*)C.x, (T*)L.x); }
-  for (int s = 0; s < c->p.smooth_post; ++s) sweep();
+  for (int s = 0; s < npost; ++s) sweep();
 }
 
 // Block-Jacobi sweeps on the finest level after its first damped step (each swaps x, x2).
@@ -381,9 +397,15 @@ void compute_row_scales(nc_ctx* c) {
 }
 
 // ------------------------------------------------------------------ flexible GMRES
+constexpr int HSLOT = 2 * MAXC + 8;   // doubles per Hessenberg slot: h1 [MAXC], h2 [MAXC], norm
+
 // Solves D A x = b (A the (P, T) block of J~, A^T when tr, D the P and T row scales) from
-// x = 0 with right preconditioning; classical Gram-Schmidt, repeated when the projection
-// removed most of the vector; Hessenberg least squares on the host.
+// x = 0 with right preconditioning.  Each Arnoldi step orthogonalises by classical
+// Gram-Schmidt applied twice ("twice is enough", Kahan and Parlett) entirely on the
+// device and copies its Hessenberg column to its own pinned slot.  The host runs one
+// step behind: it enqueues step j, then waits for and processes the column of step j-1
+// (Givens rotations, convergence test), so the device never idles on the host's round
+// trip; the step enqueued past convergence is discarded.
 template <typename T>
 int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double* relres) {
   hipStream_t st = c->stream;
@@ -403,36 +425,34 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
   double beta = bnorm;
   int total = 0;
   std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  // enqueue Arnoldi step j: z_j = M^-1 v_j, w = D A z_j, two Gram-Schmidt passes, v_{j+1}
+  auto enqueue = [&](int j) {
+    T* vj = V + (long)j * ld;
+    T* w = V + (long)(j + 1) * ld;
+    T* zj = Z + (long)j * ld;
+    precondition_pt<T>(c, tr, vj, zj, rows);
+    apply_pt<T>(c, tr, zj, w, rows);
+    for (int pass = 0; pass < 2; ++pass) {
+      { Timed tm(c, TC_MDOT, sizeof(T) * (double)(j + 2) * n); launch_mdot<T>(st, V, ld, j + 1, w, n, c->part, dres + pass * MAXC, false); }
+      { Timed tm(c, TC_MAXPY, sizeof(T) * (double)(j + 3) * n);
+        launch_maxpy<T>(st, V, ld, j + 1, dres + pass * MAXC, -1.0, w, n, c->part, pass ? dres + 2 * MAXC : nullptr); }
+    }
+    launch_scale_inv<T>(st, dres + 2 * MAXC, w, w, n);
+    ck(hipMemcpyAsync(c->hslots + (size_t)j * HSLOT, dres, sizeof(double) * (2 * MAXC + 1), hipMemcpyDeviceToHost, st));
+    ck(hipEventRecord(c->kev[j], st));
+  };
   while (true) {
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jend = 0;
-    bool done = false;
-    for (int j = 0; j < m; ++j) {
-      T* vj = V + (long)j * ld;
-      T* w = V + (long)(j + 1) * ld;
-      T* zj = Z + (long)j * ld;
-      precondition_pt<T>(c, tr, vj, zj, rows);
-      apply_pt<T>(c, tr, zj, w, rows);
-      // classical Gram-Schmidt, repeated only when the projection removed most of w
-      // ("twice is enough" criterion of Kahan and Parlett)
-      { Timed tm(c, TC_MDOT, sizeof(T) * (double)(j + 2) * n); launch_mdot<T>(st, V, ld, j + 1, w, n, c->part, dres, true); }
-      { Timed tm(c, TC_MAXPY, sizeof(T) * (double)(j + 3) * n); launch_maxpy<T>(st, V, ld, j + 1, dres, -1.0, w, n, c->part, dres + 2 * MAXC); }
-      fetch(c, dres, 2 * MAXC + 1);
-      double hsum[MAXC];
-      for (int i = 0; i <= j; ++i) hsum[i] = c->hbuf[i];
-      const double wn0 = std::sqrt(std::max(c->hbuf[j + 1], 0.0));
-      double hn = c->hbuf[2 * MAXC];
-      if (hn < 0.7 * wn0) {
-        { Timed tm(c, TC_MDOT, sizeof(T) * (double)(j + 2) * n); launch_mdot<T>(st, V, ld, j + 1, w, n, c->part, dres + MAXC, false); }
-        { Timed tm(c, TC_MAXPY, sizeof(T) * (double)(j + 3) * n); launch_maxpy<T>(st, V, ld, j + 1, dres + MAXC, -1.0, w, n, c->part, dres + 2 * MAXC); }
-        fetch(c, dres + MAXC, MAXC + 1);   // second projection and the final norm (dres[2 MAXC])
-        for (int i = 0; i <= j; ++i) hsum[i] += c->hbuf[i];
-        hn = c->hbuf[MAXC];
-      }
-      for (int i = 0; i <= j; ++i) H[i * m + j] = hsum[i];
+    bool done = false, stop = false, bad = false;
+    // process the column of step j; returns true when the cycle stops after it
+    auto process = [&](int j) -> bool {
+      ck(hipEventSynchronize(c->kev[j]));
+      const double* hs = c->hslots + (size_t)j * HSLOT;
+      for (int i = 0; i <= j; ++i) H[i * m + j] = hs[i] + hs[MAXC + i];
+      const double hn = hs[2 * MAXC];
       H[(j + 1) * m + j] = hn;
-      if (hn > 0.0) launch_scale_inv<T>(st, dres + 2 * MAXC, w, w, n);
       for (int i = 0; i < j; ++i) {
         const double a = H[i * m + j], bb = H[(i + 1) * m + j];
         H[i * m + j] = cs[i] * a + sn[i] * bb;
@@ -450,17 +470,25 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
       jend = j + 1;
       const double res = std::fabs(g[j + 1]) / bnorm;
       *relres = res;
-      if (!std::isfinite(res)) return -1;
-      if (res <= rtol || total >= maxit || hn == 0.0) {
-        done = true;
-        break;
-      }
+      if (!std::isfinite(res)) bad = true;
+      if (bad || res <= rtol || total >= maxit || hn == 0.0) done = true;
+      return done;
+    };
+    for (int j = 0; j < m && !stop; ++j) {
+      enqueue(j);
+      if (j > 0) stop = process(j - 1);
+    }
+    if (!stop) process(jend);   // the cycle's last step (jend == m - 1 here)
+    if (bad) {
+      sync(c);
+      return -1;
     }
     for (int i = jend - 1; i >= 0; --i) {
       double s = g[i];
       for (int k = i + 1; k < jend; ++k) s -= H[i * m + k] * y[k];
       y[i] = s / H[i * m + i];
     }
+    sync(c);   // the discarded speculative step has finished with dres
     std::memcpy(c->hbuf, y.data(), sizeof(double) * jend);
     ck(hipMemcpyAsync(dres + 3 * MAXC, c->hbuf, sizeof(double) * jend, hipMemcpyHostToDevice, st));
     launch_maxpy<T>(st, Z, ld, jend, dres + 3 * MAXC, 1.0, x, n, c->part, nullptr);
@@ -744,7 +772,9 @@ void nc_problem_default(nc_problem* p, int nx, int ny, int nz) {
   p->krylov_maxit = 400;
   p->smooth_pre = 2;
   p->smooth_post = 2;
-  p->smooth_omega = 0.8;
+  p->smooth_omega = 1.0;
+  p->smooth_pre_coarse = 1;
+  p->smooth_post_coarse = 1;
 }
 
 size_t nc_workspace_bytes(const nc_problem* p) {
@@ -776,7 +806,16 @@ int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stre
     c->hier_valid = false;
     c->timing = false;
     c->ev_used = 0;
+    c->kev.resize(MAXC);
+    for (auto& e : c->kev) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (hipHostMalloc((void**)&c->hslots, sizeof(double) * MAXC * HSLOT, hipHostMallocDefault) != hipSuccess) {
+      for (auto& e : c->kev) (void)hipEventDestroy(e);
+      delete c;
+      return NC_EHIP;
+    }
     if (hipHostMalloc((void**)&c->hbuf, sizeof(double) * 4 * MAXC, hipHostMallocDefault) != hipSuccess) {
+      for (auto& e : c->kev) (void)hipEventDestroy(e);
+      (void)hipHostFree(c->hslots);
       delete c;
       return NC_EHIP;
     }
@@ -789,7 +828,9 @@ int nc_destroy(nc_ctx* c) {
   if (!c) return NC_EINVAL;
   (void)hipStreamSynchronize(c->stream);
   for (auto& e : c->ev) (void)hipEventDestroy(e);
+  for (auto& e : c->kev) (void)hipEventDestroy(e);
   (void)hipHostFree(c->hbuf);
+  (void)hipHostFree(c->hslots);
   delete c;
   return NC_OK;
 }

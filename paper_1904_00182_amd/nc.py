@@ -24,7 +24,7 @@ EXPORTED = [
 ]
 
 TIMER_CLASSES = ["residual", "jv", "jtw", "smooth", "smooth_T", "pt_residual", "diag", "uproj", "transfer",
-                 "coarse", "mdot", "maxpy", "vector", "setup", "smooth_coarse"]
+                 "coarse", "mdot", "maxpy", "vector", "setup", "smooth_coarse", "pt_residual_coarse"]
 
 
 class NCProblem(ctypes.Structure):
@@ -46,6 +46,7 @@ class NCProblem(ctypes.Structure):
         ("newton_maxit", ctypes.c_int), ("krylov_restart", ctypes.c_int), ("krylov_maxit", ctypes.c_int),
         ("smooth_pre", ctypes.c_int), ("smooth_post", ctypes.c_int),
         ("smooth_omega", ctypes.c_double),
+        ("smooth_pre_coarse", ctypes.c_int), ("smooth_post_coarse", ctypes.c_int),
     ]
 
 

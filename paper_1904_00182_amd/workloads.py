@@ -31,7 +31,7 @@ def problem(grid, gr=1e3, precision=nc.NC_FP64, radius=0.0, q_h=1.0, **over):
     overrides replace any field (e.g. alpha=0 for pure conduction)."""
     nx, ny, nz = grid
     fields = dict(alpha=float(gr), kappa_f=KAPPA_F[float(gr)], precision=precision, filter_radius=float(radius),
-                  q_h=float(q_h), smooth_omega=0.8)
+                  q_h=float(q_h))
     fields.update(over)
     return nc.default_problem(nx, ny, nz, **fields)
 
