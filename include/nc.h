@@ -70,14 +70,17 @@ typedef struct nc_problem {
   double filter_radius;       /* cone density filter radius in element lengths; 0 = none */
   int    precision;           /* NC_FP64 or NC_MIXED                                     */
   int    levels;              /* multigrid levels; 0 = choose automatically              */
-  double newton_step_rtol;    /* stop after a full step with |ds_f| <= rtol |s_f| per field */
-  double krylov_rtol;         /* relative tolerance of each inner linear solve           */
+  double newton_step_rtol;    /* stop when a full step, or the error predicted to remain after
+                                 it, is <= rtol |s_f| per field                           */
+  double krylov_rtol;         /* relative tolerance of each linear solve (NC_FP64)       */
   double adjoint_rtol;        /* relative residual of the adjoint solve                  */
   int    newton_maxit, krylov_restart, krylov_maxit;
   int    smooth_pre, smooth_post; /* block-Jacobi sweeps before / after the coarse-grid
                                     correction on the finest level (pre >= 1)             */
   double smooth_omega;        /* block-Jacobi damping                                    */
   int    smooth_pre_coarse, smooth_post_coarse; /* the same on the coarser levels        */
+  double krylov_rtol_mixed;   /* relative tolerance of each float32 inner solve (NC_MIXED) */
+  int    gs_passes;           /* classical Gram-Schmidt passes per FGMRES step, 1 or 2   */
 } nc_problem;
 
 typedef struct nc_info {

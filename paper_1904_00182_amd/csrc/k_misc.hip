@@ -232,83 +232,17 @@ void launch_coarse_assemble(hipStream_t st, const LevelView<T>& L, double* elem_
   launch(dense_assemble_kernel, dim3(blocks_for(n * n)), dim3(BS), 0, st, L.g, elem_mats, A);
 }
 
-// In-place Gauss-Jordan inversion with partial pivoting in one workgroup.
-constexpr int GJ_THREADS = 1024;
-__global__ __launch_bounds__(GJ_THREADS) void gauss_jordan_kernel(double* __restrict__ A, int n, int* __restrict__ perm) {
-  __shared__ double sval[GJ_THREADS / 64];
-  __shared__ int sidx[GJ_THREADS / 64];
-  __shared__ int piv;
-  extern __shared__ double fcol[];   // n entries
-  const int tid = threadIdx.x;
-  for (int k = 0; k < n; ++k) {
-    // pivot search in column k, rows k..n-1
-    double best = -1.0;
-    int bi = k;
-    for (int r = k + tid; r < n; r += GJ_THREADS) {
-      const double v = fabs(A[(long)r * n + k]);
-      if (v > best) { best = v; bi = r; }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_down(best, off, 64);
-      const int oi = __shfl_down(bi, off, 64);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
-    if ((tid & 63) == 0) { sval[tid >> 6] = best; sidx[tid >> 6] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-      double b = sval[0];
-      int id = sidx[0];
-      for (int w = 1; w < GJ_THREADS / 64; ++w)
-        if (sval[w] > b || (sval[w] == b && sidx[w] < id)) { b = sval[w]; id = sidx[w]; }
-      piv = id;
-      perm[k] = id;
-    }
-    __syncthreads();
-    const int p = piv;
-    if (p != k) {
-      for (int c = tid; c < n; c += GJ_THREADS) {
-        const double a = A[(long)k * n + c];
-        A[(long)k * n + c] = A[(long)p * n + c];
-        A[(long)p * n + c] = a;
-      }
-    }
-    __syncthreads();
-    const double pv = A[(long)k * n + k];
-    __syncthreads();
-    const double ipv = 1.0 / pv;
-    for (int c = tid; c < n; c += GJ_THREADS) {
-      A[(long)k * n + c] = (c == k ? 1.0 : A[(long)k * n + c]) * ipv;
-    }
-    for (int r = tid; r < n; r += GJ_THREADS) fcol[r] = (r == k) ? 0.0 : A[(long)r * n + k];
-    __syncthreads();
-    // rows over waves, columns over lanes
-    for (int r = tid >> 6; r < n; r += GJ_THREADS / 64) {
-      if (r == k) continue;
-      const double f = fcol[r];
-      double* Ar = A + (long)r * n;
-      const double* Ak = A + (long)k * n;
-      for (int c = tid & 63; c < n; c += 64) Ar[c] = (c == k ? 0.0 : Ar[c]) - f * Ak[c];
-    }
-    __syncthreads();
-  }
-  // undo the row interchanges as column interchanges, in reverse order
-  for (int k = n - 1; k >= 0; --k) {
-    const int p = perm[k];
-    if (p != k) {
-      for (int r = tid; r < n; r += GJ_THREADS) {
-        const double a = A[(long)r * n + k];
-        A[(long)r * n + k] = A[(long)r * n + p];
-        A[(long)r * n + p] = a;
-      }
-    }
-    __syncthreads();
-  }
-}
+// In-place Gauss-Jordan inversion with partial pivoting: for pivot step k, the pivot p is
+// the first row r >= k of largest |A[r][k]|; rows k and p are interchanged, the pivot row is
+// scaled by 1 / A[p][k] (its column-k entry replaced by 1 first), and every other row r
+// subtracts A[r][k] times it (its column-k entry replaced by 0 first), which builds the
+// inverse in place.  The row interchanges are undone as column interchanges in reverse
+// order at the end.
 
 // The same inversion with the matrix held in registers, for n <= GJS_NMAX: row r belongs
 // to wave r % 16 (slot r / 16), column c to lane c % 64 (slot c / 64).  Each step puts the
 // pivot column and the old rows k and p in LDS; every thread then updates its entries with
-// the operations of gauss_jordan_kernel, in the same order.  The row interchanges are
+// the operations above, in the same order.  The row interchanges are
 // undone as one column permutation when the result is written back.
 constexpr int GJS_QR = 10, GJS_QC = 3, GJS_NMAX = 16 * GJS_QR;   // 64 * GJS_QC >= GJS_NMAX
 __global__ __launch_bounds__(1024) void gauss_jordan_small_kernel(double* __restrict__ A, int n, int* __restrict__ perm) {
@@ -423,11 +357,94 @@ __global__ __launch_bounds__(1024) void gauss_jordan_small_kernel(double* __rest
     }
 }
 
-void launch_gauss_jordan(hipStream_t st, double* A, int n, int* perm) {
-  if (n <= GJS_NMAX)
+// The same inversion for larger n over many workgroups, one launch per pivot step: every
+// block picks the pivot of column k from a contiguous copy of that column (same rule as
+// above), then all blocks update the matrix from Ain into Aout (two buffers, no in-place
+// hazards) with the same operations, and copy the new column k + 1 out.
+__global__ __launch_bounds__(256) void gj_column_kernel(const double* __restrict__ A, int n, int k,
+                                                         double* __restrict__ col) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) col[r] = A[(long)r * n + k];
+}
+__global__ __launch_bounds__(256) void gj_step_kernel(const double* __restrict__ Ain, double* __restrict__ Aout,
+                                                       const double* __restrict__ colk, double* __restrict__ colnext,
+                                                       int n, int k, int* __restrict__ perm) {
+  __shared__ int sp;
+  if (threadIdx.x < 64) {
+    double best = -1.0;
+    int bi = k;
+    for (int r = k + (int)threadIdx.x; r < n; r += 64) {
+      const double v = fabs(colk[r]);
+      if (v > best) { best = v; bi = r; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_down(best, off, 64);
+      const int oi = __shfl_down(bi, off, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (threadIdx.x == 0) sp = bi;
+  }
+  __syncthreads();
+  const int p = sp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) perm[k] = p;
+  const double ipv = 1.0 / Ain[(long)p * n + k];
+  const double fk = Ain[(long)k * n + k];
+  const int nn = n * n;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nn; t += gridDim.x * blockDim.x) {
+    const int r = t / n, c = t - r * n;
+    const double pr = (c == k ? 1.0 : Ain[(long)p * n + c]) * ipv;
+    double v;
+    if (r == k) v = pr;
+    else if (r == p) v = (c == k ? 0.0 : Ain[(long)k * n + c]) - fk * pr;
+    else v = (c == k ? 0.0 : Ain[t]) - colk[r] * pr;
+    Aout[t] = v;
+    if (c == k + 1) colnext[r] = v;
+  }
+}
+// inverse column map of the interchanges undone in reverse order (one block)
+__global__ __launch_bounds__(1024) void gj_colmap_kernel(const int* __restrict__ perm, int n, int* __restrict__ inv) {
+  extern __shared__ int sidx[];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sidx[j] = j;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = n - 1; k >= 0; --k) {
+      const int q = perm[k], tmp = sidx[k];
+      sidx[k] = sidx[q];
+      sidx[q] = tmp;
+    }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) inv[sidx[j]] = j;
+}
+__global__ __launch_bounds__(256) void gj_permute_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                                          int n, const int* __restrict__ inv) {
+  const int nn = n * n;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nn; t += gridDim.x * blockDim.x) {
+    const int r = t / n, c = t - r * n;
+    dst[(long)r * n + inv[c]] = src[t];
+  }
+}
+__global__ __launch_bounds__(256) void copy_f64_kernel(const double* __restrict__ a, double* __restrict__ b, long n) {
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) b[t] = a[t];
+}
+
+void launch_gauss_jordan(hipStream_t st, double* A, int n, int* perm, double* work) {
+  if (n <= GJS_NMAX) {
     launch(gauss_jordan_small_kernel, dim3(1), dim3(1024), 0, st, A, n, perm);
-  else
-    launch(gauss_jordan_kernel, dim3(1), dim3(GJ_THREADS), sizeof(double) * n, st, A, n, perm);
+    return;
+  }
+  // A holds 2 n^2 doubles (the inverse and, later, its transpose): both halves serve as
+  // the step buffers here; work holds two columns, perm 2 n ints
+  double* buf[2] = {A, A + (long)n * n};
+  const int nb = std::min(1024, ceil_div((long)n * n, 256));
+  launch(gj_column_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, (const double*)A, n, 0, work);
+  for (int k = 0; k < n; ++k)
+    launch(gj_step_kernel, dim3(nb), dim3(256), 0, st, (const double*)buf[k & 1], buf[(k + 1) & 1],
+           (const double*)(work + (long)(k & 1) * n), work + (long)((k + 1) & 1) * n, n, k, perm);
+  launch(gj_colmap_kernel, dim3(1), dim3(1024), sizeof(int) * n, st, (const int*)perm, n, perm + n);
+  double* src = buf[n & 1];
+  double* dst = buf[(n + 1) & 1];
+  launch(gj_permute_kernel, dim3(nb), dim3(256), 0, st, (const double*)src, dst, n, (const int*)(perm + n));
+  if (dst != A) launch(copy_f64_kernel, dim3(nb), dim3(256), 0, st, (const double*)dst, A, (long)n * n);
 }
 
 // x = Ainv b (one wave per row) or x = Ainv^T b (one thread per column)
@@ -483,13 +500,21 @@ void launch_pack_state(hipStream_t st, const Grid& g, const double* s5, T* pt) {
 
 // Preconditioner input of the (P, T) Krylov solve (see kernels.hpp)
 template <typename T>
-__global__ void pc_in_kernel(Grid g, const T* __restrict__ v, T inv_p, T inv_t, const T* __restrict__ dinv,
-                             int transpose, T omega, T* __restrict__ b, T* __restrict__ x) {
+__global__ void pc_in_kernel(Grid g, T* __restrict__ v, const double* __restrict__ nrm, T inv_p, T inv_t,
+                             const T* __restrict__ dinv, int transpose, T omega, T* __restrict__ b, T* __restrict__ x) {
   const PlaneIdx q = plane_idx(g);
   if (!q.ok) return;
   const int n = g.node(q.i, q.j, q.k);
-  const T bp = g.pfix(q.i, q.j, q.k) ? (T)0 : inv_p * v[2 * n];
-  const T bt = g.tfix(q.i, q.j, q.k) ? (T)0 : inv_t * v[2 * n + 1];
+  T vp = v[2 * n], vt = v[2 * n + 1];
+  if (nrm) {   // normalise the new Krylov vector in place (v <- v / |v|)
+    const double s = 1.0 / nrm[0];
+    vp = (T)(s * (double)vp);
+    vt = (T)(s * (double)vt);
+    v[2 * n] = vp;
+    v[2 * n + 1] = vt;
+  }
+  const T bp = g.pfix(q.i, q.j, q.k) ? (T)0 : inv_p * vp;
+  const T bt = g.tfix(q.i, q.j, q.k) ? (T)0 : inv_t * vt;
   b[2 * n] = bp;
   b[2 * n + 1] = bt;
   const T* D = dinv + 4 * n;
@@ -497,10 +522,10 @@ __global__ void pc_in_kernel(Grid g, const T* __restrict__ v, T inv_p, T inv_t, 
   x[2 * n + 1] = omega * (D[transpose ? 1 : 2] * bp + D[3] * bt);
 }
 template <typename T>
-void launch_pc_in(hipStream_t st, const Grid& g, const T* v, T inv_p, T inv_t, const T* dinv, bool transpose,
-                  T omega, T* b, T* x) {
-  launch(pc_in_kernel<T>, plane_grid(g, 256), dim3(256), 0, st, g, v, inv_p, inv_t, dinv,
-                     transpose ? 1 : 0, omega, b, x);
+void launch_pc_in(hipStream_t st, const Grid& g, T* v, const double* nrm, T inv_p, T inv_t, const T* dinv,
+                  bool transpose, T omega, T* b, T* x) {
+  launch(pc_in_kernel<T>, plane_grid(g, 256), dim3(256), 0, st, g, v, nrm, inv_p, inv_t, dinv, transpose ? 1 : 0,
+         omega, b, x);
 }
 
 template <typename T>
@@ -1131,7 +1156,7 @@ void launch_objective_grad(hipStream_t st, const Grid& g, const Patch& patch, do
   template void launch_coarse_assemble<T>(hipStream_t, const LevelView<T>&, double*, double*);      \
   template void launch_dense_apply<T>(hipStream_t, const double*, int, bool, const T*, T*);         \
   template void launch_pack_state<T>(hipStream_t, const Grid&, const double*, T*);                  \
-  template void launch_pc_in<T>(hipStream_t, const Grid&, const T*, T, T, const T*, bool, T, T*, T*); \
+  template void launch_pc_in<T>(hipStream_t, const Grid&, T*, const double*, T, T, const T*, bool, T, T*, T*); \
   template void launch_pack_pt<T>(hipStream_t, long, const double*, T*, double, double);             \
   template void launch_unpack_pt<T>(hipStream_t, const Grid&, const T*, double*);                    \
   template void launch_mdot<T>(hipStream_t, const T*, long, int, const T*, long, double*, double*, bool); \

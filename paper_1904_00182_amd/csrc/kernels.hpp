@@ -55,7 +55,9 @@ void launch_average_coef(hipStream_t st, const Grid& fine, const Grid& coarse, c
 // in-place Gauss-Jordan inverse with partial pivoting, dense (transposed) mat-vec
 template <typename T>
 void launch_coarse_assemble(hipStream_t st, const LevelView<T>& L, double* elem_mats, double* A);
-void launch_gauss_jordan(hipStream_t st, double* A, int n, int* perm);
+// In-place inverse of the dense n x n matrix A (row-major; A has room for 2 n^2 doubles),
+// Gauss-Jordan with partial pivoting; perm: 2 n ints, work: 2 n doubles of scratch.
+void launch_gauss_jordan(hipStream_t st, double* A, int n, int* perm, double* work);
 void launch_dense_transpose(hipStream_t st, const double* A, double* At, int n);
 template <typename T>
 void launch_dense_apply(hipStream_t st, const double* Ainv, int n, bool transpose, const T* b, T* x);
@@ -64,10 +66,11 @@ void launch_dense_apply(hipStream_t st, const double* Ainv, int n, bool transpos
 template <typename T>
 void launch_pack_state(hipStream_t st, const Grid& g, const double* s5, T* pt);           // (P, T) of s
 // Preconditioner input of the (P, T) Krylov solve: b = v / (s_P, s_T) (row scales undone;
-// constrained dofs 0) and the first damped block-Jacobi step x = omega D^-1 b (D^-T)
+// constrained dofs 0) and the first damped block-Jacobi step x = omega D^-1 b (D^-T).
+// With nrm (device scalar), v is first normalised in place: v <- v / nrm[0].
 template <typename T>
-void launch_pc_in(hipStream_t st, const Grid& g, const T* v, T inv_p, T inv_t, const T* dinv, bool transpose,
-                  T omega, T* b, T* x);
+void launch_pc_in(hipStream_t st, const Grid& g, T* v, const double* nrm, T inv_p, T inv_t, const T* dinv,
+                  bool transpose, T omega, T* b, T* x);
 // out[n][f] = s_f * r5[n][3 + f] (the (P, T) entries of a five-field float64 vector)
 template <typename T>
 void launch_pack_pt(hipStream_t st, long nodes, const double* r5, T* out, double s_p, double s_t);

@@ -47,6 +47,7 @@ class NCProblem(ctypes.Structure):
         ("smooth_pre", ctypes.c_int), ("smooth_post", ctypes.c_int),
         ("smooth_omega", ctypes.c_double),
         ("smooth_pre_coarse", ctypes.c_int), ("smooth_post_coarse", ctypes.c_int),
+        ("krylov_rtol_mixed", ctypes.c_double), ("gs_passes", ctypes.c_int),
     ]
 
 

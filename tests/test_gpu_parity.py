@@ -92,3 +92,31 @@ def test_state_adjoint_sensitivity_cavity16(precision, tol):
     assert np.linalg.norm(dfdg.cpu().numpy() - go) / np.linalg.norm(go) < tol
     assert abs(sol.objective(s) - m.objective(so)) < tol * abs(m.objective(so))
     print("newton", info, "adjoint", sol.last_info)
+
+
+@pytest.mark.parametrize("precision", [nc.NC_FP64, nc.NC_MIXED])
+def test_stress_case_paper_regime(precision):
+    """The paper's strongly coupled regime (Gr 1e6 with its Table tab:2 permeability; solid
+    permeability 1e-7 as at the end of the continuation, Sec. 5.3 eq. contsch1) with a flux giving a
+    temperature rise near 1: Newton and the multigrid-preconditioned solves still reach the
+    oracle's root, adjoint and sensitivities within 1e-8 per field."""
+    p = workloads.problem((16, 8, 16), 1e6, precision=precision, kappa_s=1e-7, q_h=100.0)
+    x = inputs.noise_design(16 * 8 * 16, 0)
+    sol = _solver(p, x)
+    s = sol.solve_state()
+    info = dict(sol.last_info)
+    assert info["status"] == nc.NC_OK, info
+    lam = sol.solve_adjoint(s, sol.objective_grad())
+    assert sol.last_info["status"] == nc.NC_OK, sol.last_info
+    dfdx = sol.sensitivity(s, lam)
+    m = oracle.Model(oracle_params(p), x)
+    so, _ = m.solve_state()
+    assert so[:, 4].max() > 0.5   # the coupled regime: temperature rise of order one
+    lo = m.solve_adjoint(so, m.dfds())
+    go, gx = m.sensitivity(so, lo)
+    errs = rel_fields(s.cpu().numpy(), so)
+    assert max(errs) < 1e-8, errs
+    lerr = rel_fields(lam.cpu().numpy(), lo)
+    assert max(e for f, e in enumerate(lerr) if np.linalg.norm(lo[:, f]) > 0) < 1e-8, lerr
+    assert np.linalg.norm(dfdx.cpu().numpy() - gx) / np.linalg.norm(gx) < 1e-8
+    print("newton", info, "adjoint", sol.last_info)
