@@ -725,8 +725,7 @@ int adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info*
     // weight the (P, T) rows of later sweeps by 1 / |lambda_f|, relative to T, so that the
     // Krylov residual measures each field's relative error (the adjoint of the pressure
     // rows is small and otherwise under-resolved)
-    static const bool reweight = std::getenv("NC_ADJ_NOREWEIGHT") == nullptr;   // experiment
-    if (reweight) {
+    {
       launch_field_norms(st, lam, nullptr, c->N, c->part, c->dres);
       fetch(c, c->dres, 5);
       const double lp = c->hbuf[3], lt = c->hbuf[4];
@@ -746,8 +745,7 @@ int adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info*
     // gaining (round-off floor) the error estimate alone decides
     const bool stalled = rel > 0.25 * rel_prev;
     if (rel <= p.adjoint_rtol || stalled) {
-      static const bool noest = std::getenv("NC_ADJ_NOEST") != nullptr;   // experiment
-      const double est = noest ? 0.0 : error_estimate(c, true, c->R, lam);
+      const double est = error_estimate(c, true, c->R, lam);
       if (debug_on()) std::fprintf(stderr, "nc adjoint sweep %d: krylov %d rel %.2e est %.2e\n", ref, its, rel, est);
       if (est <= 10.0 * p.adjoint_rtol || (stalled && est <= 1e2 * p.adjoint_rtol)) {
         status = NC_OK;
