@@ -809,7 +809,7 @@ void nc_problem_default(nc_problem* p, int nx, int ny, int nz) {
   p->levels = 0;
   p->newton_step_rtol = 1e-11;
   p->krylov_rtol = 1e-7;
-  p->krylov_rtol_mixed = 3e-5;
+  p->krylov_rtol_mixed = 6e-5;
   p->gs_passes = 1;
   p->adjoint_rtol = 1e-10;
   p->newton_maxit = 30;

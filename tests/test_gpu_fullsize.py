@@ -79,8 +79,10 @@ def _energy_balance(p, gam, s):
 @pytest.mark.parametrize("name", ["cavity128mixed", "cavity96filtered"])
 def test_full_size_solution_properties(name):
     """At full size: the heat leaving through the isothermal walls equals the heat entering
-    through the patch (discrete energy balance of the weak form), the residual of the
-    solution is at round-off, and the solve converged."""
+    through the patch (discrete energy balance of the weak form), the solve converged,
+    and the temperature residual is within the Newton stop: Newton ends once the error
+    predicted to remain is below newton_step_rtol (relative, per field), so the residual
+    per node is bounded by that fraction of the patch heat flux per node."""
     p, x, cfg = workloads.config(name, DEV)
     sol = nc.Solver(p, DEV)
     sol.set_design(x)
@@ -90,7 +92,8 @@ def test_full_size_solution_properties(name):
     sn = s.cpu().numpy()
     total, heat_in = _energy_balance(p, sol.gamma().cpu().numpy(), sn)
     assert abs(total + heat_in) < 1e-9 * heat_in, (total, heat_in)
-    assert np.abs(r[:, 4]).max() < 1e-12 * np.abs(oracle.patch_flux(oracle.Mesh(oracle_params(p)), oracle_params(p))).max()
+    flux = np.abs(oracle.patch_flux(oracle.Mesh(oracle_params(p)), oracle_params(p))).max()
+    assert np.abs(r[:, 4]).max() < p.newton_step_rtol * flux, (np.abs(r[:, 4]).max(), flux)
     assert np.all(np.isfinite(sn))
 
 
