@@ -56,7 +56,7 @@ PROFILE_NAMES = {
 # kernel sources whose hash must match the one recorded with the counter runs
 KERNEL_SOURCES = ["paper_1904_00182_amd/csrc/k_misc.hip", "paper_1904_00182_amd/csrc/k_apply.hip",
                   "paper_1904_00182_amd/csrc/element.hpp", "paper_1904_00182_amd/csrc/common.hpp",
-                  "paper_1904_00182_amd/csrc/kernels.hpp"]
+                  "paper_1904_00182_amd/csrc/kernels.hpp", "paper_1904_00182_amd/csrc/transfer.hpp"]
 
 
 def measured_traffic(cls, tname):

@@ -56,6 +56,8 @@ extern "C" {
 #define NC_FP64   0   /* everything in float64                                          */
 #define NC_MIXED  1   /* float32 inner Krylov / multigrid / operator, float64 outer loop */
 
+#define NC_DENSE_MAX 2000   /* largest coarsest-grid system solved by a dense inverse */
+
 typedef struct nc_problem {
   int    nx, ny, nz;          /* elements per axis                                       */
   double h;                   /* element edge; <= 0 means 1/nx                           */
@@ -81,6 +83,9 @@ typedef struct nc_problem {
   int    smooth_pre_coarse, smooth_post_coarse; /* the same on the coarser levels        */
   double krylov_rtol_mixed;   /* relative tolerance of each float32 inner solve (NC_MIXED) */
   int    gs_passes;           /* classical Gram-Schmidt passes per FGMRES step, 1 or 2   */
+  int    coarse_tail;         /* 1: the last smoothed level and the dense coarsest level of
+                                 each V-cycle run in one workgroup when they fit; 0: one
+                                 launch per step everywhere (same operators and order)   */
 } nc_problem;
 
 typedef struct nc_info {
@@ -160,16 +165,37 @@ int    nc_sensitivity(nc_ctx* ctx, const double* s_dev, const double* lam_dev, d
  * launches: every input read once, every output written once) for k < n over the kernel
  * classes 0 residual, 1 J v and 2 J^T w of the (P, T) Krylov solve, 3 smoothing sweep on the
  * finest grid, 4 transposed sweep on the finest grid, 5 multigrid residual on the finest
- * grid, 6 node-block diagonal, 7 velocity coupling, 8 grid transfers, 9 coarsest solve,
+ * grid, 6 node-block diagonal, 7 velocity coupling, 8 grid transfers, 9 coarsest solve (and
+ * the bottom of the V-cycle where it runs in one workgroup),
  * 10 Krylov multi-dot, 11 Krylov multi-axpy, 12 other vector kernels, 13 preconditioner
  * setup, 14 smoothing sweeps on coarser levels, 15 multigrid residuals on coarser levels;
  * returns the number of classes (16) or an error code. */
 int    nc_set_timing(nc_ctx* ctx, int enable);
 int    nc_get_timing(nc_ctx* ctx, double* ms, long* counts, double* bytes, int n);
 
+/* One application of the multigrid preconditioner of the (P, T) Krylov solves (rows
+ * a3, a6; the paper leaves the preconditioner to its references): the hierarchy is
+ * rebuilt at the linearisation state s_dev [N][5] (state injection, node-block
+ * inverses, coarsest inverse), then z = M^-1 v, or M^-T v when transpose != 0, by one
+ * V-cycle in the working precision.  v_dev, z_dev: [N][2] float64 (P, T) pairs; the
+ * constrained entries of z are zero.  A diagnostic of the solver's building block.
+ * Enqueue only. */
+int    nc_precondition(nc_ctx* ctx, int transpose, const double* s_dev, const double* v_dev, double* z_dev);
+
 /* Stand-alone cone filter on an nx*ny*nz element grid (y = F_R x, or F_R^T x when
  * transpose != 0); used to build filtered designs.  Enqueued on stream. */
 int    nc_cone_filter(int nx, int ny, int nz, double radius, const double* x_dev, double* y_dev, int transpose, void* stream);
+
+/* Coarsest-grid solve of the multigrid preconditioner, exposed on its own (the paper
+ * leaves the preconditioner to its references; the hierarchy here inverts the coarsest
+ * (P, T) operator densely): in-place Gauss-Jordan inversion with partial pivoting of a
+ * dense n x n float64 matrix, 1 <= n <= NC_DENSE_MAX.  a_dev holds 2 n^2 doubles: on
+ * entry the first n^2 are A (row-major); on return they are A^-1 and the next n^2 are
+ * (A^-1)^T (the second half is overwritten as scratch).  iwork_dev (2 n ints, returns the
+ * pivot rows in order first) and dwork_dev (2 n doubles) are scratch.  A singular A (a
+ * zero pivot) leaves non-finite entries; nothing is checked on the device.  NC_EINVAL for
+ * a bad n or NULL pointer.  Enqueued on stream. */
+int    nc_dense_inverse(double* a_dev, int n, int* iwork_dev, double* dwork_dev, void* stream);
 
 #ifdef __cplusplus
 }

@@ -12,9 +12,12 @@
 // Elements on the tile's lower x / y edge and the layer below the z chunk are recomputed
 // by the neighbouring workgroup; the tile shape is chosen per grid to keep that halo and
 // idle lanes small.
+#include <algorithm>
 #include <cstdlib>
+#include <stdexcept>
 
 #include "kernels.hpp"
+#include "transfer.hpp"
 
 namespace nc {
 
@@ -121,12 +124,13 @@ static void run_zmarch_t(hipStream_t st, const Op& op) {
   const Grid& g = op.g;
   const int tiles_x = ceil_div(g.nx + 1, TX - 1);
   const int tiles_y = ceil_div(g.ny + 1, TY - 1);
-  // z chunks: about `target` workgroups over the device (NC_ZBLOCKS overrides) with at
+  // z chunks: about `target` workgroups over the device (NC_ZBLOCKS overrides on the finest
+  // grid, NC_ZBLOCKS_COARSE on coarser levels) with at
   // least `kzmin` node planes per chunk (NC_KZMIN overrides).  A thread's serial work is
   // KZ + 1 element layers, so short chunks cut the latency of launches on small grids at
   // the price of recomputing more halo layers.
   static const int target = [] {
-    const char* e = std::getenv("NC_ZBLOCKS");
+    const char* e = std::getenv(FINE ? "NC_ZBLOCKS" : "NC_ZBLOCKS_COARSE");
     return e ? std::max(1, std::atoi(e)) : 1024;
   }();
   static const int kzmin = [] {
@@ -389,6 +393,235 @@ void launch_pt_apply(hipStream_t st, const LevelView<T>& L, bool transpose, int 
 #undef NC_PT
 }
 
+// ------------------------------------------------------------------ bottom of the V-cycle
+// The last smoothed level and the dense coarsest level in one workgroup.  On grids this
+// small each launch of the per-step path is latency bound (one wave's serial element work
+// plus the launch itself), so here the whole bottom of the cycle -- restriction into the
+// level with its first damped step, further pre-sweeps, residual, restriction to the
+// coarsest level, the dense solve, prolongation, post-sweeps and the prolongation into
+// the level above -- runs with the level's vectors in LDS, one element per thread per
+// pass and a barrier between passes.  With PF the level's node-block inverses, state
+// and coefficients are staged in LDS too.  Global loads are batched so that many are in
+// flight at once: inside one workgroup their latency, not bandwidth, sets the time.  The
+// element and node arithmetic is that of JvOp / JtwOp on two fields; each node sums its
+// elements' contributions in corner order, so results do not depend on timing.
+template <typename T>
+struct TailArgs {
+  Grid gu;              // level above
+  const T* ru;          // its residual, restricted into this level
+  T* xu;                // its iterate, to which the prolonged correction is added
+  LevelView<T> lv;      // this level
+  Grid gc;              // coarsest level
+  const double* ainv;   // coarsest inverse (its transpose for the transposed cycle), row-major
+  T omega;
+  int npre, npost;
+};
+
+constexpr int TAIL_THREADS = 512, TAIL_LDS_MAX = 65536;
+
+// LDS bytes: element contributions [E][8][2] (the coarsest vectors reuse them), the level's
+// b, x, y [N][2]; with the prefetch also D^-1 [N][4], the state [N][2], coefficients [E][2]
+template <typename T>
+static size_t tail_lds_bytes(const Grid& g, const Grid& gc, bool pf) {
+  const size_t con = std::max<size_t>(16 * (size_t)g.elems(), 4 * (size_t)gc.nodes());
+  return sizeof(T) * (con + 6 * (size_t)g.nodes() + (pf ? 6 * (size_t)g.nodes() + 2 * (size_t)g.elems() : 0));
+}
+
+__device__ inline void tail_ijk(int n, int nx1, int ny1, int& i, int& j, int& k) {
+  i = n % nx1;
+  j = (n / nx1) % ny1;
+  k = n / (nx1 * ny1);
+}
+
+template <typename T, bool TR, bool PF>
+__global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char tail_smem[];
+  const Grid g = a.lv.g, gc = a.gc, gu = a.gu;
+  const int N = (int)g.nodes(), E = (int)g.elems(), Nc = (int)gc.nodes(), Nu = (int)gu.nodes();
+  const int nc2 = 2 * Nc;
+  T* con = (T*)tail_smem;   // [E][8 corners][2]; during the coarse correction bc, xc [Nc][2]
+  T* b = con + max(16 * E, 2 * nc2);
+  T* x = b + 2 * N;
+  T* y = x + 2 * N;
+  T* sD = y + 2 * N;        // prefetched D^-1 [N][4], state [N][2], coefficients [E][2]
+  T* sSt = sD + 4 * N;
+  T* sCoef = sSt + 2 * N;
+  T* bc = con;
+  T* xc = con + nc2;
+  const int t = threadIdx.x;
+  const T om = a.omega;
+  if constexpr (PF) {
+    for (int m = t; m < 4 * N; m += TAIL_THREADS) sD[m] = a.lv.dinv[m];
+    for (int m = t; m < 2 * N; m += TAIL_THREADS) sSt[m] = a.lv.st[m];
+    for (int m = t; m < 2 * E; m += TAIL_THREADS) sCoef[m] = a.lv.coef[m];
+  }
+  const T* D = PF ? (const T*)sD : a.lv.dinv;
+  const T* ST = PF ? (const T*)sSt : a.lv.st;
+  const T* CO = PF ? (const T*)sCoef : a.lv.coef;
+  for (int n = t; n < N; n += TAIL_THREADS) {
+    int I, J, K;
+    tail_ijk(n, g.nx + 1, g.ny + 1, I, J, K);
+    double sp, stt;
+    restrict_taps(gu, I, J, K, a.ru, sp, stt);
+    const T bp = g.pfix(I, J, K) ? (T)0 : (T)sp;
+    const T bt = g.tfix(I, J, K) ? (T)0 : (T)stt;
+    b[2 * n] = bp;
+    b[2 * n + 1] = bt;
+    const T* d = a.lv.dinv + 4 * n;
+    x[2 * n] = om * (d[0] * bp + d[TR ? 2 : 1] * bt);
+    x[2 * n + 1] = om * (d[TR ? 1 : 2] * bp + d[3] * bt);
+  }
+  __syncthreads();
+  // passes: pre - 1 further sweeps, the residual (followed by the coarse correction), then
+  // the post-sweeps; a sweep writes y from x and the two swap
+  const int pre = max(a.npre, 1) - 1, passes = pre + 1 + a.npost;
+  for (int q = 0; q < passes; ++q) {
+    for (int e = t; e < E; e += TAIL_THREADS) {
+      int i, j, k;
+      tail_ijk(e, g.nx, g.ny, i, j, k);
+      T P[8], Tn[8], p[8], w[8];
+#pragma unroll
+      for (int c8 = 0; c8 < 8; ++c8) {
+        const int ni = i + (c8 & 1), nj = j + ((c8 >> 1) & 1), nk = k + (c8 >> 2);
+        const int n = g.node(ni, nj, nk);
+        P[c8] = ST[2 * n];
+        Tn[c8] = ST[2 * n + 1];
+        p[c8] = g.pfix(ni, nj, nk) ? (T)0 : x[2 * n];
+        w[c8] = g.tfix(ni, nj, nk) ? (T)0 : x[2 * n + 1];
+      }
+      LinM<T> L;
+      lin_modal(P, Tn, CO[2 * e], CO[2 * e + 1], a.lv.c, L);
+      T yP[8] = {0}, yT[8] = {0}, yU[3][8] = {{0}};
+      if constexpr (TR) elem_jtw_m<T, false>(L, p, w, yU, a.lv.c, yP, yT);
+      else elem_jv_m<T, false>(L, p, w, a.lv.c, yP, yT, yU);
+#pragma unroll
+      for (int c8 = 0; c8 < 8; ++c8) {
+        con[(8 * e + c8) * 2] = yP[c8];
+        con[(8 * e + c8) * 2 + 1] = yT[c8];
+      }
+    }
+    __syncthreads();
+    const bool resid = q == pre;
+    for (int n = t; n < N; n += TAIL_THREADS) {
+      int I, J, K;
+      tail_ijk(n, g.nx + 1, g.ny + 1, I, J, K);
+      T vp = (T)0, vt = (T)0;
+#pragma unroll
+      for (int c8 = 0; c8 < 8; ++c8) {
+        const int ei = I - (c8 & 1), ej = J - ((c8 >> 1) & 1), ek = K - (c8 >> 2);
+        if (ei >= 0 && ei < g.nx && ej >= 0 && ej < g.ny && ek >= 0 && ek < g.nz) {
+          const int e = g.elem(ei, ej, ek);
+          vp += con[(8 * e + c8) * 2];
+          vt += con[(8 * e + c8) * 2 + 1];
+        }
+      }
+      const T ap = g.pfix(I, J, K) ? x[2 * n] : vp;
+      const T at = g.tfix(I, J, K) ? x[2 * n + 1] : vt;
+      const T rp = b[2 * n] - ap, rt = b[2 * n + 1] - at;
+      if (resid) {
+        y[2 * n] = rp;
+        y[2 * n + 1] = rt;
+      } else {
+        const T* d = D + 4 * n;
+        y[2 * n] = x[2 * n] + om * (d[0] * rp + d[TR ? 2 : 1] * rt);
+        y[2 * n + 1] = x[2 * n + 1] + om * (d[TR ? 1 : 2] * rp + d[3] * rt);
+      }
+    }
+    __syncthreads();
+    if (!resid) {
+      T* tmp = x;
+      x = y;
+      y = tmp;
+      continue;
+    }
+    // coarse correction: restrict the residual, solve densely, prolong into x
+    for (int n = t; n < Nc; n += TAIL_THREADS) {
+      int I, J, K;
+      tail_ijk(n, gc.nx + 1, gc.ny + 1, I, J, K);
+      double sp, stt;
+      restrict_taps(g, I, J, K, (const T*)y, sp, stt);
+      bc[2 * n] = gc.pfix(I, J, K) ? (T)0 : (T)sp;
+      bc[2 * n + 1] = gc.tfix(I, J, K) ? (T)0 : (T)stt;
+    }
+    __syncthreads();
+    // eight lanes per row, four independent partial sums each, combined by a butterfly
+    // inside the eight lanes
+    for (int row = t >> 3; row < nc2; row += TAIL_THREADS / 8) {
+      const double* arow = a.ainv + (long)row * nc2;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int col = t & 7;
+      for (; col + 24 < nc2; col += 32) {
+        s0 += arow[col] * (double)bc[col];
+        s1 += arow[col + 8] * (double)bc[col + 8];
+        s2 += arow[col + 16] * (double)bc[col + 16];
+        s3 += arow[col + 24] * (double)bc[col + 24];
+      }
+      for (; col < nc2; col += 8) s0 += arow[col] * (double)bc[col];
+      double s = (s0 + s1) + (s2 + s3);
+      s += __shfl_xor(s, 1, 8);
+      s += __shfl_xor(s, 2, 8);
+      s += __shfl_xor(s, 4, 8);
+      if ((t & 7) == 0) xc[row] = (T)s;
+    }
+    __syncthreads();
+    for (int n = t; n < N; n += TAIL_THREADS) {
+      int I, J, K;
+      tail_ijk(n, g.nx + 1, g.ny + 1, I, J, K);
+      double sp, stt;
+      prolong_taps(gc, I, J, K, (const T*)xc, sp, stt);
+      if (!g.pfix(I, J, K)) x[2 * n] += (T)sp;
+      if (!g.tfix(I, J, K)) x[2 * n + 1] += (T)stt;
+    }
+    __syncthreads();
+  }
+  // prolongation into the level above, TAIL_B nodes per thread per batch: the batch's
+  // loads of the upper iterate are issued before any of its stores
+  constexpr int TAIL_B = 8;
+  for (int base = 0; base < Nu; base += TAIL_B * TAIL_THREADS) {
+    T up[TAIL_B], ut[TAIL_B];
+#pragma unroll
+    for (int r = 0; r < TAIL_B; ++r) {
+      const int n = base + r * TAIL_THREADS + t;
+      up[r] = n < Nu ? a.xu[2 * n] : (T)0;
+      ut[r] = n < Nu ? a.xu[2 * n + 1] : (T)0;
+    }
+#pragma unroll
+    for (int r = 0; r < TAIL_B; ++r) {
+      const int n = base + r * TAIL_THREADS + t;
+      if (n < Nu) {
+        int i, j, k;
+        tail_ijk(n, gu.nx + 1, gu.ny + 1, i, j, k);
+        double sp, stt;
+        prolong_taps(g, i, j, k, (const T*)x, sp, stt);
+        if (!gu.pfix(i, j, k)) a.xu[2 * n] = up[r] + (T)sp;
+        if (!gu.tfix(i, j, k)) a.xu[2 * n + 1] = ut[r] + (T)stt;
+      }
+    }
+  }
+}
+
+template <typename T>
+bool tail_cycle_fits(const Grid& gu, const Grid& g, const Grid& gc) {
+  return g.elems() <= TAIL_THREADS && gu.nodes() <= 65536 && tail_lds_bytes<T>(g, gc, false) <= TAIL_LDS_MAX;
+}
+
+template <typename T>
+void launch_tail_cycle(hipStream_t st, const Grid& gu, const T* ru, T* xu, const LevelView<T>& L, const Grid& gc,
+                       const double* ainv, bool transpose, T omega, int npre, int npost) {
+  if (!tail_cycle_fits<T>(gu, L.g, gc)) throw std::runtime_error("tail cycle does not fit one workgroup");
+  const TailArgs<T> a{gu, ru, xu, L, gc, ainv, omega, npre, npost};
+  const bool pf = tail_lds_bytes<T>(L.g, gc, true) <= TAIL_LDS_MAX;
+  const size_t lds = tail_lds_bytes<T>(L.g, gc, pf);
+  const dim3 grid(1), block(TAIL_THREADS);
+  if (transpose) {
+    if (pf) launch(tail_cycle_kernel<T, true, true>, grid, block, lds, st, a);
+    else launch(tail_cycle_kernel<T, true, false>, grid, block, lds, st, a);
+  } else {
+    if (pf) launch(tail_cycle_kernel<T, false, true>, grid, block, lds, st, a);
+    else launch(tail_cycle_kernel<T, false, false>, grid, block, lds, st, a);
+  }
+}
+
 // ------------------------------------------------------------------ block diagonal
 template <typename T>
 struct DiagOp {
@@ -533,6 +766,9 @@ void launch_uprojT(hipStream_t st, const LevelView<T>& L, const T* r5, T* b_pt, 
   template void launch_jv5<T>(hipStream_t, const LevelView<T>&, const T*, T*, const Scale5<T>*);    \
   template void launch_jtw5<T>(hipStream_t, const LevelView<T>&, const T*, T*, const Scale5<T>*);   \
   template void launch_pt_apply<T>(hipStream_t, const LevelView<T>&, bool, int, const T*, const T*, T*, T, bool); \
+  template bool tail_cycle_fits<T>(const Grid&, const Grid&, const Grid&);                            \
+  template void launch_tail_cycle<T>(hipStream_t, const Grid&, const T*, T*, const LevelView<T>&, const Grid&,     \
+                                     const double*, bool, T, int, int);                                \
   template void launch_pt_store<T>(hipStream_t, const LevelView<T>&, bool, const T*, T*, const Scale5<T>*);       \
   template void launch_diag_inverse<T>(hipStream_t, const LevelView<T>&, T*);                       \
   template void launch_uproj<T>(hipStream_t, const LevelView<T>&, const T*, const T*, T*, const Scale5<T>*); \

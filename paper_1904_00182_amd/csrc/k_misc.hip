@@ -3,6 +3,7 @@
 #include <utility>
 
 #include "kernels.hpp"
+#include "transfer.hpp"
 
 namespace nc {
 
@@ -34,43 +35,18 @@ static inline dim3 plane_grid(const Grid& g, int bs) {
   return dim3((unsigned)ceil_div((long)(g.nx + 1) * (g.ny + 1), bs), (unsigned)(g.nz + 1));
 }
 
-// Restriction by the transpose of trilinear prolongation (full weighting with weights
-// 1, 1/2, 1/4, 1/8), constrained coarse dofs set to zero; one thread per coarse node.
-// With dinv, also the first damped block-Jacobi step of the coarse level from a zero
-// guess, x = omega D^-1 b (D^-T b when transposed).
+// Restriction by the transpose of trilinear prolongation (full weighting), constrained
+// coarse dofs set to zero; one thread per coarse node.  With dinv, also the first damped
+// block-Jacobi step of the coarse level from a zero guess, x = omega D^-1 b (D^-T b when
+// transposed).
 template <typename T>
 __global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf, T* __restrict__ bc,
                                 const T* __restrict__ dinv, int transpose, T omega, T* __restrict__ xc) {
   const PlaneIdx q = plane_idx(coarse);
   if (!q.ok) return;
   const int I = q.i, J = q.j, K = q.k;
-  // the 27 taps, clamped into the grid with weight 0 outside it, so that every load is
-  // independent of the others
-  int ix[3], jy[3], kz[3];
-  double wx[3], wy[3], wz[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int i = 2 * I + d - 1, j = 2 * J + d - 1, k = 2 * K + d - 1;
-    const double w = d == 1 ? 1.0 : 0.5;
-    ix[d] = min(max(i, 0), fine.nx);
-    jy[d] = min(max(j, 0), fine.ny);
-    kz[d] = min(max(k, 0), fine.nz);
-    wx[d] = (i >= 0 && i <= fine.nx) ? w : 0.0;
-    wy[d] = (j >= 0 && j <= fine.ny) ? w : 0.0;
-    wz[d] = (k >= 0 && k <= fine.nz) ? w : 0.0;
-  }
-  double sp = 0.0, stt = 0.0;
-#pragma unroll
-  for (int dk = 0; dk < 3; ++dk)
-#pragma unroll
-    for (int dj = 0; dj < 3; ++dj)
-#pragma unroll
-      for (int di = 0; di < 3; ++di) {
-        const double w = wz[dk] * wy[dj] * wx[di];
-        const int m = fine.node(ix[di], jy[dj], kz[dk]);
-        sp += w * (double)rf[2 * m];
-        stt += w * (double)rf[2 * m + 1];
-      }
+  double sp, stt;
+  restrict_taps(fine, I, J, K, rf, sp, stt);
   const int n = coarse.node(I, J, K);
   const T bp = coarse.pfix(I, J, K) ? (T)0 : (T)sp;
   const T bt = coarse.tfix(I, J, K) ? (T)0 : (T)stt;
@@ -83,30 +59,14 @@ __global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf
   }
 }
 
-// Trilinear prolongation added to the fine iterate; one thread per fine node, the eight
-// coarse taps loaded together (a tap repeated with weight 0 where the fine node lies on a
-// coarse plane).
+// Trilinear prolongation added to the fine iterate; one thread per fine node.
 template <typename T>
 __global__ void prolong_kernel(Grid fine, Grid coarse, const T* __restrict__ xc, T* __restrict__ xf) {
   const PlaneIdx q = plane_idx(fine);
   if (!q.ok) return;
   const int i = q.i, j = q.j, k = q.k;
-  const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
-  const double wi[2] = {(i & 1) ? 0.5 : 1.0, (i & 1) ? 0.5 : 0.0};
-  const double wj[2] = {(j & 1) ? 0.5 : 1.0, (j & 1) ? 0.5 : 0.0};
-  const double wk[2] = {(k & 1) ? 0.5 : 1.0, (k & 1) ? 0.5 : 0.0};
-  double sp = 0.0, stt = 0.0;
-#pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const double w = wi[a] * wj[b] * wk[c];
-        const int m = coarse.node(a ? i1 : i0, b ? j1 : j0, c ? k1 : k0);
-        sp += w * (double)xc[2 * m];
-        stt += w * (double)xc[2 * m + 1];
-      }
+  double sp, stt;
+  prolong_taps(coarse, i, j, k, xc, sp, stt);
   const int n = fine.node(i, j, k);
   if (!fine.pfix(i, j, k)) xf[2 * n] += (T)sp;
   if (!fine.tfix(i, j, k)) xf[2 * n + 1] += (T)stt;
@@ -239,121 +199,114 @@ void launch_coarse_assemble(hipStream_t st, const LevelView<T>& L, double* elem_
 // inverse in place.  The row interchanges are undone as column interchanges in reverse
 // order at the end.
 
-// The same inversion with the matrix held in registers, for n <= GJS_NMAX: row r belongs
-// to wave r % 16 (slot r / 16), column c to lane c % 64 (slot c / 64).  Each step puts the
-// pivot column and the old rows k and p in LDS; every thread then updates its entries with
-// the operations above, in the same order.  The row interchanges are
-// undone as one column permutation when the result is written back.
-constexpr int GJS_QR = 10, GJS_QC = 3, GJS_NMAX = 16 * GJS_QR;   // 64 * GJS_QC >= GJS_NMAX
+// The same inversion with the matrix held in registers, for n <= GJS_NMAX, and without row
+// interchanges: the pivot of step k is the row p_k of largest |A[r][k]| among the rows
+// not yet used as pivots (ties: lowest lane, then lowest slot; a NaN counts as largest).
+// Row p_k is scaled and every other row eliminated exactly as above.  Column k then holds
+// the column of the inverse that belongs to row p_k, so after n steps entry (r, c) is
+// (A^-1)[s(r)][p_c], s(r) being the step that took row r as pivot: the write-back applies
+// both permutations at once.
+// Row r belongs to lane r % 64 (slot r / 64) of every wave, column c to wave c % 16 (slot
+// c / 16).  In step k the wave holding column k finds the pivot with a wave reduction and
+// puts the column and the pivot index in LDS (two buffers, so one barrier per step); each
+// wave reads the pivot row's entries of its own columns from lane p % 64 with readlane.
+constexpr int GJS_RI = 3, GJS_NW = 16, GJS_CJ = 10, GJS_NMAX = GJS_NW * GJS_CJ;   // 64 * GJS_RI >= GJS_NMAX
+
+__device__ inline double readlane_f64(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __global__ __launch_bounds__(1024) void gauss_jordan_small_kernel(double* __restrict__ A, int n, int* __restrict__ perm) {
-  __shared__ double colk[GJS_NMAX];
-  __shared__ double pivrow[64 * GJS_QC];
-  __shared__ double oldk[64 * GJS_QC];
-  __shared__ int sperm[GJS_NMAX];
-  __shared__ int sidx[GJS_NMAX];
-  __shared__ int sinv[GJS_NMAX];
-  __shared__ int spiv;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double a[GJS_QR][GJS_QC];
+  __shared__ double colk[2][64 * GJS_RI];
+  __shared__ int spiv[2];
+  __shared__ int sp[GJS_NMAX];   // pivot row of each step
+  __shared__ int ss[GJS_NMAX];   // step at which each row was the pivot
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double a[GJS_RI][GJS_CJ];
 #pragma unroll
-  for (int i = 0; i < GJS_QR; ++i)
+  for (int i = 0; i < GJS_RI; ++i)
 #pragma unroll
-    for (int j = 0; j < GJS_QC; ++j) {
-      const int r = w + 16 * i, c = lane + 64 * j;
+    for (int j = 0; j < GJS_CJ; ++j) {
+      const int r = lane + 64 * i, c = w + GJS_NW * j;
       a[i][j] = (r < n && c < n) ? A[(long)r * n + c] : 0.0;
     }
-  for (int k = 0; k < n; ++k) {
-    const int jk = k >> 6;
-    if (lane == (k & 63)) {
+  unsigned used = 0;   // bit i: row lane + 64 i is padding or has been a pivot
 #pragma unroll
-      for (int i = 0; i < GJS_QR; ++i) {
-        const int r = w + 16 * i;
+  for (int i = 0; i < GJS_RI; ++i)
+    if (lane + 64 * i >= n) used |= 1u << i;
 #pragma unroll
-        for (int j = 0; j < GJS_QC; ++j)
-          if (j == jk && r < n) colk[r] = a[i][j];
-      }
-    }
-    __syncthreads();
-    if (w == 0) {
-      double best = -1.0;
-      int bi = k;
-      for (int r = k + lane; r < n; r += 64) {
-        const double v = fabs(colk[r]);
-        if (v > best) { best = v; bi = r; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_down(best, off, 64);
-        const int oi = __shfl_down(bi, off, 64);
-        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-      }
-      if (lane == 0) { spiv = bi; sperm[k] = bi; perm[k] = bi; }
-    }
-    __syncthreads();
-    const int p = spiv;
-    if (w == (p & 15) || w == (k & 15)) {
+  for (int j0 = 0; j0 < GJS_CJ; ++j0) {
+    for (int wk = 0; wk < GJS_NW && wk + GJS_NW * j0 < n; ++wk) {
+      const int k = wk + GJS_NW * j0, buf = k & 1;
+      if (w == wk) {
+        double best = -1.0;
+        int bi = -1;
 #pragma unroll
-      for (int i = 0; i < GJS_QR; ++i) {
-        const int r = w + 16 * i;
-#pragma unroll
-        for (int j = 0; j < GJS_QC; ++j) {
-          if (r == p) pivrow[lane + 64 * j] = a[i][j];
-          if (r == k) oldk[lane + 64 * j] = a[i][j];
+        for (int i = 0; i < GJS_RI; ++i) {
+          double v = fabs(a[i][j0]);
+          if (v != v) v = __builtin_inf();
+          if (!((used >> i) & 1u) && v > best) { best = v; bi = lane + 64 * i; }
         }
+        // at least one row is unused (k < n), so the maximum is >= 0 and names one
+        double m = best;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+        const unsigned long long hit = __ballot(best == m);
+        const int src = __builtin_amdgcn_readfirstlane(__builtin_ctzll(hit));
+        const int p = __builtin_amdgcn_readlane(bi, src);
+#pragma unroll
+        for (int i = 0; i < GJS_RI; ++i) colk[buf][lane + 64 * i] = a[i][j0];
+        if (lane == 0) spiv[buf] = p;
       }
-    }
-    __syncthreads();
-    const double ipv = 1.0 / pivrow[k];
-    const double fk = oldk[k];
-    double pr[GJS_QC];
+      __syncthreads();
+      const int p = __builtin_amdgcn_readfirstlane(spiv[buf]);
+      const int pl = p & 63, pi = p >> 6;
+      if (threadIdx.x == 0) { sp[k] = p; ss[p] = k; perm[k] = p; }
+      const double ipv = 1.0 / colk[buf][p];
+      double f[GJS_RI];
 #pragma unroll
-    for (int j = 0; j < GJS_QC; ++j) {
-      const int c = lane + 64 * j;
-      pr[j] = c < n ? (c == k ? 1.0 : pivrow[c]) * ipv : 0.0;
-    }
+      for (int i = 0; i < GJS_RI; ++i) f[i] = colk[buf][lane + 64 * i] * ipv;
+      double pr[GJS_CJ];   // row p in this wave's columns (wave-uniform)
+      if (pi == 0) {
 #pragma unroll
-    for (int i = 0; i < GJS_QR; ++i) {
-      const int r = w + 16 * i;
-      const double fr = r < n ? colk[r] : 0.0;
+        for (int j = 0; j < GJS_CJ; ++j) pr[j] = readlane_f64(a[0][j], pl);
+      } else if (pi == 1) {
 #pragma unroll
-      for (int j = 0; j < GJS_QC; ++j) {
-        const int c = lane + 64 * j;
-        a[i][j] = (c == k ? 0.0 : a[i][j]) - fr * pr[j];
+        for (int j = 0; j < GJS_CJ; ++j) pr[j] = readlane_f64(a[1][j], pl);
+      } else {
+#pragma unroll
+        for (int j = 0; j < GJS_CJ; ++j) pr[j] = readlane_f64(a[2][j], pl);
       }
-    }
-    // rows k and p: the scaled pivot row, and the old row k eliminated in row p's place
-    if (w == (p & 15) || w == (k & 15)) {
 #pragma unroll
-      for (int i = 0; i < GJS_QR; ++i) {
-        const int r = w + 16 * i;
+      for (int i = 0; i < GJS_RI; ++i)
 #pragma unroll
-        for (int j = 0; j < GJS_QC; ++j) {
-          const int c = lane + 64 * j;
-          if (r == k) a[i][j] = pr[j];
-          else if (r == p) a[i][j] = (c == k ? 0.0 : oldk[c]) - fk * pr[j];
-        }
+        for (int j = 0; j < GJS_CJ; ++j) a[i][j] = fma(-f[i], pr[j], a[i][j]);
+      if (w == wk) {
+#pragma unroll
+        for (int i = 0; i < GJS_RI; ++i) a[i][j0] = -f[i];
       }
-    }
-    __syncthreads();
-  }
-  // column permutation undoing the interchanges in reverse order: result column j is
-  // column sidx[j] of the eliminated matrix
-  if (threadIdx.x == 0) {
-    for (int j = 0; j < n; ++j) sidx[j] = j;
-    for (int k = n - 1; k >= 0; --k) {
-      const int q = sperm[k], tmp = sidx[k];
-      sidx[k] = sidx[q];
-      sidx[q] = tmp;
+      if (lane == pl) {
+        used |= 1u << pi;
+#pragma unroll
+        for (int i = 0; i < GJS_RI; ++i)
+          if (i == pi) {
+#pragma unroll
+            for (int j = 0; j < GJS_CJ; ++j) a[i][j] = (w == wk && j == j0) ? ipv : pr[j] * ipv;
+          }
+      }
     }
   }
   __syncthreads();
-  if ((int)threadIdx.x < n) sinv[sidx[threadIdx.x]] = threadIdx.x;
-  __syncthreads();
 #pragma unroll
-  for (int i = 0; i < GJS_QR; ++i)
+  for (int i = 0; i < GJS_RI; ++i)
 #pragma unroll
-    for (int j = 0; j < GJS_QC; ++j) {
-      const int r = w + 16 * i, c = lane + 64 * j;
-      if (r < n && c < n) A[(long)r * n + sinv[c]] = a[i][j];
+    for (int j = 0; j < GJS_CJ; ++j) {
+      const int r = lane + 64 * i, c = w + GJS_NW * j;
+      if (r < n && c < n) A[(long)ss[r] * n + sp[c]] = a[i][j];
     }
 }
 

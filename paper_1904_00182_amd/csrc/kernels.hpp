@@ -27,6 +27,16 @@ void launch_pt_store(hipStream_t st, const LevelView<T>& L, bool transpose, cons
 template <typename T>
 void launch_pt_apply(hipStream_t st, const LevelView<T>& L, bool transpose, int mode, const T* x, const T* b,
                      T* y, T omega, bool fine);
+// The bottom of a V-cycle in one workgroup, for a level L small enough (tail_cycle_fits)
+// whose next level gc is the dense coarsest: from the residual ru of the level gu above,
+// restriction into L with the first damped block-Jacobi step, npre - 1 further sweeps,
+// residual, restriction to gc, x = ainv b there (ainv: the inverse, or its transpose for
+// the transposed cycle), prolongation, npost sweeps, and xu += P x on gu.
+template <typename T>
+bool tail_cycle_fits(const Grid& gu, const Grid& g, const Grid& gc);
+template <typename T>
+void launch_tail_cycle(hipStream_t st, const Grid& gu, const T* ru, T* xu, const LevelView<T>& L, const Grid& gc,
+                       const double* ainv, bool transpose, T omega, int npre, int npost);
 // Inverse 2x2 (P, T) node blocks of the level Jacobian into dinv [N][4].
 template <typename T>
 void launch_diag_inverse(hipStream_t st, const LevelView<T>& L, T* dinv);

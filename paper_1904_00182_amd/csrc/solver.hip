@@ -169,6 +169,7 @@ bool valid_problem(const nc_problem* p) {
   if (p->krylov_restart < 1 || p->krylov_restart > MAXC - 2) return false;
   if (!(p->krylov_rtol > 0) || !(p->krylov_rtol_mixed > 0) || !(p->adjoint_rtol > 0)) return false;
   if (p->gs_passes != 1 && p->gs_passes != 2) return false;
+  if (p->coarse_tail != 0 && p->coarse_tail != 1) return false;
   if (p->smooth_pre < 1 || p->smooth_post < 0 || p->smooth_pre_coarse < 1 || p->smooth_post_coarse < 0) return false;
   return true;
 }
@@ -226,7 +227,7 @@ size_t carve(nc_ctx* c, char* base) {
   c->sens = cv.take<double>(c->E);
   const Grid& gc = c->lev[c->L - 1].g;
   c->ncoarse = (int)(2 * gc.nodes());
-  c->dense = c->ncoarse <= 2000;
+  c->dense = c->ncoarse <= NC_DENSE_MAX;
   c->emats = cv.take<double>(c->dense ? gc.elems() * 256 : 1);
   c->A = cv.take<double>(c->dense ? 2 * (size_t)c->ncoarse * c->ncoarse : 1);   // inverse and its transpose
   c->perm = cv.take<int>(c->dense ? 2 * c->ncoarse : 1);
@@ -338,15 +339,23 @@ void vcycle(nc_ctx* c, int l, bool tr, bool x_ready = false) {
   for (int s = 1; s < npre; ++s) sweep();
   { Timed tm(c, l == 0 ? TC_PT_RESID : TC_PT_RESID_COARSE, sizeof(T) * (8 * nn(L.g) + 2 * ne(L.g))); launch_pt_apply<T>(st, v, tr, MODE_RESID, (const T*)L.x, (const T*)L.b, (T*)L.r, om, l == 0); }
   Level& C = c->lev[l + 1];
-  // the coarse level's first smoothing step rides along with the restriction, except on a
-  // coarsest level solved by the dense inverse
-  const bool fuse = !(l + 1 == c->L - 1 && c->dense);
-  {
-    Timed tm(c, TC_TRANSFER, sizeof(T) * (2 * nn(L.g) + (fuse ? 8 : 2) * nn(C.g)));
-    launch_restrict<T>(st, L.g, C.g, (const T*)L.r, (T*)C.b, fuse ? (const T*)C.dinv : nullptr, tr, om, (T*)C.x);
+  if (c->dense && c->p.coarse_tail && l + 2 == c->L - 1 && tail_cycle_fits<T>(L.g, C.g, c->lev[l + 2].g)) {
+    // the rest of the cycle below this level in one workgroup
+    const size_t n2 = (size_t)c->ncoarse * c->ncoarse;
+    Timed tm(c, TC_COARSE, sizeof(T) * (6.0 * nn(L.g) + 8.0 * nn(C.g) + 2.0 * ne(C.g)) + 8.0 * n2);
+    launch_tail_cycle<T>(st, L.g, (const T*)L.r, (T*)L.x, view<T>(c, l + 1), c->lev[l + 2].g, tr ? c->A + n2 : c->A,
+                         tr, om, c->p.smooth_pre_coarse, c->p.smooth_post_coarse);
+  } else {
+    // the coarse level's first smoothing step rides along with the restriction, except on
+    // a coarsest level solved by the dense inverse
+    const bool fuse = !(l + 1 == c->L - 1 && c->dense);
+    {
+      Timed tm(c, TC_TRANSFER, sizeof(T) * (2 * nn(L.g) + (fuse ? 8 : 2) * nn(C.g)));
+      launch_restrict<T>(st, L.g, C.g, (const T*)L.r, (T*)C.b, fuse ? (const T*)C.dinv : nullptr, tr, om, (T*)C.x);
+    }
+    vcycle<T>(c, l + 1, tr, fuse);
+    { Timed tm(c, TC_TRANSFER, sizeof(T) * (4 * nn(L.g) + 2 * nn(C.g))); launch_prolong_add<T>(st, L.g, C.g, (const T*)C.x, (T*)L.x); }
   }
-  vcycle<T>(c, l + 1, tr, fuse);
-  { Timed tm(c, TC_TRANSFER, sizeof(T) * (4 * nn(L.g) + 2 * nn(C.g))); launch_prolong_add<T>(st, L.g, C.g, (const T*)C.x, (T*)L.x); }
   for (int s = 0; s < npost; ++s) sweep();
 }
 
@@ -811,6 +820,7 @@ void nc_problem_default(nc_problem* p, int nx, int ny, int nz) {
   p->krylov_rtol = 1e-7;
   p->krylov_rtol_mixed = 6e-5;
   p->gs_passes = 1;
+  p->coarse_tail = 1;
   p->adjoint_rtol = 1e-10;
   p->newton_maxit = 30;
   p->krylov_restart = 24;
@@ -1041,6 +1051,36 @@ int nc_cone_filter(int nx, int ny, int nz, double radius, const double* x, doubl
   if (transpose && radius > 0) return NC_EINVAL;   // the transpose needs a temporary; use a context
   return guarded([&]() {
     launch_cone_filter((hipStream_t)stream, Grid{nx, ny, nz}, radius, x, y, false, nullptr);
+    ck(hipGetLastError());
+    return NC_OK;
+  });
+}
+
+int nc_precondition(nc_ctx* c, int transpose, const double* s, const double* v, double* z) {
+  if (!c || !s || !v || !z || !c->design_set) return NC_EINVAL;
+  return guarded([&]() {
+    linearize(c, s, true);
+    hipStream_t st = c->stream;
+    if (c->mixed) {
+      launch_scale2<double, float>(st, c->N, v, (float*)c->kb, 1.0, 1.0);
+      precondition_pt<float>(c, transpose != 0, (float*)c->kb, (float*)c->kx, nullptr);
+      launch_scale2<float, double>(st, c->N, (const float*)c->kx, z, 1.0, 1.0);
+    } else {
+      launch_scale2<double, double>(st, c->N, v, (double*)c->kb, 1.0, 1.0);
+      precondition_pt<double>(c, transpose != 0, (double*)c->kb, (double*)c->kx, nullptr);
+      launch_scale2<double, double>(st, c->N, (const double*)c->kx, z, 1.0, 1.0);
+    }
+    ck(hipGetLastError());
+    return NC_OK;
+  });
+}
+
+int nc_dense_inverse(double* a, int n, int* iwork, double* dwork, void* stream) {
+  if (n < 1 || n > NC_DENSE_MAX || !a || !iwork || !dwork) return NC_EINVAL;
+  return guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    launch_gauss_jordan(st, a, n, iwork, dwork);
+    launch_dense_transpose(st, a, a + (size_t)n * n, n);
     ck(hipGetLastError());
     return NC_OK;
   });

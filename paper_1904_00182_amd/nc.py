@@ -15,12 +15,13 @@ from .build import lib_path
 NC_OK, NC_NOT_CONVERGED = 0, 1
 NC_EINVAL, NC_ENOMEM, NC_EHIP, NC_ENAN = -1, -2, -3, -4
 NC_FP64, NC_MIXED = 0, 1
+NC_DENSE_MAX = 2000   # largest coarsest-grid system inverted densely
 
 EXPORTED = [
     "nc_problem_default", "nc_workspace_bytes", "nc_create", "nc_destroy", "nc_status_string",
     "nc_set_design", "nc_get_gamma", "nc_residual", "nc_linearize", "nc_jac_apply", "nc_jacT_apply",
     "nc_jac_apply_f32", "nc_jacT_apply_f32", "nc_solve_state", "nc_objective", "nc_objective_grad",
-    "nc_solve_adjoint", "nc_sensitivity", "nc_cone_filter", "nc_set_timing", "nc_get_timing",
+    "nc_solve_adjoint", "nc_sensitivity", "nc_precondition", "nc_cone_filter", "nc_dense_inverse", "nc_set_timing", "nc_get_timing",
 ]
 
 TIMER_CLASSES = ["residual", "jv", "jtw", "smooth", "smooth_T", "pt_residual", "diag", "uproj", "transfer",
@@ -48,6 +49,7 @@ class NCProblem(ctypes.Structure):
         ("smooth_omega", ctypes.c_double),
         ("smooth_pre_coarse", ctypes.c_int), ("smooth_post_coarse", ctypes.c_int),
         ("krylov_rtol_mixed", ctypes.c_double), ("gs_passes", ctypes.c_int),
+        ("coarse_tail", ctypes.c_int),
     ]
 
 
@@ -86,6 +88,7 @@ def load():
             "nc_residual": (I, [V, V, V]),
             "nc_linearize": (I, [V, V]),
             "nc_jac_apply": (I, [V, V, V]),
+            "nc_precondition": (I, [V, I, V, V, V]),
             "nc_jacT_apply": (I, [V, V, V]),
             "nc_jac_apply_f32": (I, [V, V, V]),
             "nc_jacT_apply_f32": (I, [V, V, V]),
@@ -95,6 +98,7 @@ def load():
             "nc_solve_adjoint": (I, [V, V, V, V, ctypes.POINTER(NCInfo)]),
             "nc_sensitivity": (I, [V, V, V, V, V]),
             "nc_cone_filter": (I, [I, I, I, D, V, V, I, V]),
+            "nc_dense_inverse": (I, [V, I, V, V, V]),
             "nc_set_timing": (I, [V, I]),
             "nc_get_timing": (I, [V, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D), I]),
         }
@@ -211,6 +215,16 @@ class Solver:
         _check(f(self.ctx, _ptr(v), _ptr(y)), "nc_jac_apply")
         return y
 
+    def precondition(self, s, v, transpose=False):
+        """z = M^-1 v (M^-T v) for the (P, T) pairs v [N][2]: one multigrid V-cycle of the
+        Krylov preconditioner, with the hierarchy rebuilt at the state s [N][5]."""
+        s = self._in(s, (self.N, 5), torch.float64)
+        v = self._in(v, (self.N, 2), torch.float64)
+        z = torch.empty((self.N, 2), dtype=torch.float64, device=self.device)
+        _check(self.lib.nc_precondition(self.ctx, 1 if transpose else 0, _ptr(s), _ptr(v), _ptr(z)),
+               "nc_precondition")
+        return z
+
     def solve_state(self, s0=None, out=None):
         s = out if out is not None else self._vec()
         if s0 is not None:
@@ -281,3 +295,18 @@ def cone_filter(x, nx, ny, nz, radius, stream=None):
     _check(load().nc_cone_filter(nx, ny, nz, float(radius), _ptr(x), _ptr(y), 0, _stream_handle(st)),
            "nc_cone_filter")
     return y
+
+
+def dense_inverse(a, stream=None):
+    """(A^-1, (A^-1)^T) of a square float64 device tensor via nc_dense_inverse, the
+    multigrid's coarsest-grid inverse."""
+    n = a.shape[0]
+    if a.dim() != 2 or a.shape[1] != n:
+        raise ValueError("dense_inverse needs a square matrix")
+    buf = torch.empty(2 * n * n, dtype=torch.float64, device=a.device)
+    buf[: n * n].copy_(a.reshape(-1))
+    iwork = torch.empty(2 * max(n, 1), dtype=torch.int32, device=a.device)
+    dwork = torch.empty(2 * max(n, 1), dtype=torch.float64, device=a.device)
+    st = stream if stream is not None else torch.cuda.current_stream(a.device)
+    _check(load().nc_dense_inverse(_ptr(buf), n, _ptr(iwork), _ptr(dwork), _stream_handle(st)), "nc_dense_inverse")
+    return buf[: n * n].view(n, n), buf[n * n:].view(n, n)

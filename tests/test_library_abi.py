@@ -48,6 +48,8 @@ def test_host_only_entry_points():
     assert nc.workspace_bytes(bad) == 0
     assert lib.nc_status_string(-2) == b"workspace too small"
     assert lib.nc_create(ctypes.byref(p), None, 0, None, ctypes.byref(ctypes.c_void_p())) == nc.NC_EINVAL
+    for n in (0, -1, nc.NC_DENSE_MAX + 1):
+        assert lib.nc_dense_inverse(None, n, None, None, None) == nc.NC_EINVAL
 
 
 def test_ctypes_struct_matches_header_fields():
