@@ -626,7 +626,8 @@ constexpr int KB_MAX = RED_BLOCKS / 4;   // blocks; partials of column c at part
 // (sqrt of the column sum for c >= sqrt_from).  One block: (column, 16 lanes), each lane
 // with 8 independent loads in flight.
 __global__ __launch_bounds__(KBS) void reduce_cols_kernel(const double* __restrict__ part, long stride, int nblk,
-                                                          int ncol, int sqrt_from, double* __restrict__ out) {
+                                                          int ncol, int sqrt_from, double* __restrict__ out,
+                                                          double* __restrict__ hout) {
   constexpr int LN = 16;
   for (int c0 = 0; c0 < ncol; c0 += KBS / LN) {
     const int c = c0 + (int)(threadIdx.x / LN), sub = threadIdx.x % LN;
@@ -644,7 +645,11 @@ __global__ __launch_bounds__(KBS) void reduce_cols_kernel(const double* __restri
     }
 #pragma unroll
     for (int off = LN / 2; off > 0; off >>= 1) s += __shfl_down(s, off, LN);
-    if (sub == 0 && c < ncol) out[c] = c >= sqrt_from ? sqrt(s) : s;
+    if (sub == 0 && c < ncol) {
+      const double v = c >= sqrt_from ? sqrt(s) : s;
+      out[c] = v;
+      if (hout) hout[c] = v;
+    }
   }
 }
 
@@ -739,11 +744,11 @@ static int stream_blocks(long n) {
 
 template <typename T>
 void launch_mdot(hipStream_t st, const T* V, long ld, int cnt, const T* w, long n, double* part, double* out,
-                 bool with_norm) {
+                 bool with_norm, double* hout) {
   const int nb = stream_blocks<T>(n);
   const int ncol = cnt + (with_norm ? 1 : 0);
   launch(mdot_kernel<T>, dim3(nb), dim3(KBS), 0, st, V, ld, cnt, w, n, with_norm ? 1 : 0, part);
-  launch(reduce_cols_kernel, dim3(1), dim3(KBS), 0, st, part, (long)RED_BLOCKS, nb, ncol, ncol, out);
+  launch(reduce_cols_kernel, dim3(1), dim3(KBS), 0, st, part, (long)RED_BLOCKS, nb, ncol, ncol, out, hout);
 }
 
 // out[c] = sum over blocks of part[b][c] in a fixed order; sqrt if do_sqrt.  One block of
@@ -853,12 +858,12 @@ __global__ __launch_bounds__(KBS) __attribute__((amdgpu_waves_per_eu(4))) void m
 
 template <typename T>
 void launch_maxpy(hipStream_t st, const T* V, long ld, int cnt, const double* h, double sign, T* w, long n, double* part,
-                  double* nrm_out) {
+                  double* nrm_out, double* hnrm_out) {
   const int nb = stream_blocks<T>(n);
   launch(maxpy_kernel<T>, dim3(nb), dim3(KBS), 0, st, V, ld, cnt, h, sign, w, n,
                      nrm_out ? part : nullptr);
   if (nrm_out)
-    launch(reduce_cols_kernel, dim3(1), dim3(KBS), 0, st, part, (long)RED_BLOCKS, nb, 1, 0, nrm_out);
+    launch(reduce_cols_kernel, dim3(1), dim3(KBS), 0, st, part, (long)RED_BLOCKS, nb, 1, 0, nrm_out, hnrm_out);
 }
 
 template <typename T>
@@ -1112,8 +1117,8 @@ void launch_objective_grad(hipStream_t st, const Grid& g, const Patch& patch, do
   template void launch_pc_in<T>(hipStream_t, const Grid&, T*, const double*, T, T, const T*, bool, T, T*, T*); \
   template void launch_pack_pt<T>(hipStream_t, long, const double*, T*, double, double);             \
   template void launch_unpack_pt<T>(hipStream_t, const Grid&, const T*, double*);                    \
-  template void launch_mdot<T>(hipStream_t, const T*, long, int, const T*, long, double*, double*, bool); \
-  template void launch_maxpy<T>(hipStream_t, const T*, long, int, const double*, double, T*, long, double*, double*); \
+  template void launch_mdot<T>(hipStream_t, const T*, long, int, const T*, long, double*, double*, bool, double*); \
+  template void launch_maxpy<T>(hipStream_t, const T*, long, int, const double*, double, T*, long, double*, double*, double*); \
   template void launch_scale_inv<T>(hipStream_t, const double*, const T*, T*, long);                \
   template void launch_norm<T>(hipStream_t, const T*, long, double*, double*);                     \
   template void launch_diag_scale<T>(hipStream_t, const Grid&, const T*, bool, T, const T*, T*);    \

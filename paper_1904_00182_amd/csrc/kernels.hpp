@@ -104,14 +104,16 @@ void launch_rsub(hipStream_t st, const T* b, T* out, long n);                   
 // RED_BLOCKS * MAXC doubles for the per-block partial sums.
 constexpr int RED_BLOCKS = 2048;
 constexpr int MAXC = 32;
-// out[c] = V[c] . w for c < cnt (and out[cnt] = w . w when with_norm)
+// out[c] = V[c] . w for c < cnt (and out[cnt] = w . w when with_norm); hout, when not
+// null (pinned host memory), receives the same values from the same kernel
 template <typename T>
 void launch_mdot(hipStream_t st, const T* V, long ld, int cnt, const T* w, long n, double* part, double* out,
-                 bool with_norm = false);
+                 bool with_norm = false, double* hout = nullptr);
 // w += sign * sum_c h[c] V[c]; if nrm_out != null also nrm_out[0] = ||w||_2 after the update
+// (and hnrm_out[0], pinned host memory, when not null)
 template <typename T>
 void launch_maxpy(hipStream_t st, const T* V, long ld, int cnt, const double* h, double sign, T* w, long n,
-                  double* part, double* nrm_out);
+                  double* part, double* nrm_out, double* hnrm_out = nullptr);
 template <typename T>
 void launch_scale_inv(hipStream_t st, const double* nrm, const T* w, T* v, long n);
 // per-field 2-norms of [N][5] arrays: out[f] = ||a_f||, and if b != null out[5+f] = ||b_f||

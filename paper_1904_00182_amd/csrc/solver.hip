@@ -421,11 +421,12 @@ constexpr int HSLOT = 2 * MAXC + 8;   // doubles per Hessenberg slot: h1 [MAXC],
 
 // Solves D A x = b (A the (P, T) block of J~, A^T when tr, D the P and T row scales) from
 // x = 0 with right preconditioning.  Each Arnoldi step orthogonalises by classical
-// Gram-Schmidt applied twice ("twice is enough", Kahan and Parlett) entirely on the
-// device and copies its Hessenberg column to its own pinned slot.  The host runs one
-// step behind: it enqueues step j, then waits for and processes the column of step j-1
-// (Givens rotations, convergence test), so the device never idles on the host's round
-// trip; the step enqueued past convergence is discarded.
+// Gram-Schmidt (gs_passes times; two passes are "twice is enough", Kahan and Parlett)
+// entirely on the device, and its reduction kernels also store the Hessenberg column in
+// the step's own pinned host slot.  The host runs one step behind: it enqueues step j,
+// then waits for and processes the column of step j-1 (Givens rotations, convergence
+// test), so the device never idles on the host's round trip; the step enqueued past
+// convergence is discarded.
 template <typename T>
 int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double* relres) {
   hipStream_t st = c->stream;
@@ -454,12 +455,15 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
     // v_j arrives unnormalised from step j-1 (its norm is still in dres); step 0's is normal
     precondition_pt<T>(c, tr, vj, zj, rows, j > 0 ? dres + 2 * MAXC : nullptr);
     apply_pt<T>(c, tr, zj, w, rows);
+    // the reductions store the Hessenberg column into the step's pinned slot as well
+    double* hs = c->hslots + (size_t)j * HSLOT;
     for (int pass = 0; pass < passes; ++pass) {
-      { Timed tm(c, TC_MDOT, sizeof(T) * (double)(j + 2) * n); launch_mdot<T>(st, V, ld, j + 1, w, n, c->part, dres + pass * MAXC, false); }
+      const bool last = pass == passes - 1;
+      { Timed tm(c, TC_MDOT, sizeof(T) * (double)(j + 2) * n); launch_mdot<T>(st, V, ld, j + 1, w, n, c->part, dres + pass * MAXC, false, hs + pass * MAXC); }
       { Timed tm(c, TC_MAXPY, sizeof(T) * (double)(j + 3) * n);
-        launch_maxpy<T>(st, V, ld, j + 1, dres + pass * MAXC, -1.0, w, n, c->part, pass == passes - 1 ? dres + 2 * MAXC : nullptr); }
+        launch_maxpy<T>(st, V, ld, j + 1, dres + pass * MAXC, -1.0, w, n, c->part, last ? dres + 2 * MAXC : nullptr,
+                        last ? hs + 2 * MAXC : nullptr); }
     }
-    ck(hipMemcpyAsync(c->hslots + (size_t)j * HSLOT, dres, sizeof(double) * (2 * MAXC + 1), hipMemcpyDeviceToHost, st));
     ck(hipEventRecord(c->kev[j], st));
   };
   while (true) {
