@@ -28,6 +28,15 @@ struct Grid {
   }
 };
 
+// A node's (P, T) pair and its 2x2 block as single aligned vectors (the [N][2] and [N][4]
+// layouts start every node on a multiple of the vector size).
+template <typename T> struct Pair;
+template <> struct Pair<float> { using type = float2; };
+template <> struct Pair<double> { using type = double2; };
+template <typename T> struct Quad;
+template <> struct Quad<float> { using type = float4; };
+template <> struct Quad<double> { using type = double4; };
+
 // Read-only view of one level's linearisation for the operator kernels.
 template <typename T>
 struct LevelView {

@@ -461,7 +461,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
   for (int n = t; n < N; n += TAIL_THREADS) {
     int I, J, K;
     tail_ijk(n, g.nx + 1, g.ny + 1, I, J, K);
-    double sp, stt;
+    TAcc<T> sp, stt;
     restrict_taps(gu, I, J, K, a.ru, sp, stt);
     const T bp = g.pfix(I, J, K) ? (T)0 : (T)sp;
     const T bt = g.tfix(I, J, K) ? (T)0 : (T)stt;
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
     for (int n = t; n < Nc; n += TAIL_THREADS) {
       int I, J, K;
       tail_ijk(n, gc.nx + 1, gc.ny + 1, I, J, K);
-      double sp, stt;
+      TAcc<T> sp, stt;
       restrict_taps(g, I, J, K, (const T*)y, sp, stt);
       bc[2 * n] = gc.pfix(I, J, K) ? (T)0 : (T)sp;
       bc[2 * n + 1] = gc.tfix(I, J, K) ? (T)0 : (T)stt;
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
     for (int n = t; n < N; n += TAIL_THREADS) {
       int I, J, K;
       tail_ijk(n, g.nx + 1, g.ny + 1, I, J, K);
-      double sp, stt;
+      TAcc<T> sp, stt;
       prolong_taps(gc, I, J, K, (const T*)xc, sp, stt);
       if (!g.pfix(I, J, K)) x[2 * n] += (T)sp;
       if (!g.tfix(I, J, K)) x[2 * n + 1] += (T)stt;
@@ -591,7 +591,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
       if (n < Nu) {
         int i, j, k;
         tail_ijk(n, gu.nx + 1, gu.ny + 1, i, j, k);
-        double sp, stt;
+        TAcc<T> sp, stt;
         prolong_taps(g, i, j, k, (const T*)x, sp, stt);
         if (!gu.pfix(i, j, k)) a.xu[2 * n] = up[r] + (T)sp;
         if (!gu.tfix(i, j, k)) a.xu[2 * n + 1] = ut[r] + (T)stt;

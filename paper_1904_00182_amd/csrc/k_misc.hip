@@ -45,17 +45,17 @@ __global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf
   const PlaneIdx q = plane_idx(coarse);
   if (!q.ok) return;
   const int I = q.i, J = q.j, K = q.k;
-  double sp, stt;
+  TAcc<T> sp, stt;
   restrict_taps(fine, I, J, K, rf, sp, stt);
+  using P2 = typename Pair<T>::type;
   const int n = coarse.node(I, J, K);
   const T bp = coarse.pfix(I, J, K) ? (T)0 : (T)sp;
   const T bt = coarse.tfix(I, J, K) ? (T)0 : (T)stt;
-  bc[2 * n] = bp;
-  bc[2 * n + 1] = bt;
+  reinterpret_cast<P2*>(bc)[n] = P2{bp, bt};
   if (dinv) {
-    const T* D = dinv + 4 * n;
-    xc[2 * n] = omega * (D[0] * bp + D[transpose ? 2 : 1] * bt);
-    xc[2 * n + 1] = omega * (D[transpose ? 1 : 2] * bp + D[3] * bt);
+    const typename Quad<T>::type D = reinterpret_cast<const typename Quad<T>::type*>(dinv)[n];
+    reinterpret_cast<P2*>(xc)[n] =
+        P2{omega * (D.x * bp + (transpose ? D.z : D.y) * bt), omega * ((transpose ? D.y : D.z) * bp + D.w * bt)};
   }
 }
 
@@ -65,11 +65,14 @@ __global__ void prolong_kernel(Grid fine, Grid coarse, const T* __restrict__ xc,
   const PlaneIdx q = plane_idx(fine);
   if (!q.ok) return;
   const int i = q.i, j = q.j, k = q.k;
-  double sp, stt;
+  TAcc<T> sp, stt;
   prolong_taps(coarse, i, j, k, xc, sp, stt);
+  using P2 = typename Pair<T>::type;
   const int n = fine.node(i, j, k);
-  if (!fine.pfix(i, j, k)) xf[2 * n] += (T)sp;
-  if (!fine.tfix(i, j, k)) xf[2 * n + 1] += (T)stt;
+  P2 v = reinterpret_cast<const P2*>(xf)[n];
+  if (!fine.pfix(i, j, k)) v.x += (T)sp;
+  if (!fine.tfix(i, j, k)) v.y += (T)stt;
+  reinterpret_cast<P2*>(xf)[n] = v;
 }
 
 template <typename T>
@@ -455,24 +458,25 @@ void launch_pack_state(hipStream_t st, const Grid& g, const double* s5, T* pt) {
 template <typename T>
 __global__ void pc_in_kernel(Grid g, T* __restrict__ v, const double* __restrict__ nrm, T inv_p, T inv_t,
                              const T* __restrict__ dinv, int transpose, T omega, T* __restrict__ b, T* __restrict__ x) {
+  using P2 = typename Pair<T>::type;
+  using Q4 = typename Quad<T>::type;
   const PlaneIdx q = plane_idx(g);
   if (!q.ok) return;
   const int n = g.node(q.i, q.j, q.k);
-  T vp = v[2 * n], vt = v[2 * n + 1];
+  const P2 vv = reinterpret_cast<const P2*>(v)[n];
+  T vp = vv.x, vt = vv.y;
   if (nrm) {   // normalise the new Krylov vector in place (v <- v / |v|)
     const double s = 1.0 / nrm[0];
     vp = (T)(s * (double)vp);
     vt = (T)(s * (double)vt);
-    v[2 * n] = vp;
-    v[2 * n + 1] = vt;
+    reinterpret_cast<P2*>(v)[n] = P2{vp, vt};
   }
   const T bp = g.pfix(q.i, q.j, q.k) ? (T)0 : inv_p * vp;
   const T bt = g.tfix(q.i, q.j, q.k) ? (T)0 : inv_t * vt;
-  b[2 * n] = bp;
-  b[2 * n + 1] = bt;
-  const T* D = dinv + 4 * n;
-  x[2 * n] = omega * (D[0] * bp + D[transpose ? 2 : 1] * bt);
-  x[2 * n + 1] = omega * (D[transpose ? 1 : 2] * bp + D[3] * bt);
+  reinterpret_cast<P2*>(b)[n] = P2{bp, bt};
+  const Q4 D = reinterpret_cast<const Q4*>(dinv)[n];
+  reinterpret_cast<P2*>(x)[n] =
+      P2{omega * (D.x * bp + (transpose ? D.z : D.y) * bt), omega * ((transpose ? D.y : D.z) * bp + D.w * bt)};
 }
 template <typename T>
 void launch_pc_in(hipStream_t st, const Grid& g, T* v, const double* nrm, T inv_p, T inv_t, const T* dinv,
@@ -603,10 +607,12 @@ __device__ inline double hsum(double2 a, double2 b) { return a.x * b.x + a.y * b
 //
 // Both kernels split the vectors into one contiguous chunk per block and walk it in
 // sub-tiles of KBS x KT<T>::U 16-byte vectors.  The multi-dot keeps the sub-tile of w in
-// registers and streams the basis vectors in groups of KG (KG x KT<T>::U loads in flight per
-// thread), so w and every basis vector are read once; each wave reduces its partial dot
-// products and its lane 0 adds them to the wave's own row of LDS sums (no barrier between
-// groups); the block adds the wave rows in order at the end.  Full sub-tiles take
+// registers and streams the basis vectors in groups of KGT<T>::G, issuing each group's loads
+// before the previous group is used (two groups of KT<T>::U loads in flight per thread), so
+// w and every basis vector are read once and the memory system does not wait on the
+// reductions; each wave reduces its partial dot products and its lane 0 adds them to the
+// wave's own row of LDS sums (no barrier between groups); the block adds the wave rows in
+// order at the end.  Every block but the last covers whole sub-tiles.  Full sub-tiles take
 // unguarded vector loads, so the loads of a group are all in flight together.  A second,
 // one-block launch adds the per-block sums in block order, so results are deterministic;
 // the launch boundary makes the partials visible across the chip's L2 caches (a
@@ -619,8 +625,15 @@ template <typename T>
 struct KT {
   static constexpr int U = sizeof(T) == 4 ? 2 : 4;
 };
-constexpr int KG = 4;      // basis vectors per group
-constexpr int KB_MAX = RED_BLOCKS / 4;   // blocks; partials of column c at part[c * RED_BLOCKS + b]
+// basis vectors per group; two groups are in flight at a time (the next group's loads are
+// issued before the current group is used), so that the memory system never waits for a
+// group's reductions
+template <typename T>
+struct KGT {
+  static constexpr int G = sizeof(T) == 4 ? 4 : 2;    // multi-dot
+  static constexpr int GA = sizeof(T) == 4 ? 2 : 1;   // multi-axpy (its float64 accumulators take the rest)
+};
+// blocks: at most RED_BLOCKS (partials of column c at part[c * RED_BLOCKS + b])
 
 // out[c] = sum over b < nblk of part[c * stride + b] for c < ncol, in a fixed order
 // (sqrt of the column sum for c >= sqrt_from).  One block: (column, 16 lanes), each lane
@@ -670,11 +683,43 @@ __device__ inline typename Vec16<T>::type load16(const T* __restrict__ p, long i
   return r;
 }
 
-// Contiguous chunk of 16-byte vectors of block b: [beg, end)
+// Contiguous chunk of 16-byte vectors of block b, [beg, end): whole sub-tiles, so that only
+// the last block ends in a partial one
+template <typename T>
 __device__ inline void block_chunk(long nvt, long& beg, long& end) {
-  const long per = (nvt + gridDim.x - 1) / gridDim.x;
+  constexpr long SUB = (long)KBS * KT<T>::U;
+  const long per = ((nvt + gridDim.x - 1) / gridDim.x + SUB - 1) / SUB * SUB;
   beg = (long)blockIdx.x * per;
   end = beg + per < nvt ? beg + per : nvt;
+}
+
+// One group of the multi-dot's basis vectors (column c0 + g; past cnt, w itself for the
+// norm column or as filler)
+template <bool FULL, typename T>
+__device__ __attribute__((always_inline)) inline void mdot_load(const T* __restrict__ V, long ld, int cnt,
+                                                                const T* __restrict__ w, int c0, long base, long end,
+                                                                long nv, long n,
+                                                                typename Vec16<T>::type (&vt)[KGT<T>::G][KT<T>::U]) {
+#pragma unroll
+  for (int g = 0; g < KGT<T>::G; ++g) {
+    const T* v = c0 + g < cnt ? V + (long)(c0 + g) * ld : w;
+#pragma unroll
+    for (int u = 0; u < KT<T>::U; ++u) vt[g][u] = load16<FULL>(v, base + u * KBS + threadIdx.x, end, nv, n);
+  }
+}
+template <typename T>
+__device__ __attribute__((always_inline)) inline void mdot_use(const typename Vec16<T>::type (&vt)[KGT<T>::G][KT<T>::U],
+                                                               const typename Vec16<T>::type (&wt)[KT<T>::U], int c0,
+                                                               int ncol, double (*wpart)[MAXC + 1]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int g = 0; g < KGT<T>::G; ++g) {
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < KT<T>::U; ++u) s += hsum(vt[g][u], wt[u]);
+    s = wave_sum(s);
+    if (lane == 0 && c0 + g < ncol) wpart[wv][c0 + g] += s;
+  }
 }
 
 // One sub-tile of the multi-dot: lane 0 of each wave adds the wave's partial dot products
@@ -683,27 +728,17 @@ template <bool FULL, typename T>
 __device__ inline void mdot_subtile(const T* __restrict__ V, long ld, int cnt, int ncol, const T* __restrict__ w,
                                     long base, long end, long nv, long n, double (*wpart)[MAXC + 1]) {
   using V16 = typename Vec16<T>::type;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int G = KGT<T>::G;
   V16 wt[KT<T>::U];
 #pragma unroll
   for (int u = 0; u < KT<T>::U; ++u) wt[u] = load16<FULL>(w, base + u * KBS + threadIdx.x, end, nv, n);
-  for (int c0 = 0; c0 < ncol; c0 += KG) {
-    V16 vt[KG][KT<T>::U];
-#pragma unroll
-    for (int g = 0; g < KG; ++g) {
-      const int c = c0 + g < cnt ? c0 + g : -1;   // -1: the norm column or unused
-      const T* v = c >= 0 ? V + (long)c * ld : w;
-#pragma unroll
-      for (int u = 0; u < KT<T>::U; ++u) vt[g][u] = load16<FULL>(v, base + u * KBS + threadIdx.x, end, nv, n);
-    }
-#pragma unroll
-    for (int g = 0; g < KG; ++g) {
-      double s = 0.0;
-#pragma unroll
-      for (int u = 0; u < KT<T>::U; ++u) s += hsum(vt[g][u], wt[u]);
-      s = wave_sum(s);
-      if (lane == 0 && c0 + g < ncol) wpart[wv][c0 + g] += s;
-    }
+  V16 va[G][KT<T>::U], vb[G][KT<T>::U];
+  mdot_load<FULL>(V, ld, cnt, w, 0, base, end, nv, n, va);
+  for (int c0 = 0; c0 < ncol; c0 += 2 * G) {
+    if (c0 + G < ncol) mdot_load<FULL>(V, ld, cnt, w, c0 + G, base, end, nv, n, vb);
+    mdot_use<T>(va, wt, c0, ncol, wpart);
+    if (c0 + 2 * G < ncol) mdot_load<FULL>(V, ld, cnt, w, c0 + 2 * G, base, end, nv, n, va);
+    if (c0 + G < ncol) mdot_use<T>(vb, wt, c0 + G, ncol, wpart);
   }
 }
 
@@ -720,7 +755,7 @@ __global__ __launch_bounds__(KBS) __attribute__((amdgpu_waves_per_eu(4))) void m
     for (int c = 0; c <= MAXC; ++c) wpart[wv][c] = 0.0;
   const long nv = n / VW, nvt = (n + VW - 1) / VW;
   long beg, end;
-  block_chunk(nvt, beg, end);
+  block_chunk<T>(nvt, beg, end);
   const long lim = end < nv ? end : nv;
   for (long base = beg; base < end; base += (long)KBS * KT<T>::U) {
     if (base + (long)KBS * KT<T>::U <= lim) mdot_subtile<true>(V, ld, cnt, ncol, w, base, end, nv, n, wpart);
@@ -735,11 +770,12 @@ __global__ __launch_bounds__(KBS) __attribute__((amdgpu_waves_per_eu(4))) void m
   }
 }
 
-// blocks for streaming n elements: at least one 16-byte vector per thread, at most KB_MAX
+// blocks for streaming n elements: one sub-tile each, at most RED_BLOCKS
 template <typename T>
 static int stream_blocks(long n) {
   const long nvt = (n + Vec16<T>::W - 1) / Vec16<T>::W;
-  return (int)std::max<long>(1, std::min<long>(KB_MAX, (nvt + KBS - 1) / KBS));
+  const long sub = (long)KBS * KT<T>::U;
+  return (int)std::max<long>(1, std::min<long>(RED_BLOCKS, (nvt + sub - 1) / sub));
 }
 
 template <typename T>
@@ -770,6 +806,34 @@ __global__ __launch_bounds__(1024) void reduce_parts_kernel(const double* __rest
   if (sub == 0 && c < cnt) out[c] = do_sqrt ? sqrt(s) : s;
 }
 
+// One group of the multi-axpy's basis vectors (rows past cnt re-read row c0 with weight 0)
+template <bool FULL, typename T>
+__device__ __attribute__((always_inline)) inline void maxpy_load(const T* __restrict__ V, long ld, int cnt, int c0,
+                                                                 long base, long end, long nv, long n,
+                                                                 typename Vec16<T>::type (&vt)[KGT<T>::GA][KT<T>::U]) {
+#pragma unroll
+  for (int g = 0; g < KGT<T>::GA; ++g) {
+    const T* v = V + (long)(c0 + g < cnt ? c0 + g : c0) * ld;
+#pragma unroll
+    for (int u = 0; u < KT<T>::U; ++u) vt[g][u] = load16<FULL>(v, base + u * KBS + threadIdx.x, end, nv, n);
+  }
+}
+template <typename T>
+__device__ __attribute__((always_inline)) inline void maxpy_use(const typename Vec16<T>::type (&vt)[KGT<T>::GA][KT<T>::U],
+                                                                const double* hs, int cnt, int c0,
+                                                                double (&a)[KT<T>::U][Vec16<T>::W]) {
+#pragma unroll
+  for (int g = 0; g < KGT<T>::GA; ++g) {
+    const double hc = c0 + g < cnt ? hs[c0 + g] : 0.0;
+#pragma unroll
+    for (int u = 0; u < KT<T>::U; ++u) {
+      const T* pv = reinterpret_cast<const T*>(&vt[g][u]);
+#pragma unroll
+      for (int q = 0; q < Vec16<T>::W; ++q) a[u][q] += hc * (double)pv[q];
+    }
+  }
+}
+
 // One sub-tile of the multi-axpy; returns the partial sum of squares of the result.
 template <bool FULL, typename T>
 __device__ inline double maxpy_subtile(const T* __restrict__ V, long ld, int cnt, const double* hs, T* __restrict__ w,
@@ -784,24 +848,14 @@ __device__ inline double maxpy_subtile(const T* __restrict__ V, long ld, int cnt
 #pragma unroll
     for (int q = 0; q < VW; ++q) a[u][q] = (double)pw[q];
   }
-  for (int c0 = 0; c0 < cnt; c0 += KG) {
-    V16 vt[KG][KT<T>::U];
-#pragma unroll
-    for (int g = 0; g < KG; ++g) {
-      const T* v = V + (long)(c0 + g < cnt ? c0 + g : c0) * ld;   // unused rows re-read row c0 (weight 0)
-#pragma unroll
-      for (int u = 0; u < KT<T>::U; ++u) vt[g][u] = load16<FULL>(v, base + u * KBS + threadIdx.x, end, nv, n);
-    }
-#pragma unroll
-    for (int g = 0; g < KG; ++g) {
-      const double hc = c0 + g < cnt ? hs[c0 + g] : 0.0;
-#pragma unroll
-      for (int u = 0; u < KT<T>::U; ++u) {
-        const T* pv = reinterpret_cast<const T*>(&vt[g][u]);
-#pragma unroll
-        for (int q = 0; q < VW; ++q) a[u][q] += hc * (double)pv[q];
-      }
-    }
+  constexpr int G = KGT<T>::GA;
+  V16 va[G][KT<T>::U], vb[G][KT<T>::U];
+  maxpy_load<FULL>(V, ld, cnt, 0, base, end, nv, n, va);
+  for (int c0 = 0; c0 < cnt; c0 += 2 * G) {
+    if (c0 + G < cnt) maxpy_load<FULL>(V, ld, cnt, c0 + G, base, end, nv, n, vb);
+    maxpy_use<T>(va, hs, cnt, c0, a);
+    if (c0 + 2 * G < cnt) maxpy_load<FULL>(V, ld, cnt, c0 + 2 * G, base, end, nv, n, va);
+    if (c0 + G < cnt) maxpy_use<T>(vb, hs, cnt, c0 + G, a);
   }
   double nrm = 0.0;
 #pragma unroll
@@ -837,7 +891,7 @@ __global__ __launch_bounds__(KBS) __attribute__((amdgpu_waves_per_eu(4))) void m
   __syncthreads();
   const long nv = n / VW, nvt = (n + VW - 1) / VW;
   long beg, end;
-  block_chunk(nvt, beg, end);
+  block_chunk<T>(nvt, beg, end);
   const long lim = end < nv ? end : nv;
   double nrm = 0.0;
   for (long base = beg; base < end; base += (long)KBS * KT<T>::U) {

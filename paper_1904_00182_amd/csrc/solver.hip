@@ -825,7 +825,7 @@ void nc_problem_default(nc_problem* p, int nx, int ny, int nz) {
   p->krylov_rtol_mixed = 6e-5;
   p->gs_passes = 1;
   p->coarse_tail = 1;
-  p->adjoint_rtol = 1e-10;
+  p->adjoint_rtol = 3e-11;
   p->newton_maxit = 30;
   p->krylov_restart = 24;
   p->krylov_maxit = 400;
