@@ -425,8 +425,9 @@ constexpr int HSLOT = 2 * MAXC + 8;   // doubles per Hessenberg slot: h1 [MAXC],
 // entirely on the device, and its reduction kernels also store the Hessenberg column in
 // the step's own pinned host slot.  The host runs one step behind: it enqueues step j,
 // then waits for and processes the column of step j-1 (Givens rotations, convergence
-// test), so the device never idles on the host's round trip; the step enqueued past
-// convergence is discarded.
+// test), so the device does not idle on the host's round trip -- except before a step
+// predicted to end the solve, where it waits rather than enqueue a step that would be
+// discarded.
 template <typename T>
 int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double* relres) {
   hipStream_t st = c->stream;
@@ -466,6 +467,14 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
     }
     ck(hipEventRecord(c->kev[j], st));
   };
+  // relative residuals of the last two processed steps, and whether the next step
+  // processed is expected to end the solve
+  double res_prev = -1.0, res_prev2 = -1.0;
+  auto likely_done = [&]() -> bool {
+    if (total + 1 >= maxit) return true;
+    if (!(res_prev > 0.0 && res_prev2 > 0.0)) return false;
+    return res_prev * (res_prev / res_prev2) <= rtol;
+  };
   while (true) {
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -495,15 +504,26 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
       jend = j + 1;
       const double res = std::fabs(g[j + 1]) / bnorm;
       *relres = res;
+      res_prev2 = res_prev;
+      res_prev = res;
       if (!std::isfinite(res)) bad = true;
       if (bad || res <= rtol || total >= maxit || hn == 0.0) done = true;
       return done;
     };
-    for (int j = 0; j < m && !stop; ++j) {
-      enqueue(j);
-      if (j > 0) stop = process(j - 1);
+    // Step j+1 is enqueued before step j is processed (so the device does not wait for the
+    // host), unless step j is predicted to end the solve: then the host waits for step j
+    // first, and enqueues step j+1 only if the solve goes on.  The prediction extrapolates
+    // the last contraction of the residual; a wrong guess costs one host round trip, a
+    // right one the whole discarded step.
+    enqueue(0);
+    for (int j = 0;; ++j) {
+      const bool more = j + 1 < m;
+      const bool spec = more && !likely_done();
+      if (spec) enqueue(j + 1);
+      stop = process(j);
+      if (stop || !more) break;
+      if (!spec) enqueue(j + 1);
     }
-    if (!stop) process(jend);   // the cycle's last step (jend == m - 1 here)
     if (bad) {
       sync(c);
       return -1;
