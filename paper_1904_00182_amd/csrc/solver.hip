@@ -103,6 +103,8 @@ struct nc_ctx {
   // bookkeeping
   bool design_set;
   bool hier_valid;       // multigrid hierarchy (node-block inverses, coarse inverse) built for this design
+  bool rows_valid;       // rows64 / rows32 and res_floor computed for this design
+  double res_floor;      // round-off floor of the scaled residual
   // optional event timing per kernel class
   bool timing;
   std::vector<hipEvent_t> ev;
@@ -403,15 +405,22 @@ const Scale5<float>* row_scales<float>(nc_ctx* c) { return &c->krow32; }
 
 // Constant per-field row scales ~ 1 / (diagonal of each field's block): lumped mass for
 // the velocity rows, (8h/3) kappa_mean/mu and (8h/3) k_mean for the P and T rows.
+// They depend on the design only and are computed once per design; every solve starts its
+// Krylov row weights from them.
+double residual_floor(nc_ctx* c);
 void compute_row_scales(nc_ctx* c) {
-  const Level& L0 = c->lev[0];
-  launch_coef_sums(c->stream, L0.coef64, c->E, c->part, c->dres);
-  fetch(c, c->dres, 2);
-  const double km = c->hbuf[0] / c->E, kapm = c->hbuf[1] / c->E;
-  const double lap = 8.0 * L0.h / 3.0;
-  const double du = 1.0 / (8.0 * L0.c64.W), dp = 1.0 / (lap * kapm / c->p.mu), dt = 1.0 / (lap * km);
-  c->rows64 = Scale5<double>{{du, du, du, dp, dt}};
-  c->rows32 = Scale5<float>{{(float)du, (float)du, (float)du, (float)dp, (float)dt}};
+  if (!c->rows_valid) {
+    const Level& L0 = c->lev[0];
+    launch_coef_sums(c->stream, L0.coef64, c->E, c->part, c->dres);
+    fetch(c, c->dres, 2);
+    const double km = c->hbuf[0] / c->E, kapm = c->hbuf[1] / c->E;
+    const double lap = 8.0 * L0.h / 3.0;
+    const double du = 1.0 / (8.0 * L0.c64.W), dp = 1.0 / (lap * kapm / c->p.mu), dt = 1.0 / (lap * km);
+    c->rows64 = Scale5<double>{{du, du, du, dp, dt}};
+    c->rows32 = Scale5<float>{{(float)du, (float)du, (float)du, (float)dp, (float)dt}};
+    c->res_floor = residual_floor(c);
+    c->rows_valid = true;
+  }
   c->krow64 = c->rows64;
   c->krow32 = c->rows32;
 }
@@ -533,7 +542,8 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
       for (int k = i + 1; k < jend; ++k) s -= H[i * m + k] * y[k];
       y[i] = s / H[i * m + i];
     }
-    sync(c);   // the discarded speculative step has finished with dres
+    // the coefficients go through the pinned buffer: its last device-to-host use was
+    // synchronised, and any later host write to it follows a synchronising fetch
     std::memcpy(c->hbuf, y.data(), sizeof(double) * jend);
     ck(hipMemcpyAsync(dres + 3 * MAXC, c->hbuf, sizeof(double) * jend, hipMemcpyHostToDevice, st));
     launch_maxpy<T>(st, Z, ld, jend, dres + 3 * MAXC, 1.0, x, n, c->part, nullptr);
@@ -548,7 +558,6 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
     if (beta / bnorm <= rtol) break;
     launch_scale_inv<T>(st, dres, V, V, n);
   }
-  sync(c);
   return total;
 }
 
@@ -618,16 +627,20 @@ double norm64(nc_ctx* c, const double* a) {
   return c->hbuf[0];
 }
 
-// 2-norm of a five-field vector with the per-field row scales of the equilibrated system
-double scaled_norm(nc_ctx* c, const double* a) {
-  launch_field_norms(c->stream, a, nullptr, c->N, c->part, c->dres);
-  fetch(c, c->dres, 5);
+// 2-norm of a five-field vector with the per-field row scales of the equilibrated system,
+// from its fetched per-field norms fn[5] or computed
+double scaled_from(const nc_ctx* c, const double* fn) {
   double s = 0.0;
   for (int f = 0; f < 5; ++f) {
-    const double v = c->rows64.s[f] * c->hbuf[f];
+    const double v = c->rows64.s[f] * fn[f];
     s += v * v;
   }
   return std::sqrt(s);
+}
+double scaled_norm(nc_ctx* c, const double* a) {
+  launch_field_norms(c->stream, a, nullptr, c->N, c->part, c->dres);
+  fetch(c, c->dres, 5);
+  return scaled_from(c, c->hbuf);
 }
 
 // round-off floor of the scaled residual: 1e-12 of the scaled boundary-flux load
@@ -649,7 +662,7 @@ int newton(nc_ctx* c, double* s, nc_info* info) {
   const Level& L0 = c->lev[0];
   launch_mask_state(st, L0.g, s);
   compute_row_scales(c);
-  const double floor = residual_floor(c);
+  const double floor = c->res_floor;
   launch_residual(st, L0.g, L0.c64, c->patch, L0.coef64, s, c->R);
   // merit function of the damped Newton iteration: the residual 2-norm with the per-field
   // row scales (the same root; the scaling keeps the small pressure rows visible)
@@ -672,9 +685,13 @@ int newton(nc_ctx* c, double* s, nc_info* info) {
     if (it >= 2 && its > 2 * first_its + 4) c->hier_valid = false;
     kits += its;
     // d solves J d = R; the Newton step is -d.  Per-field size of the step relative to
-    // the state, taken before the line search.
+    // the state, taken before the line search, fetched together with the residual of the
+    // full step (the first trial of the line search)
     launch_field_norms(st, c->d, s, c->N, c->part, c->dres);
-    fetch(c, c->dres, 10);
+    launch_axpy(st, -1.0, c->d, s, c->strial, c->n5);
+    { Timed tm(c, TC_RESIDUAL, 8.0 * (10 * nn(L0.g) + 2 * ne(L0.g))); launch_residual(st, L0.g, L0.c64, c->patch, L0.coef64, c->strial, c->tmp5); }
+    launch_field_norms(st, c->tmp5, nullptr, c->N, c->part, c->dres + 16);
+    fetch(c, c->dres, 21);
     double step = 0.0, step_pt = 0.0;
     for (int f = 0; f < 5; ++f) {
       const double sf = c->hbuf[5 + f], df = c->hbuf[f];
@@ -689,11 +706,13 @@ int newton(nc_ctx* c, double* s, nc_info* info) {
     // left is about eta |delta| + O(|delta|^2); below the step tolerance no further step
     // is needed
     const bool predicted = relres <= 10.0 * lin_rtol && std::max(relres, step_pt) * step_pt <= p.newton_step_rtol;
-    double lam = 1.0, rt = 0.0;
+    double lam = 1.0, rt = scaled_from(c, c->hbuf + 16);
     while (true) {
-      launch_axpy(st, -lam, c->d, s, c->strial, c->n5);
-      { Timed tm(c, TC_RESIDUAL, 8.0 * (10 * nn(L0.g) + 2 * ne(L0.g))); launch_residual(st, L0.g, L0.c64, c->patch, L0.coef64, c->strial, c->tmp5); }
-      rt = scaled_norm(c, c->tmp5);
+      if (lam < 1.0) {
+        launch_axpy(st, -lam, c->d, s, c->strial, c->n5);
+        { Timed tm(c, TC_RESIDUAL, 8.0 * (10 * nn(L0.g) + 2 * ne(L0.g))); launch_residual(st, L0.g, L0.c64, c->patch, L0.coef64, c->strial, c->tmp5); }
+        rt = scaled_norm(c, c->tmp5);
+      }
       if (!std::isfinite(rt)) return NC_ENAN;
       if (rt <= rn || rt <= floor || tiny || lam < 1.0 / 64) break;
       lam *= 0.5;
@@ -755,12 +774,16 @@ int adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info*
     if (its < 0) return NC_ENAN;
     kits += its;
     launch_axpy(st, 1.0, c->d, lam, lam, c->n5);
+    // per-field norms of lambda and of the new residual r = rhs - J^T lambda, one fetch
+    launch_field_norms(st, lam, nullptr, c->N, c->part, c->dres);
+    launch_jtw5<double>(st, view<double>(c, 0), lam, c->tmp5);
+    launch_axpy(st, -1.0, c->tmp5, c->ra, c->R, c->n5);
+    launch_field_norms(st, c->R, nullptr, c->N, c->part, c->dres + 16);
+    fetch(c, c->dres, 21);
     // weight the (P, T) rows of later sweeps by 1 / |lambda_f|, relative to T, so that the
     // Krylov residual measures each field's relative error (the adjoint of the pressure
     // rows is small and otherwise under-resolved)
     {
-      launch_field_norms(st, lam, nullptr, c->N, c->part, c->dres);
-      fetch(c, c->dres, 5);
       const double lp = c->hbuf[3], lt = c->hbuf[4];
       if (lp > 0 && lt > 0) {
         const double wgt = std::min(1e4, std::max(1e-4, lt / lp));
@@ -769,9 +792,7 @@ int adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info*
         if (debug_on()) std::fprintf(stderr, "nc adjoint sweep %d: P-row weight %.3e\n", ref, wgt);
       }
     }
-    launch_jtw5<double>(st, view<double>(c, 0), lam, c->tmp5);
-    launch_axpy(st, -1.0, c->tmp5, c->ra, c->R, c->n5);
-    rel = scaled_norm(c, c->R) / bn;
+    rel = scaled_from(c, c->hbuf + 16) / bn;
     if (!std::isfinite(rel)) return NC_ENAN;
     // converged when the (row-scaled) residual is small and one preconditioner application
     // predicts a per-field relative error below the same tolerance; when refinement stops
@@ -942,6 +963,7 @@ int nc_set_design(nc_ctx* c, const double* x) {
     ck(hipGetLastError());
     c->design_set = true;
     c->hier_valid = false;
+    c->rows_valid = false;
     return NC_OK;
   });
 }
