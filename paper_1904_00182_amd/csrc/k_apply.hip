@@ -95,6 +95,62 @@ __global__ __launch_bounds__(TX* TY) void zmarch_kernel(const Op op, const int K
   }
 }
 
+// The z-march with one node plane per workgroup (KZ = 1) computes two element layers one
+// after the other: the layer below the plane (recomputed, as the halo) and its own.  On
+// the small coarse grids that take KZ = 1 that serial pair sets the launch time, so there
+// a workgroup of TX x TY x 2 threads computes both layers at once (threadIdx.z = 0: layer
+// K - 1, 1: layer K) and the owner of node (i, j, K) adds the eight contributions in the
+// z-march's order -- the four from the layer below, then the four from its own layer --
+// so the results are the same bit for bit.  Used on grids of at most 16384 elements.
+template <class Op, int TX, int TY>
+__global__ __launch_bounds__(TX* TY * 2) void zpair_kernel(const Op op) {
+  using T = typename Op::real;
+  constexpr int NI = Op::NIN, NO = Op::NOUT, NT = TX * TY;
+  __shared__ T xch[2][4 * NO * NT];   // [layer][corner][field][thread]: the corners on plane K
+  const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z, tid = tx + TX * ty;
+  const int nx = op.g.nx, ny = op.g.ny, nz = op.g.nz;
+  const unsigned nbx = gridDim.x, nby = gridDim.y, total = nbx * nby * gridDim.z;
+  const unsigned wid = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+  const unsigned per = total / NXCD, rem = total % NXCD, xcd = wid % NXCD, kk = wid / NXCD;
+  const unsigned tile = xcd < rem ? xcd * (per + 1) + kk : rem * (per + 1) + (xcd - rem) * per + kk;
+  const int bx = (int)(tile % nbx), by = (int)((tile / nbx) % nby), K = (int)(tile / (nbx * nby));
+  const int i = bx * (TX - 1) - 1 + tx;
+  const int j = by * (TY - 1) - 1 + ty;
+  const int kl = K - 1 + tz;
+  T out[8][NO];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int f = 0; f < NO; ++f) out[a][f] = (T)0;
+  if (i >= 0 && i < nx && j >= 0 && j < ny && kl >= 0 && kl < nz) {
+    T nd[8][NI];
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      op.load(i + (cc & 1), j + (cc >> 1), kl, nd[cc]);
+      op.load(i + (cc & 1), j + (cc >> 1), kl + 1, nd[4 + cc]);
+    }
+    op.element(i, j, kl, nd, out);
+  }
+  // layer K - 1 gives its top corners to plane K, layer K its bottom corners
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+    for (int f = 0; f < NO; ++f) xch[tz][(cc * NO + f) * NT + tid] = out[cc + 4 * (1 - tz)][f];
+  __syncthreads();
+  if (tz == 1 && tx >= 1 && ty >= 1 && i <= nx && j <= ny) {
+    const int tl = tid - 1, td = tid - TX, tld = tid - TX - 1;
+    T v[NO];
+#pragma unroll
+    for (int f = 0; f < NO; ++f) {
+      const T acc = xch[0][(0 * NO + f) * NT + tid] + xch[0][(1 * NO + f) * NT + tl] +
+                    xch[0][(2 * NO + f) * NT + td] + xch[0][(3 * NO + f) * NT + tld];
+      v[f] = acc + xch[1][(0 * NO + f) * NT + tid] + xch[1][(1 * NO + f) * NT + tl] +
+             xch[1][(2 * NO + f) * NT + td] + xch[1][(3 * NO + f) * NT + tld];
+    }
+    op.finish(i, j, K, v);
+  }
+}
+
 // Tile shapes (threads in x, y); a tile owns (TX-1) x (TY-1) node columns.
 struct TileCfg {
   int tx, ty;
@@ -140,6 +196,15 @@ static void run_zmarch_t(hipStream_t st, const Op& op) {
   const int want = std::max(1, target * 256 / (TX * TY) / std::max(1, tiles_x * tiles_y));
   const int KZ = std::max(kzmin, ceil_div(g.nz + 1, want));
   const int chunks = ceil_div(g.nz + 1, KZ);
+  if constexpr (!FINE) {
+    // paired layers win where the launch is latency bound (32x16x32 6.8 -> 6.1 us,
+    // 16x8x16 6.4 -> 5.5 us) and lose where it has work to fill the chip (64x32x64
+    // 11.5 -> 14.0 us)
+    if (KZ == 1 && g.elems() <= 16384) {
+      launch((zpair_kernel<Op, TX, TY>), dim3(tiles_x, tiles_y, g.nz + 1), dim3(TX, TY, 2), 0, st, op);
+      return;
+    }
+  }
   dim3 grid(tiles_x, tiles_y, chunks), block(TX, TY, 1);
   launch((zmarch_kernel<Op, TX, TY, FINE>), grid, block, 0, st, op, KZ);
 }

@@ -790,7 +790,8 @@ void launch_mdot(hipStream_t st, const T* V, long ld, int cnt, const T* w, long 
 // out[c] = sum over blocks of part[b][c] in a fixed order; sqrt if do_sqrt.  One block of
 // 1024 threads: (column, 32 lanes), each lane with 8 independent loads in flight.
 __global__ __launch_bounds__(1024) void reduce_parts_kernel(const double* __restrict__ part, int nblk, int cnt,
-                                                            double* __restrict__ out, int do_sqrt) {
+                                                            double* __restrict__ out, int do_sqrt,
+                                                            double* __restrict__ hout) {
   const int c = threadIdx.x >> 5, sub = threadIdx.x & 31;
   double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (c < cnt) {
@@ -803,7 +804,11 @@ __global__ __launch_bounds__(1024) void reduce_parts_kernel(const double* __rest
   }
   double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   for (int off = 16; off > 0; off >>= 1) s += __shfl_down(s, off, 32);
-  if (sub == 0 && c < cnt) out[c] = do_sqrt ? sqrt(s) : s;
+  if (sub == 0 && c < cnt) {
+    const double v = do_sqrt ? sqrt(s) : s;
+    out[c] = v;
+    if (hout) hout[c] = v;
+  }
 }
 
 // One group of the multi-axpy's basis vectors (rows past cnt re-read row c0 with weight 0)
@@ -949,9 +954,9 @@ __global__ __launch_bounds__(BS) void norm_kernel(const T* __restrict__ a, long 
   }
 }
 template <typename T>
-void launch_norm(hipStream_t st, const T* a, long n, double* part, double* out) {
+void launch_norm(hipStream_t st, const T* a, long n, double* part, double* out, double* hout) {
   launch(norm_kernel<T>, dim3(RED_BLOCKS), dim3(BS), 0, st, a, n, part);
-  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 1);
+  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 1, hout);
 }
 
 __global__ __launch_bounds__(BS) void field_norms_kernel(const double* __restrict__ a, const double* __restrict__ b,
@@ -986,7 +991,7 @@ __global__ __launch_bounds__(BS) void field_norms_kernel(const double* __restric
 }
 void launch_field_norms(hipStream_t st, const double* a, const double* b, long nodes, double* part, double* out) {
   launch(field_norms_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, a, b, nodes, part);
-  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 10, out, 1);
+  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 10, out, 1, (double*)nullptr);
 }
 
 // ------------------------------------------------------------------ design chain
@@ -1111,7 +1116,7 @@ __global__ __launch_bounds__(BS) void coef_sum_kernel(const double* __restrict__
 }
 void launch_coef_sums(hipStream_t st, const double* coef, long E, double* part, double* out) {
   launch(coef_sum_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, coef, E, part);
-  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 2, out, 0);
+  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 2, out, 0, (double*)nullptr);
 }
 
 // ------------------------------------------------------------------ objective
@@ -1137,7 +1142,7 @@ __global__ __launch_bounds__(BS) void objective_kernel(Grid g, Patch pa, const d
 }
 void launch_objective(hipStream_t st, const Grid& g, const Patch& patch, const double* s5, double* part, double* out) {
   launch(objective_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, g, patch, s5, part);
-  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 0);
+  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 0, (double*)nullptr);
 }
 
 __global__ void objective_grad_kernel(Grid g, Patch pa, double* __restrict__ g5) {
@@ -1174,7 +1179,7 @@ void launch_objective_grad(hipStream_t st, const Grid& g, const Patch& patch, do
   template void launch_mdot<T>(hipStream_t, const T*, long, int, const T*, long, double*, double*, bool, double*); \
   template void launch_maxpy<T>(hipStream_t, const T*, long, int, const double*, double, T*, long, double*, double*, double*); \
   template void launch_scale_inv<T>(hipStream_t, const double*, const T*, T*, long);                \
-  template void launch_norm<T>(hipStream_t, const T*, long, double*, double*);                     \
+  template void launch_norm<T>(hipStream_t, const T*, long, double*, double*, double*);            \
   template void launch_diag_scale<T>(hipStream_t, const Grid&, const T*, bool, T, const T*, T*);    \
   template void launch_rsub<T>(hipStream_t, const T*, T*, long);
 NC_INST(double)

@@ -119,7 +119,7 @@ void launch_scale_inv(hipStream_t st, const double* nrm, const T* w, T* v, long 
 // per-field 2-norms of [N][5] arrays: out[f] = ||a_f||, and if b != null out[5+f] = ||b_f||
 void launch_field_norms(hipStream_t st, const double* a, const double* b, long nodes, double* part, double* out);
 template <typename T>
-void launch_norm(hipStream_t st, const T* a, long n, double* part, double* out);
+void launch_norm(hipStream_t st, const T* a, long n, double* part, double* out, double* hout = nullptr);
 
 // ---- design chain and sensitivities
 void launch_cone_filter(hipStream_t st, const Grid& g, double radius, const double* x, double* y, bool transpose,

@@ -88,7 +88,7 @@ struct nc_ctx {
   // reductions
   double *part, *dres;
   double* hbuf;          // pinned host mirror of dres
-  double* hslots;        // pinned: one Hessenberg column (h1, h2, norm) per Krylov iteration
+  double* hslots;        // pinned: one Hessenberg column (h1, h2, norm) per Krylov iteration, then |b|
   std::vector<hipEvent_t> kev;   // completion of each Krylov iteration's column copy
   // float64 Newton / adjoint vectors
   double *R, *d, *strial, *ra, *tmp5;
@@ -447,13 +447,14 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
   T* Z = (T*)c->Z;
   double* dres = c->dres;
   ck(hipMemsetAsync(x, 0, sizeof(T) * n, st));
-  launch_norm<T>(st, b, n, c->part, dres);
-  fetch(c, dres, 1);
-  const double bnorm = c->hbuf[0];
+  // |b| also goes to the pinned slot after the Hessenberg slots; the host reads it with
+  // step 0's column rather than waiting for it here
+  const double* hb = c->hslots + (size_t)MAXC * HSLOT;
+  launch_norm<T>(st, b, n, c->part, dres, c->hslots + (size_t)MAXC * HSLOT);
   *relres = 0.0;
-  if (!(bnorm > 0.0)) return bnorm == 0.0 ? 0 : -1;
   launch_scale_inv<T>(st, dres, b, V, n);
-  double beta = bnorm;
+  double bnorm = -1.0, beta = -1.0;
+  bool no_rhs = false;
   int total = 0;
   std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   const int passes = c->p.gs_passes;   // classical Gram-Schmidt passes per step (1 or 2)
@@ -492,6 +493,16 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
     // process the column of step j; returns true when the cycle stops after it
     auto process = [&](int j) -> bool {
       ck(hipEventSynchronize(c->kev[j]));
+      if (bnorm < 0.0) {   // the solve's first step: |b| arrived with it
+        bnorm = hb[0];
+        beta = bnorm;
+        g[0] = beta;
+        if (!(bnorm > 0.0)) {   // zero (x stays 0) or non-finite right-hand side
+          no_rhs = true;
+          done = true;
+          return true;
+        }
+      }
       const double* hs = c->hslots + (size_t)j * HSLOT;
       for (int i = 0; i <= j; ++i) H[i * m + j] = passes == 2 ? hs[i] + hs[MAXC + i] : hs[i];
       const double hn = hs[2 * MAXC];
@@ -533,6 +544,7 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
       if (stop || !more) break;
       if (!spec) enqueue(j + 1);
     }
+    if (no_rhs) return bnorm == 0.0 ? 0 : -1;
     if (bad) {
       sync(c);
       return -1;
@@ -908,7 +920,7 @@ int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stre
     c->ev_used = 0;
     c->kev.resize(MAXC);
     for (auto& e : c->kev) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    if (hipHostMalloc((void**)&c->hslots, sizeof(double) * MAXC * HSLOT, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->hslots, sizeof(double) * (MAXC + 1) * HSLOT, hipHostMallocDefault) != hipSuccess) {
       for (auto& e : c->kev) (void)hipEventDestroy(e);
       delete c;
       return NC_EHIP;
