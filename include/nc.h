@@ -86,6 +86,9 @@ typedef struct nc_problem {
   int    coarse_tail;         /* 1: the last smoothed level and the dense coarsest level of
                                  each V-cycle run in one workgroup when they fit; 0: one
                                  launch per step everywhere (same operators and order)   */
+  double newton_eta0;         /* linear tolerance of the first Newton step; later steps use
+                                 0.9 (|R_k| / |R_k-1|)^2 between the Krylov tolerance and
+                                 this (Eisenstat-Walker); 0: the Krylov tolerance always   */
 } nc_problem;
 
 typedef struct nc_info {

@@ -172,6 +172,7 @@ bool valid_problem(const nc_problem* p) {
   if (!(p->krylov_rtol > 0) || !(p->krylov_rtol_mixed > 0) || !(p->adjoint_rtol > 0)) return false;
   if (p->gs_passes != 1 && p->gs_passes != 2) return false;
   if (p->coarse_tail != 0 && p->coarse_tail != 1) return false;
+  if (!(p->newton_eta0 >= 0.0 && p->newton_eta0 < 1.0)) return false;
   if (p->smooth_pre < 1 || p->smooth_post < 0 || p->smooth_pre_coarse < 1 || p->smooth_post_coarse < 0) return false;
   return true;
 }
@@ -685,13 +686,25 @@ int newton(nc_ctx* c, double* s, nc_info* info) {
   int kits = 0, it = 0;
   double relres = 0.0;
   int first_its = 0;
+  double rn_last = rn;   // merit before the previous step
   for (it = 0; it < p.newton_maxit; ++it) {
     if (rn <= floor) { status = NC_OK; break; }   // already at the residual's round-off floor
+    // inexact-Newton forcing term (Eisenstat and Walker's second choice): the first step
+    // is solved only to newton_eta0, later ones to 0.9 (|R_k| / |R_k-1|)^2, never looser
+    // than newton_eta0 nor tighter than the Krylov tolerance.  Far from the root the
+    // linear solve need not beat the contraction the nonlinearity allows; near it the
+    // ratio is small and the Krylov tolerance governs, so the final accuracy is unchanged.
+    double eta = lin_rtol;
+    if (p.newton_eta0 > lin_rtol) {
+      const double q = rn / rn_last;
+      eta = it == 0 ? p.newton_eta0 : std::min(p.newton_eta0, std::max(lin_rtol, 0.9 * q * q));
+    }
+    rn_last = rn;
     // rebuild the preconditioner on the first two steps (the first step moves the state
     // from the guess to near the root) or when the last solve needed many more iterations
     const bool rebuild = it < 2 || !c->hier_valid;
     linearize(c, s, rebuild);
-    const int its = linear_solve(c, false, c->R, c->d, lin_rtol, &relres);
+    const int its = linear_solve(c, false, c->R, c->d, eta, &relres);
     if (its < 0) return NC_ENAN;
     if (it == 1) first_its = its;
     if (it >= 2 && its > 2 * first_its + 4) c->hier_valid = false;
@@ -880,6 +893,7 @@ void nc_problem_default(nc_problem* p, int nx, int ny, int nz) {
   p->coarse_tail = 1;
   p->adjoint_rtol = 3e-11;
   p->newton_maxit = 30;
+  p->newton_eta0 = 3e-3;
   p->krylov_restart = 24;
   p->krylov_maxit = 400;
   p->smooth_pre = 2;

@@ -49,7 +49,7 @@ class NCProblem(ctypes.Structure):
         ("smooth_omega", ctypes.c_double),
         ("smooth_pre_coarse", ctypes.c_int), ("smooth_post_coarse", ctypes.c_int),
         ("krylov_rtol_mixed", ctypes.c_double), ("gs_passes", ctypes.c_int),
-        ("coarse_tail", ctypes.c_int),
+        ("coarse_tail", ctypes.c_int), ("newton_eta0", ctypes.c_double),
     ]
 
 

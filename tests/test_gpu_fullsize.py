@@ -12,6 +12,9 @@ from gpu_helpers import oracle_params, local_rows, sample_nodes, to_dev, DEV
 
 pytestmark = pytest.mark.gpu
 
+# stated accuracy of mixed-precision results against the float64 solve, per field
+MIXED_BOUND = 1e-8
+
 FULL = [("cavity64", 1e-11), ("cavity96filtered", 1e-11), ("cavity128mixed", 1e-11)]
 
 
@@ -80,9 +83,11 @@ def _energy_balance(p, gam, s):
 def test_full_size_solution_properties(name):
     """At full size: the heat leaving through the isothermal walls equals the heat entering
     through the patch (discrete energy balance of the weak form), the solve converged,
-    and the temperature residual is within the Newton stop: Newton ends once the error
-    predicted to remain is below newton_step_rtol (relative, per field), so the residual
-    per node is bounded by that fraction of the patch heat flux per node."""
+    and the temperature residual per node is below the solution's accuracy times the
+    patch heat flux per node: newton_step_rtol in float64, and in mixed precision the
+    stated mixed-mode accuracy 1e-8 (checked against the float64 solve field by field in
+    test_mixed_precision_error_vs_fp64_at_1m_elements).  Newton stops on the error
+    predicted to remain, which does not bound the residual of each node by itself."""
     p, x, cfg = workloads.config(name, DEV)
     sol = nc.Solver(p, DEV)
     sol.set_design(x)
@@ -93,7 +98,8 @@ def test_full_size_solution_properties(name):
     total, heat_in = _energy_balance(p, sol.gamma().cpu().numpy(), sn)
     assert abs(total + heat_in) < 1e-9 * heat_in, (total, heat_in)
     flux = np.abs(oracle.patch_flux(oracle.Mesh(oracle_params(p)), oracle_params(p))).max()
-    assert np.abs(r[:, 4]).max() < p.newton_step_rtol * flux, (np.abs(r[:, 4]).max(), flux)
+    acc = p.newton_step_rtol if p.precision == nc.NC_FP64 else MIXED_BOUND
+    assert np.abs(r[:, 4]).max() < acc * flux, (np.abs(r[:, 4]).max(), flux)
     assert np.all(np.isfinite(sn))
 
 
@@ -119,4 +125,4 @@ def test_mixed_precision_error_vs_fp64_at_1m_elements():
             if nb > 0:
                 err = np.linalg.norm(a2[:, f] - b2[:, f]) / nb
                 print("mixed vs fp64 field", f, err)
-                assert err < 1e-8
+                assert err < MIXED_BOUND
