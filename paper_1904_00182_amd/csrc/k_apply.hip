@@ -734,9 +734,10 @@ struct DiagOp {
 };
 
 template <typename T>
-void launch_diag_inverse(hipStream_t st, const LevelView<T>& L, T* dinv) {
+void launch_diag_inverse(hipStream_t st, const LevelView<T>& L, T* dinv, bool fine) {
   DiagOp<T> op{L.g, L.c, L.coef, L.st, dinv};
-  run_zmarch(st, op);
+  if (fine) run_zmarch<DiagOp<T>, 1>(st, op);
+  else run_zmarch<DiagOp<T>, 0>(st, op);
 }
 
 // ------------------------------------------------------------------ velocity coupling
@@ -835,7 +836,7 @@ void launch_uprojT(hipStream_t st, const LevelView<T>& L, const T* r5, T* b_pt, 
   template void launch_tail_cycle<T>(hipStream_t, const Grid&, const T*, T*, const LevelView<T>&, const Grid&,     \
                                      const double*, bool, T, int, int);                                \
   template void launch_pt_store<T>(hipStream_t, const LevelView<T>&, bool, const T*, T*, const Scale5<T>*);       \
-  template void launch_diag_inverse<T>(hipStream_t, const LevelView<T>&, T*);                       \
+  template void launch_diag_inverse<T>(hipStream_t, const LevelView<T>&, T*, bool);                 \
   template void launch_uproj<T>(hipStream_t, const LevelView<T>&, const T*, const T*, T*, const Scale5<T>*); \
   template void launch_uprojT<T>(hipStream_t, const LevelView<T>&, const T*, T*, T*, const Scale5<T>*);
 NC_INST(double)

@@ -39,7 +39,7 @@ void launch_tail_cycle(hipStream_t st, const Grid& gu, const T* ru, T* xu, const
                        const double* ainv, bool transpose, T omega, int npre, int npost);
 // Inverse 2x2 (P, T) node blocks of the level Jacobian into dinv [N][4].
 template <typename T>
-void launch_diag_inverse(hipStream_t st, const LevelView<T>& L, T* dinv);
+void launch_diag_inverse(hipStream_t st, const LevelView<T>& L, T* dinv, bool fine);
 // Preconditioner pieces coupling the velocity rows (block-triangular structure):
 //   forward: z = [ (r_u - C x)/M ; x ] with x the (P, T) correction (constrained dofs: z = r)
 // (r5 is divided by the row scales `rows` on input when given)

@@ -283,7 +283,7 @@ void linearize_levels(nc_ctx* c) {
   }
   for (int l = 0; l < c->L; ++l) {
     Timed tm(c, TC_SETUP);
-    launch_diag_inverse<T>(st, view<T>(c, l), (T*)c->lev[l].dinv);
+    launch_diag_inverse<T>(st, view<T>(c, l), (T*)c->lev[l].dinv, l == 0);
   }
   if (c->dense) {
     { Timed tm(c, TC_SETUP); launch_coarse_assemble<T>(st, view<T>(c, c->L - 1), c->emats, c->A); }
