@@ -11,6 +11,47 @@
 
 namespace nc {
 
+// One z-layer of an array as a buffer resource: entries are addressed by a 32-bit byte
+// offset within the layer (one layer of a five-field float64 array stays below 4 GiB,
+// checked at context creation), and the layer base is a scalar operand, so a thread's
+// offsets are computed once and reused from layer to layer.  Reads past the layer's end
+// return zero instead of touching other memory.
+template <typename T>
+struct LayerRef {
+  __amdgpu_buffer_rsrc_t r;
+  // 0x00020000: the third descriptor word of the gfx9-family raw buffer (32-bit data format)
+  __device__ LayerRef(const T* base, unsigned entries)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), 0, (int)(entries * (unsigned)sizeof(T)), 0x00020000)) {}
+  // base[idx .. idx + sizeof(V) / sizeof(T)) as one V
+  template <typename V = T>
+  __device__ V ld(unsigned idx) const {
+    const int off = (int)(idx * (unsigned)sizeof(T));
+    if constexpr (sizeof(V) == 4) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    else if constexpr (sizeof(V) == 8) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else if constexpr (sizeof(V) == 16) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    else {
+      static_assert(sizeof(V) == 32, "4, 8, 16 or 32 bytes");
+      using U4 = unsigned __attribute__((ext_vector_type(4)));
+      struct {
+        U4 lo, hi;
+      } w{__builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0), __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0)};
+      return __builtin_bit_cast(V, w);
+    }
+  }
+  template <typename V = T>
+  __device__ void st(unsigned idx, const V& v) const {
+    const int off = (int)(idx * (unsigned)sizeof(T));
+    using U2 = unsigned __attribute__((ext_vector_type(2)));
+    using U4 = unsigned __attribute__((ext_vector_type(4)));
+    if constexpr (sizeof(V) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+    else if constexpr (sizeof(V) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, off, 0, 0);
+    else {
+      static_assert(sizeof(V) == 16, "4, 8 or 16 bytes");
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), r, off, 0, 0);
+    }
+  }
+};
+
 // Structured grid of one multigrid level: nx*ny*nz cubes, nodes (nx+1)(ny+1)(nz+1).
 struct Grid {
   int nx, ny, nz;
@@ -19,6 +60,22 @@ struct Grid {
   // 32-bit indices: grids are limited to fewer than 2^31 / 5 nodes (checked at context creation)
   __host__ __device__ int node(int i, int j, int k) const { return i + (nx + 1) * (j + (ny + 1) * k); }
   __host__ __device__ int elem(int i, int j, int k) const { return i + nx * (j + ny * k); }
+  // The same indices split into a z-layer and a position within it: node (i, j, k) of an
+  // [N][nf] array is entry nf * col(i, j) of layer(a, nf, k), element (i, j, k) of an [E][nf]
+  // array entry nf * ecol(i, j) of elayer(a, nf, k).  k must be the same for the whole
+  // wavefront (the z-march's layer is), which keeps the layer resource in scalar registers.
+  __host__ __device__ unsigned col(int i, int j) const { return (unsigned)(i + (nx + 1) * j); }
+  __host__ __device__ unsigned ecol(int i, int j) const { return (unsigned)(i + nx * j); }
+  template <typename P>
+  __device__ LayerRef<P> layer(const P* a, int nf, int k) const {
+    const unsigned len = (unsigned)nf * (unsigned)(nx + 1) * (unsigned)(ny + 1);
+    return LayerRef<P>(a + (size_t)len * k, len);
+  }
+  template <typename P>
+  __device__ LayerRef<P> elayer(const P* a, int nf, int k) const {
+    const unsigned len = (unsigned)nf * (unsigned)nx * (unsigned)ny;
+    return LayerRef<P>(a + (size_t)len * k, len);
+  }
   // Dirichlet sets of the cavity: T on the vertical walls and the top, P at (0, 0, nz).
   __host__ __device__ bool tfix(int i, int j, int k) const { return i == 0 || i == nx || j == 0 || j == ny || k == nz; }
   __host__ __device__ bool pfix(int i, int j, int k) const { return i == 0 && j == 0 && k == nz; }

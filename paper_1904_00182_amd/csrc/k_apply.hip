@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <stdexcept>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "transfer.hpp"
@@ -23,10 +24,22 @@ namespace nc {
 
 constexpr unsigned NXCD = 8;   // accelerator complex dies of the MI355X
 
+// Occupancy floor of an operator's z-march (waves per SIMD the register allocation must
+// leave room for): Op::MIN_WAVES where the operator sets it, else 1.
+template <class Op, class = void>
+struct MinWaves {
+  static constexpr int value = 1;
+};
+template <class Op>
+struct MinWaves<Op, std::void_t<decltype(Op::MIN_WAVES)>> {
+  static constexpr int value = Op::MIN_WAVES;
+};
+
 // FINE: 1 for launches on the finest grid, 0 on coarser multigrid levels (the same code;
 // separate instantiations keep the two apart in kernel traces).
 template <class Op, int TX, int TY, int FINE>
-__global__ __launch_bounds__(TX* TY) void zmarch_kernel(const Op op, const int KZ) {
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MinWaves<Op>::value)))
+void zmarch_kernel(const Op op, const int KZ) {
   using T = typename Op::real;
   constexpr int NI = Op::NIN, NO = Op::NOUT, NT = TX * TY;
   __shared__ T xch[6 * NO * NT];
@@ -106,8 +119,11 @@ template <class Op, int TX, int TY>
 __global__ __launch_bounds__(TX* TY * 2) void zpair_kernel(const Op op) {
   using T = typename Op::real;
   constexpr int NI = Op::NIN, NO = Op::NOUT, NT = TX * TY;
+  static_assert(NT % 64 == 0, "each wavefront on one layer");
   __shared__ T xch[2][4 * NO * NT];   // [layer][corner][field][thread]: the corners on plane K
-  const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z, tid = tx + TX * ty;
+  // threadIdx.z is the same across a wavefront (TX * TY is a multiple of 64): reading it as
+  // a scalar keeps the layer addressing of the operator in scalar registers
+  const int tx = threadIdx.x, ty = threadIdx.y, tz = __builtin_amdgcn_readfirstlane(threadIdx.z), tid = tx + TX * ty;
   const int nx = op.g.nx, ny = op.g.ny, nz = op.g.nz;
   const unsigned nbx = gridDim.x, nby = gridDim.y, total = nbx * nby * gridDim.z;
   const unsigned wid = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
@@ -275,6 +291,8 @@ void launch_residual(hipStream_t st, const Grid& g, const ElemConst<double>& c, 
 template <typename T, int NF, int MODE>
 struct JvOp {
   using real = T;
+  static constexpr int MIN_WAVES = 2;   // two waves per SIMD also for the float64 five-field applies
+  static_assert(NF == 2 || MODE == MODE_STORE, "five-field applies store only");
   static constexpr int NIN = 4, NOUT = NF;
   Grid g;
   ElemConst<T> c;
@@ -287,12 +305,23 @@ struct JvOp {
   T omega;
   Scale5<T> rs;   // output row scales (five-field mode)
   __device__ void load(int i, int j, int k, T in[NIN]) const {
-    const long n = g.node(i, j, k);
-    in[0] = st[2 * n];
-    in[1] = st[2 * n + 1];
-    T p = x[NF * n + NF - 2], t = x[NF * n + NF - 1];
+    using P2 = typename Pair<T>::type;
+    const unsigned n = g.col(i, j);
+    const P2 s = g.layer(st, 2, k).template ld<P2>(2 * n);
+    const auto xk = g.layer(x, NF, k);
+    T p, t;
+    if constexpr (NF == 2) {
+      const P2 v = xk.template ld<P2>(2 * n);
+      p = v.x;
+      t = v.y;
+    } else {
+      p = xk.template ld<T>(NF * n + NF - 2);
+      t = xk.template ld<T>(NF * n + NF - 1);
+    }
     if (g.pfix(i, j, k)) p = (T)0;
     if (g.tfix(i, j, k)) t = (T)0;
+    in[0] = s.x;
+    in[1] = s.y;
     in[2] = p;
     in[3] = t;
   }
@@ -300,9 +329,9 @@ struct JvOp {
     T P[8], Tn[8], p[8], t[8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) { P[a] = nd[a][0]; Tn[a] = nd[a][1]; p[a] = nd[a][2]; t[a] = nd[a][3]; }
-    const long e = g.elem(i, j, k);
+    const auto kc = g.elayer(coef, 2, k).template ld<typename Pair<T>::type>(2 * g.ecol(i, j));
     LinM<T> L;
-    lin_modal(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    lin_modal(P, Tn, kc.x, kc.y, c, L);
     T yP[8] = {0}, yT[8] = {0}, yU[3][8] = {{0}};
     elem_jv_m<T, NF == 5>(L, p, t, c, yP, yT, yU);
 #pragma unroll
@@ -313,27 +342,36 @@ struct JvOp {
     }
   }
   __device__ void finish(int i, int j, int k, const T v[NOUT]) const {
-    const long n = g.node(i, j, k);
+    using P2 = typename Pair<T>::type;
+    const unsigned n = g.col(i, j);
+    const auto xk = g.layer(x, NF, k);
+    const auto yk = g.layer(y, NF, k);
     const bool pf = g.pfix(i, j, k), tf = g.tfix(i, j, k);
-    const T ap = pf ? x[NF * n + NF - 2] : v[NF - 2];
-    const T at = tf ? x[NF * n + NF - 1] : v[NF - 1];
     if constexpr (NF == 5) {
       const T M = c.W * (T)g.valence(i, j, k);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) y[5 * n + d] = rs.s[d] * (v[d] + M * x[5 * n + d]);
-    }
-    if (MODE == MODE_STORE) {
-      y[NF * n + NF - 2] = rs.s[3] * ap;
-      y[NF * n + NF - 1] = rs.s[4] * at;
+      for (int d = 0; d < 3; ++d) yk.template st<T>(5 * n + d, rs.s[d] * (v[d] + M * xk.template ld<T>(5 * n + d)));
+      const T ap = pf ? xk.template ld<T>(5 * n + 3) : v[3];
+      const T at = tf ? xk.template ld<T>(5 * n + 4) : v[4];
+      yk.template st<T>(5 * n + 3, rs.s[3] * ap);
+      yk.template st<T>(5 * n + 4, rs.s[4] * at);
     } else {
-      const T rp = b[2 * n] - ap, rt = b[2 * n + 1] - at;
-      if (MODE == MODE_RESID) {
-        y[2 * n] = rp;
-        y[2 * n + 1] = rt;
+      // x at the node itself: needed by the sweep, otherwise only at constrained dofs
+      P2 xn{};
+      if (MODE == MODE_SMOOTH) xn = xk.template ld<P2>(2 * n);
+      const T ap = pf ? (MODE == MODE_SMOOTH ? xn.x : xk.template ld<T>(2 * n)) : v[0];
+      const T at = tf ? (MODE == MODE_SMOOTH ? xn.y : xk.template ld<T>(2 * n + 1)) : v[1];
+      if (MODE == MODE_STORE) {
+        yk.template st<P2>(2 * n, P2{rs.s[3] * ap, rs.s[4] * at});
       } else {
-        const T* D = dinv + 4 * n;
-        y[2 * n] = x[2 * n] + omega * (D[0] * rp + D[1] * rt);
-        y[2 * n + 1] = x[2 * n + 1] + omega * (D[2] * rp + D[3] * rt);
+        const P2 bn = g.layer(b, 2, k).template ld<P2>(2 * n);
+        const T rp = bn.x - ap, rt = bn.y - at;
+        if (MODE == MODE_RESID) {
+          yk.template st<P2>(2 * n, P2{rp, rt});
+        } else {
+          const auto D = g.layer(dinv, 4, k).template ld<typename Quad<T>::type>(4 * n);
+          yk.template st<P2>(2 * n, P2{xn.x + omega * (D.x * rp + D.y * rt), xn.y + omega * (D.z * rp + D.w * rt)});
+        }
       }
     }
   }
@@ -342,6 +380,8 @@ struct JvOp {
 template <typename T, int NF, int MODE>
 struct JtwOp {
   using real = T;
+  static constexpr int MIN_WAVES = 2;   // two waves per SIMD also for the float64 five-field applies
+  static_assert(NF == 2 || MODE == MODE_STORE, "five-field applies store only");
   static constexpr int NIN = NF == 5 ? 7 : 4, NOUT = 2;
   Grid g;
   ElemConst<T> c;
@@ -354,18 +394,27 @@ struct JtwOp {
   T omega;
   Scale5<T> rs;   // output row scales (five-field mode)
   __device__ void load(int i, int j, int k, T in[NIN]) const {
-    const long n = g.node(i, j, k);
-    in[0] = st[2 * n];
-    in[1] = st[2 * n + 1];
-    T p = x[NF * n + NF - 2], t = x[NF * n + NF - 1];
+    using P2 = typename Pair<T>::type;
+    const unsigned n = g.col(i, j);
+    const P2 s = g.layer(st, 2, k).template ld<P2>(2 * n);
+    const auto xk = g.layer(x, NF, k);
+    T p, t;
+    if constexpr (NF == 2) {
+      const P2 v = xk.template ld<P2>(2 * n);
+      p = v.x;
+      t = v.y;
+    } else {
+      p = xk.template ld<T>(NF * n + NF - 2);
+      t = xk.template ld<T>(NF * n + NF - 1);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) in[4 + d] = xk.template ld<T>(5 * n + d);
+    }
     if (g.pfix(i, j, k)) p = (T)0;
     if (g.tfix(i, j, k)) t = (T)0;
+    in[0] = s.x;
+    in[1] = s.y;
     in[2] = p;
     in[3] = t;
-    if constexpr (NF == 5) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) in[4 + d] = x[5 * n + d];
-    }
   }
   __device__ void element(int i, int j, int k, const T nd[8][NIN], T out[8][NOUT]) const {
     T P[8], Tn[8], wP[8], wT[8], wU[3][8];
@@ -374,36 +423,45 @@ struct JtwOp {
       P[a] = nd[a][0]; Tn[a] = nd[a][1]; wP[a] = nd[a][2]; wT[a] = nd[a][3];
       if constexpr (NF == 5) { wU[0][a] = nd[a][4]; wU[1][a] = nd[a][5]; wU[2][a] = nd[a][6]; }
     }
-    const long e = g.elem(i, j, k);
+    const auto kc = g.elayer(coef, 2, k).template ld<typename Pair<T>::type>(2 * g.ecol(i, j));
     LinM<T> L;
-    lin_modal(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    lin_modal(P, Tn, kc.x, kc.y, c, L);
     T yP[8] = {0}, yT[8] = {0};
     elem_jtw_m<T, NF == 5>(L, wP, wT, wU, c, yP, yT);
 #pragma unroll
     for (int a = 0; a < 8; ++a) { out[a][0] = yP[a]; out[a][1] = yT[a]; }
   }
   __device__ void finish(int i, int j, int k, const T v[NOUT]) const {
-    const long n = g.node(i, j, k);
+    using P2 = typename Pair<T>::type;
+    const unsigned n = g.col(i, j);
+    const auto xk = g.layer(x, NF, k);
+    const auto yk = g.layer(y, NF, k);
     const bool pf = g.pfix(i, j, k), tf = g.tfix(i, j, k);
-    const T ap = pf ? x[NF * n + NF - 2] : v[0];
-    const T at = tf ? x[NF * n + NF - 1] : v[1];
     if constexpr (NF == 5) {
       const T M = c.W * (T)g.valence(i, j, k);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) y[5 * n + d] = rs.s[d] * M * x[5 * n + d];
-    }
-    if (MODE == MODE_STORE) {
-      y[NF * n + NF - 2] = rs.s[3] * ap;
-      y[NF * n + NF - 1] = rs.s[4] * at;
+      for (int d = 0; d < 3; ++d) yk.template st<T>(5 * n + d, rs.s[d] * M * xk.template ld<T>(5 * n + d));
+      const T ap = pf ? xk.template ld<T>(5 * n + 3) : v[0];
+      const T at = tf ? xk.template ld<T>(5 * n + 4) : v[1];
+      yk.template st<T>(5 * n + 3, rs.s[3] * ap);
+      yk.template st<T>(5 * n + 4, rs.s[4] * at);
     } else {
-      const T rp = b[2 * n] - ap, rt = b[2 * n + 1] - at;
-      if (MODE == MODE_RESID) {
-        y[2 * n] = rp;
-        y[2 * n + 1] = rt;
+      // x at the node itself: needed by the sweep, otherwise only at constrained dofs
+      P2 xn{};
+      if (MODE == MODE_SMOOTH) xn = xk.template ld<P2>(2 * n);
+      const T ap = pf ? (MODE == MODE_SMOOTH ? xn.x : xk.template ld<T>(2 * n)) : v[0];
+      const T at = tf ? (MODE == MODE_SMOOTH ? xn.y : xk.template ld<T>(2 * n + 1)) : v[1];
+      if (MODE == MODE_STORE) {
+        yk.template st<P2>(2 * n, P2{rs.s[3] * ap, rs.s[4] * at});
       } else {
-        const T* D = dinv + 4 * n;     // (D^-1)^T
-        y[2 * n] = x[2 * n] + omega * (D[0] * rp + D[2] * rt);
-        y[2 * n + 1] = x[2 * n + 1] + omega * (D[1] * rp + D[3] * rt);
+        const P2 bn = g.layer(b, 2, k).template ld<P2>(2 * n);
+        const T rp = bn.x - ap, rt = bn.y - at;
+        if (MODE == MODE_RESID) {
+          yk.template st<P2>(2 * n, P2{rp, rt});
+        } else {
+          const auto D = g.layer(dinv, 4, k).template ld<typename Quad<T>::type>(4 * n);   // (D^-1)^T
+          yk.template st<P2>(2 * n, P2{xn.x + omega * (D.x * rp + D.z * rt), xn.y + omega * (D.y * rp + D.w * rt)});
+        }
       }
     }
   }

@@ -166,6 +166,7 @@ double ne(const Grid& g) { return (double)g.nx * g.ny * g.nz; }
 bool valid_problem(const nc_problem* p) {
   if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
   if ((double)(p->nx + 1) * (p->ny + 1) * (p->nz + 1) * 5 >= 2147483647.0) return false;   // 32-bit indices
+  if ((double)(p->nx + 1) * (p->ny + 1) * 5 * 8 >= 4294967296.0) return false;   // 32-bit offsets in a layer
   if (p->mu <= 0 || p->kappa_s <= 0 || p->kappa_f <= 0 || p->k_f <= 0 || p->k_s <= 0) return false;
   if (p->precision != NC_FP64 && p->precision != NC_MIXED) return false;
   if (p->krylov_restart < 1 || p->krylov_restart > MAXC - 2) return false;
