@@ -59,7 +59,8 @@ extern "C" {
 #define NC_DENSE_MAX 2000   /* largest coarsest-grid system solved by a dense inverse */
 
 typedef struct nc_problem {
-  int    nx, ny, nz;          /* elements per axis                                       */
+  int    nx, ny, nz;          /* elements per axis; at most 2^31 / 5 nodes in all and    *
+                               * (nx+1)(ny+1) < 2^32 / 40 nodes in one z-layer           */
   double h;                   /* element edge; <= 0 means 1/nx                           */
   double rho0, mu, cp, g0;    /* reference density, viscosity, heat capacity, gravity    */
   double alpha;               /* thermal expansion coefficient (= Gr with unit constants)*/

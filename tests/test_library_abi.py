@@ -49,6 +49,10 @@ def test_host_only_entry_points():
     for field, value in (("newton_eta0", 1.0), ("newton_eta0", -1e-3), ("coarse_tail", 2), ("gs_passes", 3)):
         assert nc.workspace_bytes(nc.default_problem(16, 8, 16, **{field: value})) == 0, field
     assert p.newton_eta0 == 3e-3 and p.coarse_tail == 1 and p.gs_passes == 1
+    # size limits: fewer than 2^31 / 5 nodes, and a z-layer of a five-field float64 array
+    # below 4 GiB (the operator kernels address a layer with 32-bit byte offsets)
+    assert nc.workspace_bytes(nc.default_problem(2048, 2048, 128)) == 0
+    assert nc.workspace_bytes(nc.default_problem(12000, 12000, 1)) == 0
     assert lib.nc_status_string(-2) == b"workspace too small"
     assert lib.nc_create(ctypes.byref(p), None, 0, None, ctypes.byref(ctypes.c_void_p())) == nc.NC_EINVAL
     for n in (0, -1, nc.NC_DENSE_MAX + 1):
