@@ -14,6 +14,10 @@
 // idle lanes small.
 #include <algorithm>
 #include <cstdlib>
+#include <array>
+#include <cstdio>
+#include <map>
+#include <mutex>
 #include <stdexcept>
 #include <type_traits>
 
@@ -35,15 +39,35 @@ struct MinWaves<Op, std::void_t<decltype(Op::MIN_WAVES)>> {
   static constexpr int value = Op::MIN_WAVES;
 };
 
+// Largest workgroup of an operator's z-march: Op::MAX_THREADS where the operator sets it,
+// else 256.
+template <class Op, class = void>
+struct MaxThreads {
+  static constexpr int value = 256;
+};
+template <class Op>
+struct MaxThreads<Op, std::void_t<decltype(Op::MAX_THREADS)>> {
+  static constexpr int value = Op::MAX_THREADS;
+};
+
+// Shape of a z-march launch: tiles of tx x ty threads (tx * ty <= the kernel's NT, the
+// workgroup rounded up to whole wavefronts) and the nz + 1 node planes split into `chunks`
+// z ranges of as equal length as possible.
+struct ZShape {
+  int tx, ty, chunks;
+};
+
 // FINE: 1 for launches on the finest grid, 0 on coarser multigrid levels (the same code;
 // separate instantiations keep the two apart in kernel traces).
-template <class Op, int TX, int TY, int FINE>
-__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MinWaves<Op>::value)))
-void zmarch_kernel(const Op op, const int KZ) {
+template <class Op, int NT, int FINE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<Op>::value)))
+void zmarch_kernel(const Op op, const ZShape zs) {
   using T = typename Op::real;
-  constexpr int NI = Op::NIN, NO = Op::NOUT, NT = TX * TY;
+  constexpr int NI = Op::NIN, NO = Op::NOUT;
   __shared__ T xch[6 * NO * NT];
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+  const int TX = zs.tx;
+  const int tid = threadIdx.x, ty = tid / TX, tx = tid - ty * TX;
+  const bool active = ty < zs.ty;   // lanes past the tile in its last wavefront idle
   const int nx = op.g.nx, ny = op.g.ny, nz = op.g.nz;
   // XCD-aware tile order: workgroups are dispatched round-robin over the XCDs by linear id,
   // so id w runs on XCD w % NXCD; give each XCD one contiguous range of tiles (x fastest,
@@ -54,12 +78,13 @@ void zmarch_kernel(const Op op, const int KZ) {
   const unsigned tile = xcd < rem ? xcd * (per + 1) + kk : rem * (per + 1) + (xcd - rem) * per + kk;
   const int bx = (int)(tile % nbx), by = (int)((tile / nbx) % nby), bz = (int)(tile / (nbx * nby));
   const int i = bx * (TX - 1) - 1 + tx;
-  const int j = by * (TY - 1) - 1 + ty;
-  const int K0 = bz * KZ;
-  const bool colok = i >= 0 && i < nx && j >= 0 && j < ny;
-  const bool owner = tx >= 1 && ty >= 1 && i <= nx && j <= ny;
+  const int j = by * (zs.ty - 1) - 1 + ty;
+  // node planes [K0, K1) of this chunk
+  const int K0 = (int)((long)bz * (nz + 1) / zs.chunks), K1 = (int)((long)(bz + 1) * (nz + 1) / zs.chunks);
+  const bool colok = active && i >= 0 && i < nx && j >= 0 && j < ny;
+  const bool owner = active && tx >= 1 && ty >= 1 && i <= nx && j <= ny;
   const int kbeg = K0 > 0 ? K0 - 1 : 0;
-  const int kend = min(K0 + KZ - 1, nz);
+  const int kend = K1 - 1;
   T acc[NO];
 #pragma unroll
   for (int f = 0; f < NO; ++f) acc[f] = (T)0;
@@ -167,7 +192,8 @@ __global__ __launch_bounds__(TX* TY * 2) void zpair_kernel(const Op op) {
   }
 }
 
-// Tile shapes (threads in x, y); a tile owns (TX-1) x (TY-1) node columns.
+// Tile shapes of the coarse levels (threads in x, y); a tile owns (TX-1) x (TY-1) node
+// columns.
 struct TileCfg {
   int tx, ty;
 };
@@ -191,18 +217,95 @@ static int pick_tile(const Grid& g) {
   return bi;
 }
 
-template <class Op, int TX, int TY, int FINE>
-static void run_zmarch_t(hipStream_t st, const Op& op) {
+// Shape of the z-march on the finest grid, chosen per grid and kernel from a timing model.
+// A wavefront's element layer takes a fixed VALU time per SIMD, so a layer step of the
+// busiest CU takes w = (wavefronts it holds over all rounds) / 4 of those units, but no
+// less than LAT units however few wavefronts share a SIMD (latency no longer hidden; 2.4
+// fits the 128 x 64 x 128 sweep timings), plus w / 4 that latency does not hide either;
+// the launch takes a chunk's planes + 1 such steps.  Ties go to more resident wavefronts
+// (occupancy calculator), then to fewer lanes.  Tile
+// widths are free between 8 and NT / 8 so that the (TX-1) x (TY-1) owned columns can
+// divide the node plane with little left over: 11 x 23 threads in 26 chunks for 129 x 65 x
+// 129 nodes (26.0 us per fine sweep, against 29.1 us for 16 x 16 tiles in 22 chunks, which
+// launch 1.4 lanes per element column).  NC_ZSHAPE=tx,ty,chunks forces a shape.
+template <class Op, int NT>
+static ZShape fine_shape(const Grid& g) {
+  static const ZShape forced = [] {
+    ZShape z{0, 0, 0};
+    const char* e = std::getenv("NC_ZSHAPE");
+    if (e && std::sscanf(e, "%d,%d,%d", &z.tx, &z.ty, &z.chunks) != 3) z = ZShape{0, 0, 0};
+    return z;
+  }();
+  if (forced.tx >= 2 && forced.ty >= 2 && forced.tx * forced.ty <= NT && forced.chunks >= 1 &&
+      forced.chunks <= g.nz + 1)
+    return forced;
+  static std::mutex mu;
+  static std::map<std::array<int, 4>, ZShape> cache;
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  const std::array<int, 4> key{g.nx, g.ny, g.nz, dev};
+  const auto hit = cache.find(key);
+  if (hit != cache.end()) return hit->second;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+  int resident[NT / 64 + 1] = {0};   // workgroups per CU by wavefronts per workgroup
+  for (int w = 1; w <= NT / 64; ++w) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(zmarch_kernel<Op, NT, 1>),
+                                                     64 * w, 0) != hipSuccess || nb < 1)
+      nb = 1;
+    resident[w] = nb;
+  }
+  constexpr double LAT = 2.4;
+  double best = -1;
+  long best_live = 0, best_lanes = 0;
+  ZShape bz{16, 16, 1};
+  for (int tx = 8; tx <= NT / 8; ++tx)
+    for (int ty = 8; tx * ty <= NT; ++ty) {
+      const int waves = ceil_div(tx * ty, 64);
+      const long tiles = (long)ceil_div(g.nx + 1, tx - 1) * ceil_div(g.ny + 1, ty - 1);
+      for (int ch = 1; ch <= g.nz + 1; ++ch) {
+        const long per_cu = (tiles * ch + cus - 1) / cus;
+        const int kz = ceil_div(g.nz + 1, ch);
+        const double w = (double)(per_cu * waves) / 4.0;
+        const double cost = (kz + 1) * (std::max(LAT, w) + 0.25 * w);
+        const long live = std::min<long>(per_cu, resident[waves]) * waves;
+        const long lanes = tiles * ch * waves;
+        const bool better = best < 0 || cost < best * (1 - 1e-9) ||
+                            (cost <= best * (1 + 1e-9) && (live > best_live || (live == best_live && lanes < best_lanes)));
+        if (better) {
+          best = cost;
+          best_live = live;
+          best_lanes = lanes;
+          bz = ZShape{tx, ty, ch};
+        }
+      }
+    }
+  cache[key] = bz;
+  return bz;
+}
+
+template <class Op>
+static void run_zmarch_fine(hipStream_t st, const Op& op) {
+  constexpr int NT = MaxThreads<Op>::value;
+  const Grid& g = op.g;
+  const ZShape zs = fine_shape<Op, NT>(g);
+  const dim3 grid(ceil_div(g.nx + 1, zs.tx - 1), ceil_div(g.ny + 1, zs.ty - 1), zs.chunks);
+  launch((zmarch_kernel<Op, NT, 1>), grid, dim3(64 * ceil_div(zs.tx * zs.ty, 64)), 0, st, op, zs);
+}
+
+template <class Op, int TX, int TY>
+static void run_zmarch_coarse(hipStream_t st, const Op& op) {
+  constexpr int NT = MaxThreads<Op>::value;
   const Grid& g = op.g;
   const int tiles_x = ceil_div(g.nx + 1, TX - 1);
   const int tiles_y = ceil_div(g.ny + 1, TY - 1);
-  // z chunks: about `target` workgroups over the device (NC_ZBLOCKS overrides on the finest
-  // grid, NC_ZBLOCKS_COARSE on coarser levels) with at
-  // least `kzmin` node planes per chunk (NC_KZMIN overrides).  A thread's serial work is
-  // KZ + 1 element layers, so short chunks cut the latency of launches on small grids at
-  // the price of recomputing more halo layers.
+  // z chunks on the coarse levels: about `target` workgroups over the device
+  // (NC_ZBLOCKS_COARSE overrides) with at least `kzmin` node planes per chunk (NC_KZMIN
+  // overrides).  A thread's serial work is KZ + 1 element layers, so short chunks cut the
+  // latency of launches on small grids at the price of recomputing more halo layers.
   static const int target = [] {
-    const char* e = std::getenv(FINE ? "NC_ZBLOCKS" : "NC_ZBLOCKS_COARSE");
+    const char* e = std::getenv("NC_ZBLOCKS_COARSE");
     return e ? std::max(1, std::atoi(e)) : 1024;
   }();
   static const int kzmin = [] {
@@ -212,25 +315,28 @@ static void run_zmarch_t(hipStream_t st, const Op& op) {
   const int want = std::max(1, target * 256 / (TX * TY) / std::max(1, tiles_x * tiles_y));
   const int KZ = std::max(kzmin, ceil_div(g.nz + 1, want));
   const int chunks = ceil_div(g.nz + 1, KZ);
-  if constexpr (!FINE) {
-    // paired layers win where the launch is latency bound (32x16x32 6.8 -> 6.1 us,
-    // 16x8x16 6.4 -> 5.5 us) and lose where it has work to fill the chip (64x32x64
-    // 11.5 -> 14.0 us)
-    if (KZ == 1 && g.elems() <= 16384) {
-      launch((zpair_kernel<Op, TX, TY>), dim3(tiles_x, tiles_y, g.nz + 1), dim3(TX, TY, 2), 0, st, op);
-      return;
-    }
+  // paired layers win where the launch is latency bound (32x16x32 6.8 -> 6.1 us,
+  // 16x8x16 6.4 -> 5.5 us) and lose where it has work to fill the chip (64x32x64
+  // 11.5 -> 14.0 us)
+  if (KZ == 1 && g.elems() <= 16384) {
+    launch((zpair_kernel<Op, TX, TY>), dim3(tiles_x, tiles_y, g.nz + 1), dim3(TX, TY, 2), 0, st, op);
+    return;
   }
-  dim3 grid(tiles_x, tiles_y, chunks), block(TX, TY, 1);
-  launch((zmarch_kernel<Op, TX, TY, FINE>), grid, block, 0, st, op, KZ);
+  static_assert(TX * TY <= NT, "coarse tiles fit the kernel's workgroup");
+  launch((zmarch_kernel<Op, NT, 0>), dim3(tiles_x, tiles_y, chunks), dim3(TX * TY), 0, st, op,
+         ZShape{TX, TY, chunks});
 }
 
 template <class Op, int FINE = 1>
 static void run_zmarch(hipStream_t st, const Op& op) {
-  switch (pick_tile(op.g)) {
-    case 0: run_zmarch_t<Op, 16, 16, FINE>(st, op); break;
-    case 1: run_zmarch_t<Op, 32, 8, FINE>(st, op); break;
-    default: run_zmarch_t<Op, 8, 8, FINE>(st, op); break;
+  if constexpr (FINE) {
+    run_zmarch_fine(st, op);
+  } else {
+    switch (pick_tile(op.g)) {
+      case 0: run_zmarch_coarse<Op, 16, 16>(st, op); break;
+      case 1: run_zmarch_coarse<Op, 32, 8>(st, op); break;
+      default: run_zmarch_coarse<Op, 8, 8>(st, op); break;
+    }
   }
 }
 

@@ -59,20 +59,28 @@ __global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf
   }
 }
 
-// Trilinear prolongation added to the fine iterate; one thread per fine node.
+// Trilinear prolongation added to the fine iterate; one thread per pair of fine nodes
+// (2m, j, k), (2m + 1, j, k) along x.
 template <typename T>
 __global__ void prolong_kernel(Grid fine, Grid coarse, const T* __restrict__ xc, T* __restrict__ xf) {
-  const PlaneIdx q = plane_idx(fine);
-  if (!q.ok) return;
-  const int i = q.i, j = q.j, k = q.k;
-  TAcc<T> sp, stt;
-  prolong_taps(coarse, i, j, k, xc, sp, stt);
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int row = coarse.nx + 1;   // pairs per fine row; the last pair has its even node only
+  const int j = p / row, m = p - j * row, k = (int)blockIdx.y;
+  if (j > fine.ny) return;
+  TAcc<T> sp[2], stt[2];
+  prolong_taps_pair(coarse, m, j, k, xc, sp, stt);
   using P2 = typename Pair<T>::type;
-  const int n = fine.node(i, j, k);
-  P2 v = reinterpret_cast<const P2*>(xf)[n];
-  if (!fine.pfix(i, j, k)) v.x += (T)sp;
-  if (!fine.tfix(i, j, k)) v.y += (T)stt;
-  reinterpret_cast<P2*>(xf)[n] = v;
+  P2* x = reinterpret_cast<P2*>(xf);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = 2 * m + h;
+    if (i > fine.nx) break;
+    const int n = fine.node(i, j, k);
+    P2 v = x[n];
+    if (!fine.pfix(i, j, k)) v.x += (T)sp[h];
+    if (!fine.tfix(i, j, k)) v.y += (T)stt[h];
+    x[n] = v;
+  }
 }
 
 template <typename T>
@@ -112,7 +120,8 @@ void launch_restrict(hipStream_t st, const Grid& fine, const Grid& coarse, const
 }
 template <typename T>
 void launch_prolong_add(hipStream_t st, const Grid& fine, const Grid& coarse, const T* xc, T* xf) {
-  launch(prolong_kernel<T>, plane_grid(fine, 256), dim3(256), 0, st, fine, coarse, xc, xf);
+  const dim3 grid((unsigned)ceil_div((long)(coarse.nx + 1) * (fine.ny + 1), 256), (unsigned)(fine.nz + 1));
+  launch(prolong_kernel<T>, grid, dim3(256), 0, st, fine, coarse, xc, xf);
 }
 template <typename T>
 void launch_inject_state(hipStream_t st, const Grid& fine, const Grid& coarse, const T* sf, T* sc) {

@@ -1,0 +1,74 @@
+"""The operator kernels add every node's element contributions in one fixed order (the
+layer below, then the node's own layer, corner by corner) whatever the tile shape and the
+z chunking of the launch, so that shapes forced through NC_ZSHAPE (finest grid) and NC_TILE
+(coarser levels) reproduce the residual, the Jacobian applies in both precisions, a
+preconditioner application and a whole state + adjoint solve bit for bit.  Each shape
+runs in a child process because the library reads the two variables once per process."""
+
+import os
+import subprocess
+import sys
+
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+CHILD = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[2])
+from paper_1904_00182_amd import nc, workloads
+grid = (32, 16, 32)
+out = {}
+for prec in (nc.NC_FP64, nc.NC_MIXED):
+    p = workloads.problem(grid, 1e4, prec)
+    sol = nc.Solver(p, "cuda:0")
+    sol.set_design(workloads.design(grid, "blobs", 4, "cuda:0"))
+    rng = np.random.default_rng(3)
+    s0 = torch.as_tensor(rng.standard_normal((sol.N, 5)) * 0.05, device="cuda:0")
+    v = torch.as_tensor(rng.standard_normal((sol.N, 5)), device="cuda:0")
+    out[f"{prec}-residual"] = sol.residual(s0)
+    sol.linearize(s0)
+    for tr in (False, True):
+        out[f"{prec}-jac{int(tr)}"] = sol.jac_apply(v, transpose=tr)
+        out[f"{prec}-jac32_{int(tr)}"] = sol.jac_apply(v.float(), transpose=tr)
+        out[f"{prec}-pc{int(tr)}"] = sol.precondition(s0, v[:, 3:].contiguous(), transpose=tr)
+    s = sol.solve_state()
+    out[f"{prec}-state"] = s
+    out[f"{prec}-adjoint"] = sol.solve_adjoint(s, sol.objective_grad())
+    out[f"{prec}-its"] = torch.tensor([sol.last_info["krylov_its"]])
+torch.save({k: t.cpu() for k, t in out.items()}, sys.argv[1])
+"""
+
+# (NC_ZSHAPE, NC_TILE): ragged tiles in several chunks, one node plane per chunk, a single
+# chunk marching through all 33 planes; the coarse levels on each of the three tiles
+SHAPES = [(None, None), ("9,13,5", "1"), ("16,16,33", "2"), ("11,23,1", "0")]
+
+
+def _run(tmp_path, zshape, tile):
+    env = dict(os.environ)
+    env.pop("NC_ZSHAPE", None)
+    env.pop("NC_TILE", None)
+    if zshape:
+        env["NC_ZSHAPE"] = zshape
+    if tile:
+        env["NC_TILE"] = tile
+    path = str(tmp_path / f"out_{zshape}_{tile}.pt")
+    print("z-march shape", zshape, "coarse tile", tile, flush=True)
+    r = subprocess.run([sys.executable, "-c", CHILD, path, ROOT], env=env, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return torch.load(path, weights_only=True)
+
+
+def test_results_do_not_depend_on_the_launch_shape(tmp_path):
+    ref = _run(tmp_path, *SHAPES[0])
+    assert all(torch.isfinite(t).all() for t in ref.values())
+    for zshape, tile in SHAPES[1:]:
+        got = _run(tmp_path, zshape, tile)
+        for k in ref:
+            assert torch.equal(ref[k], got[k]), (zshape, tile, k)
