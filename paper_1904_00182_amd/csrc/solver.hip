@@ -83,6 +83,13 @@ struct nc_ctx {
   double* gjwork;
   int ncoarse;
   bool dense;            // coarsest level solved by the dense inverse (else smoothing only)
+  // The coarsest inverse is built on a stream of its own, concurrently with the other
+  // levels' setup and the first half of the first V-cycle: `fork` (on stream) orders it
+  // after the state injection, `join` (on side) marks it done, and join_pending says
+  // whether stream still has to wait for it before the first use of A.
+  hipStream_t side;
+  hipEvent_t fork, join;
+  bool join_pending;
   // Krylov space in the working precision
   void *V, *Z, *kx, *kb;
   // reductions
@@ -121,6 +128,7 @@ namespace {
 // ------------------------------------------------------------------ event timing
 void timing_flush(nc_ctx* c) {
   if (!c->timing || c->ev_used == 0) return;
+  ck(hipStreamSynchronize(c->side));   // timed launches of the coarsest inverse
   ck(hipEventSynchronize(c->ev[2 * c->ev_used - 1]));
   for (int k = 0; k < c->ev_used; ++k) {
     float ms = 0.f;
@@ -282,14 +290,19 @@ void linearize_levels(nc_ctx* c) {
     else
       launch_inject_state<float>(st, c->lev[l - 1].g, c->lev[l].g, c->lev[l - 1].st32, c->lev[l].st32);
   }
+  if (c->dense) {
+    // after the injection (and every earlier reader of A on stream)
+    ck(hipEventRecord(c->fork, st));
+    ck(hipStreamWaitEvent(c->side, c->fork, 0));
+    { Timed tm(c, TC_SETUP); launch_coarse_assemble<T>(c->side, view<T>(c, c->L - 1), c->emats, c->A); }
+    { Timed tm(c, TC_SETUP); launch_gauss_jordan(c->side, c->A, c->ncoarse, c->perm, c->gjwork); }
+    { Timed tm(c, TC_SETUP); launch_dense_transpose(c->side, c->A, c->A + (size_t)c->ncoarse * c->ncoarse, c->ncoarse); }
+    ck(hipEventRecord(c->join, c->side));
+    c->join_pending = true;
+  }
   for (int l = 0; l < c->L; ++l) {
     Timed tm(c, TC_SETUP);
     launch_diag_inverse<T>(st, view<T>(c, l), (T*)c->lev[l].dinv, l == 0);
-  }
-  if (c->dense) {
-    { Timed tm(c, TC_SETUP); launch_coarse_assemble<T>(st, view<T>(c, c->L - 1), c->emats, c->A); }
-    { Timed tm(c, TC_SETUP); launch_gauss_jordan(st, c->A, c->ncoarse, c->perm, c->gjwork); }
-    { Timed tm(c, TC_SETUP); launch_dense_transpose(st, c->A, c->A + (size_t)c->ncoarse * c->ncoarse, c->ncoarse); }
   }
 }
 
@@ -304,6 +317,13 @@ void linearize(nc_ctx* c, const double* s, bool levels) {
   if (c->mixed) linearize_levels<float>(c);
   else linearize_levels<double>(c);
   c->hier_valid = true;
+}
+
+// Makes stream wait for the coarsest inverse built on the side stream.
+void join_coarse(nc_ctx* c) {
+  if (!c->join_pending) return;
+  ck(hipStreamWaitEvent(c->stream, c->join, 0));
+  c->join_pending = false;
 }
 
 // ------------------------------------------------------------------ V-cycle
@@ -329,6 +349,7 @@ void vcycle(nc_ctx* c, int l, bool tr, bool x_ready = false) {
   };
   if (l == c->L - 1) {
     if (c->dense) {
+      join_coarse(c);
       Timed tm(c, TC_COARSE, (double)sizeof(T) * ((double)c->ncoarse * c->ncoarse + 2.0 * c->ncoarse));
       launch_dense_apply<T>(st, c->A, c->ncoarse, tr, (const T*)L.b, (T*)L.x);
     } else {
@@ -346,6 +367,7 @@ void vcycle(nc_ctx* c, int l, bool tr, bool x_ready = false) {
   if (c->dense && c->p.coarse_tail && l + 2 == c->L - 1 && tail_cycle_fits<T>(L.g, C.g, c->lev[l + 2].g)) {
     // the rest of the cycle below this level in one workgroup
     const size_t n2 = (size_t)c->ncoarse * c->ncoarse;
+    join_coarse(c);
     Timed tm(c, TC_COARSE, sizeof(T) * (6.0 * nn(L.g) + 8.0 * nn(C.g) + 2.0 * ne(C.g)) + 8.0 * n2);
     launch_tail_cycle<T>(st, L.g, (const T*)L.r, (T*)L.x, view<T>(c, l + 1), c->lev[l + 2].g, tr ? c->A + n2 : c->A,
                          tr, om, c->p.smooth_pre_coarse, c->p.smooth_post_coarse);
@@ -911,6 +933,22 @@ size_t nc_workspace_bytes(const nc_problem* p) {
   return carve(&tmp, nullptr);
 }
 
+// Frees what a context holds besides the caller's workspace, after its side stream drains.
+static void release(nc_ctx* c) {
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->fork) (void)hipEventDestroy(c->fork);
+  if (c->join) (void)hipEventDestroy(c->join);
+  for (auto& e : c->ev) (void)hipEventDestroy(e);
+  for (auto& e : c->kev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->hbuf) (void)hipHostFree(c->hbuf);
+  if (c->hslots) (void)hipHostFree(c->hslots);
+  delete c;
+}
+
 int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stream, nc_ctx** out) {
   if (!out || !valid_problem(p) || !workspace_dev) return NC_EINVAL;
   *out = nullptr;
@@ -933,17 +971,21 @@ int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stre
     c->hier_valid = false;
     c->timing = false;
     c->ev_used = 0;
+    c->join_pending = false;
     c->kev.resize(MAXC);
-    for (auto& e : c->kev) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    if (hipHostMalloc((void**)&c->hslots, sizeof(double) * (MAXC + 1) * HSLOT, hipHostMallocDefault) != hipSuccess) {
-      for (auto& e : c->kev) (void)hipEventDestroy(e);
-      delete c;
-      return NC_EHIP;
-    }
-    if (hipHostMalloc((void**)&c->hbuf, sizeof(double) * 4 * MAXC, hipHostMallocDefault) != hipSuccess) {
-      for (auto& e : c->kev) (void)hipEventDestroy(e);
-      (void)hipHostFree(c->hslots);
-      delete c;
+    for (auto& e : c->kev) e = nullptr;
+    c->side = nullptr;
+    c->fork = c->join = nullptr;
+    c->hslots = c->hbuf = nullptr;
+    bool ok = true;
+    for (auto& e : c->kev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->join, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&c->hslots, sizeof(double) * (MAXC + 1) * HSLOT, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&c->hbuf, sizeof(double) * 4 * MAXC, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+      release(c);
       return NC_EHIP;
     }
     *out = c;
@@ -954,11 +996,7 @@ int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stre
 int nc_destroy(nc_ctx* c) {
   if (!c) return NC_EINVAL;
   (void)hipStreamSynchronize(c->stream);
-  for (auto& e : c->ev) (void)hipEventDestroy(e);
-  for (auto& e : c->kev) (void)hipEventDestroy(e);
-  (void)hipHostFree(c->hbuf);
-  (void)hipHostFree(c->hslots);
-  delete c;
+  release(c);
   return NC_OK;
 }
 
