@@ -49,9 +49,9 @@ KERNEL_NAMES = {
     "maxpy": "maxpy_kernel<{t}> (FGMRES multi-axpy)",
 }
 PROFILE_NAMES = {
-    "jv": r"zmarch_kernel<JvOp<{t}, 2, 0>, \d+, \d+, 1>", "jtw": r"zmarch_kernel<JtwOp<{t}, 2, 0>, \d+, \d+, 1>",
-    "smooth": r"zmarch_kernel<JvOp<{t}, 2, 2>, \d+, \d+, 1>", "smooth_T": r"zmarch_kernel<JtwOp<{t}, 2, 2>, \d+, \d+, 1>",
-    "pt_residual": r"zmarch_kernel<JvOp<{t}, 2, 1>, \d+, \d+, 1>", "mdot": r"mdot_kernel<{t}>", "maxpy": r"maxpy_kernel<{t}>",
+    "jv": r"zmarch_kernel<JvOp<{t}, 2, 0>, \d+, 1>", "jtw": r"zmarch_kernel<JtwOp<{t}, 2, 0>, \d+, 1>",
+    "smooth": r"zmarch_kernel<JvOp<{t}, 2, 2>, \d+, 1>", "smooth_T": r"zmarch_kernel<JtwOp<{t}, 2, 2>, \d+, 1>",
+    "pt_residual": r"zmarch_kernel<JvOp<{t}, 2, 1>, \d+, 1>", "mdot": r"mdot_kernel<{t}>", "maxpy": r"maxpy_kernel<{t}>",
 }
 # kernel sources whose hash must match the one recorded with the counter runs
 KERNEL_SOURCES = ["paper_1904_00182_amd/csrc/k_misc.hip", "paper_1904_00182_amd/csrc/k_apply.hip",

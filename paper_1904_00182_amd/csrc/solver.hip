@@ -84,12 +84,14 @@ struct nc_ctx {
   int ncoarse;
   bool dense;            // coarsest level solved by the dense inverse (else smoothing only)
   // The coarsest inverse is built on a stream of its own, concurrently with the other
-  // levels' setup and the first half of the first V-cycle: `fork` (on stream) orders it
-  // after the state injection, `join` (on side) marks it done, and join_pending says
-  // whether stream still has to wait for it before the first use of A.
-  hipStream_t side;
-  hipEvent_t fork, join;
-  bool join_pending;
+  // levels' setup and the first half of the first V-cycle, and the coarser levels' node-
+  // block inverses on a second one, concurrently with the finest level's: `fork` (on
+  // stream) orders both after the state injection, `join` (on side) and `join2` (on side2)
+  // mark them done, and the pending flags say whether stream still has to wait for them
+  // (before the first use of A, and before the first step down from the finest level).
+  hipStream_t side, side2;
+  hipEvent_t fork, join, join2;
+  bool join_pending, join2_pending;
   // Krylov space in the working precision
   void *V, *Z, *kx, *kb;
   // reductions
@@ -128,7 +130,8 @@ namespace {
 // ------------------------------------------------------------------ event timing
 void timing_flush(nc_ctx* c) {
   if (!c->timing || c->ev_used == 0) return;
-  ck(hipStreamSynchronize(c->side));   // timed launches of the coarsest inverse
+  ck(hipStreamSynchronize(c->side));   // timed launches on the setup streams
+  ck(hipStreamSynchronize(c->side2));
   ck(hipEventSynchronize(c->ev[2 * c->ev_used - 1]));
   for (int k = 0; k < c->ev_used; ++k) {
     float ms = 0.f;
@@ -280,19 +283,44 @@ void fetch(nc_ctx* c, const double* dev, int count) {
   sync(c);
 }
 
+// Make stream wait for the coarsest inverse built on the side stream, and for the coarser
+// levels' node-block inverses.
+void join_coarse(nc_ctx* c) {
+  if (!c->join_pending) return;
+  ck(hipStreamWaitEvent(c->stream, c->join, 0));
+  c->join_pending = false;
+}
+void join_levels(nc_ctx* c) {
+  if (!c->join2_pending) return;
+  ck(hipStreamWaitEvent(c->stream, c->join2, 0));
+  c->join2_pending = false;
+}
+
 // ------------------------------------------------------------------ linearisation
 template <typename T>
 void linearize_levels(nc_ctx* c) {
   hipStream_t st = c->stream;
+  // the injection below overwrites what the previous setup on the side streams read
+  join_coarse(c);
+  join_levels(c);
   for (int l = 1; l < c->L; ++l) {
     if (sizeof(T) == 8)
       launch_inject_state<double>(st, c->lev[l - 1].g, c->lev[l].g, c->lev[l - 1].st64, c->lev[l].st64);
     else
       launch_inject_state<float>(st, c->lev[l - 1].g, c->lev[l].g, c->lev[l - 1].st32, c->lev[l].st32);
   }
+  // after the injection (and every earlier reader of A and of the coarse levels on stream)
+  if (c->dense || c->L > 1) ck(hipEventRecord(c->fork, st));
+  if (c->L > 1) {
+    ck(hipStreamWaitEvent(c->side2, c->fork, 0));
+    for (int l = 1; l < c->L; ++l) {
+      Timed tm(c, TC_SETUP);
+      launch_diag_inverse<T>(c->side2, view<T>(c, l), (T*)c->lev[l].dinv, false);
+    }
+    ck(hipEventRecord(c->join2, c->side2));
+    c->join2_pending = true;
+  }
   if (c->dense) {
-    // after the injection (and every earlier reader of A on stream)
-    ck(hipEventRecord(c->fork, st));
     ck(hipStreamWaitEvent(c->side, c->fork, 0));
     { Timed tm(c, TC_SETUP); launch_coarse_assemble<T>(c->side, view<T>(c, c->L - 1), c->emats, c->A); }
     { Timed tm(c, TC_SETUP); launch_gauss_jordan(c->side, c->A, c->ncoarse, c->perm, c->gjwork); }
@@ -300,9 +328,9 @@ void linearize_levels(nc_ctx* c) {
     ck(hipEventRecord(c->join, c->side));
     c->join_pending = true;
   }
-  for (int l = 0; l < c->L; ++l) {
+  {
     Timed tm(c, TC_SETUP);
-    launch_diag_inverse<T>(st, view<T>(c, l), (T*)c->lev[l].dinv, l == 0);
+    launch_diag_inverse<T>(st, view<T>(c, 0), (T*)c->lev[0].dinv, true);
   }
 }
 
@@ -317,13 +345,6 @@ void linearize(nc_ctx* c, const double* s, bool levels) {
   if (c->mixed) linearize_levels<float>(c);
   else linearize_levels<double>(c);
   c->hier_valid = true;
-}
-
-// Makes stream wait for the coarsest inverse built on the side stream.
-void join_coarse(nc_ctx* c) {
-  if (!c->join_pending) return;
-  ck(hipStreamWaitEvent(c->stream, c->join, 0));
-  c->join_pending = false;
 }
 
 // ------------------------------------------------------------------ V-cycle
@@ -364,6 +385,7 @@ void vcycle(nc_ctx* c, int l, bool tr, bool x_ready = false) {
   for (int s = 1; s < npre; ++s) sweep();
   { Timed tm(c, l == 0 ? TC_PT_RESID : TC_PT_RESID_COARSE, sizeof(T) * (8 * nn(L.g) + 2 * ne(L.g))); launch_pt_apply<T>(st, v, tr, MODE_RESID, (const T*)L.x, (const T*)L.b, (T*)L.r, om, l == 0); }
   Level& C = c->lev[l + 1];
+  if (l == 0) join_levels(c);
   if (c->dense && c->p.coarse_tail && l + 2 == c->L - 1 && tail_cycle_fits<T>(L.g, C.g, c->lev[l + 2].g)) {
     // the rest of the cycle below this level in one workgroup
     const size_t n2 = (size_t)c->ncoarse * c->ncoarse;
@@ -935,12 +957,13 @@ size_t nc_workspace_bytes(const nc_problem* p) {
 
 // Frees what a context holds besides the caller's workspace, after its side stream drains.
 static void release(nc_ctx* c) {
-  if (c->side) {
-    (void)hipStreamSynchronize(c->side);
-    (void)hipStreamDestroy(c->side);
-  }
-  if (c->fork) (void)hipEventDestroy(c->fork);
-  if (c->join) (void)hipEventDestroy(c->join);
+  for (hipStream_t s : {c->side, c->side2})
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  for (hipEvent_t e : {c->fork, c->join, c->join2})
+    if (e) (void)hipEventDestroy(e);
   for (auto& e : c->ev) (void)hipEventDestroy(e);
   for (auto& e : c->kev)
     if (e) (void)hipEventDestroy(e);
@@ -971,17 +994,19 @@ int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stre
     c->hier_valid = false;
     c->timing = false;
     c->ev_used = 0;
-    c->join_pending = false;
+    c->join_pending = c->join2_pending = false;
     c->kev.resize(MAXC);
     for (auto& e : c->kev) e = nullptr;
-    c->side = nullptr;
-    c->fork = c->join = nullptr;
+    c->side = c->side2 = nullptr;
+    c->fork = c->join = c->join2 = nullptr;
     c->hslots = c->hbuf = nullptr;
     bool ok = true;
     for (auto& e : c->kev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&c->join, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->join2, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&c->hslots, sizeof(double) * (MAXC + 1) * HSLOT, hipHostMallocDefault) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&c->hbuf, sizeof(double) * 4 * MAXC, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
@@ -1018,6 +1043,9 @@ int nc_set_design(nc_ctx* c, const double* x) {
     hipStream_t st = c->stream;
     const nc_problem& p = c->p;
     Level& L0 = c->lev[0];
+    // the setup streams may still read the coefficients of the previous design
+    join_coarse(c);
+    join_levels(c);
     launch_cone_filter(st, L0.g, p.filter_radius, x, c->gamma, false, c->ftmp);
     launch_ramp(st, c->E, c->gamma, p.k_f, p.k_s, p.q_c, p.kappa_f, p.kappa_s, p.q_p, L0.coef64, L0.coef32, c->dk,
                 c->dkap);
