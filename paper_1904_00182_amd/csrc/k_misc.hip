@@ -40,7 +40,7 @@ static inline dim3 plane_grid(const Grid& g, int bs) {
 // block-Jacobi step of the coarse level from a zero guess, x = omega D^-1 b (D^-T b when
 // transposed).
 template <typename T>
-__global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf, T* __restrict__ bc,
+__global__ __launch_bounds__(128) void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf, T* __restrict__ bc,
                                 const T* __restrict__ dinv, int transpose, T omega, T* __restrict__ xc) {
   const PlaneIdx q = plane_idx(coarse);
   if (!q.ok) return;
@@ -62,7 +62,7 @@ __global__ void restrict_kernel(Grid fine, Grid coarse, const T* __restrict__ rf
 // Trilinear prolongation added to the fine iterate; one thread per pair of fine nodes
 // (2m, j, k), (2m + 1, j, k) along x.
 template <typename T>
-__global__ void prolong_kernel(Grid fine, Grid coarse, const T* __restrict__ xc, T* __restrict__ xf) {
+__global__ __launch_bounds__(256) void prolong_kernel(Grid fine, Grid coarse, const T* __restrict__ xc, T* __restrict__ xf) {
   const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   const int row = coarse.nx + 1;   // pairs per fine row; the last pair has its even node only
   const int j = p / row, m = p - j * row, k = (int)blockIdx.y;
@@ -136,7 +136,7 @@ void launch_average_coef(hipStream_t st, const Grid& fine, const Grid& coarse, c
 // Element Jacobian columns of the (P, T) operator: mats[e][col][row], 16 x 16, local dof
 // index 2 a + field.
 template <typename T>
-__global__ void elem_matrix_kernel(LevelView<T> L, double* __restrict__ mats) {
+__global__ __launch_bounds__(BS) void elem_matrix_kernel(LevelView<T> L, double* __restrict__ mats) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long E = L.g.elems();
   if (t >= E * 16) return;
@@ -1080,7 +1080,7 @@ void launch_ramp(hipStream_t st, long E, const double* gamma, double k_f, double
 }
 
 // ------------------------------------------------------------------ sensitivities
-__global__ void sensitivity_kernel(Grid g, ElemConst<double> c, const double* __restrict__ coef,
+__global__ __launch_bounds__(BS) void sensitivity_kernel(Grid g, ElemConst<double> c, const double* __restrict__ coef,
                                    const double* __restrict__ dk, const double* __restrict__ dkap,
                                    const double* __restrict__ s5, const double* __restrict__ l5, double* __restrict__ out) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
