@@ -656,11 +656,32 @@ static size_t tail_lds_bytes(const Grid& g, const Grid& gc, bool pf) {
   return sizeof(T) * (con + 6 * (size_t)g.nodes() + (pf ? 6 * (size_t)g.nodes() + 2 * (size_t)g.elems() : 0));
 }
 
-__device__ inline void tail_ijk(int n, int nx1, int ny1, int& i, int& j, int& k) {
-  i = n % nx1;
-  j = (n / nx1) % ny1;
-  k = n / (nx1 * ny1);
-}
+// (i, j, k) of a linear index n = i + nx1 (j + ny1 k) in a box of nx1 x ny1 x ... points.
+// The two divisions take a float estimate of the quotient and one correction step, exact
+// for n < 2^22 (the tail's grids are far smaller), in place of the integer division
+// sequences that otherwise dominate the tail's index arithmetic.
+struct TailIdx {
+  int d1, d2;
+  float r1, r2;
+  __device__ TailIdx(int nx1, int ny1) : d1(nx1), d2(nx1 * ny1), r1(1.0f / (float)nx1), r2(1.0f / (float)(nx1 * ny1)) {}
+  __device__ static int div(int n, int d, float r, int& rem) {
+    int q = (int)((float)n * r);
+    rem = n - q * d;
+    if (rem < 0) {
+      --q;
+      rem += d;
+    } else if (rem >= d) {
+      ++q;
+      rem -= d;
+    }
+    return q;
+  }
+  __device__ void operator()(int n, int& i, int& j, int& k) const {
+    int rem;
+    k = div(n, d2, r2, rem);
+    j = div(rem, d1, r1, i);
+  }
+};
 
 template <typename T, bool TR, bool PF>
 __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs<T> a) {
@@ -679,6 +700,8 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
   T* xc = con + nc2;
   const int t = threadIdx.x;
   const T om = a.omega;
+  const TailIdx node_g(g.nx + 1, g.ny + 1), elem_g(g.nx, g.ny), node_gc(gc.nx + 1, gc.ny + 1),
+      node_gu(gu.nx + 1, gu.ny + 1);
   if constexpr (PF) {
     for (int m = t; m < 4 * N; m += TAIL_THREADS) sD[m] = a.lv.dinv[m];
     for (int m = t; m < 2 * N; m += TAIL_THREADS) sSt[m] = a.lv.st[m];
@@ -689,7 +712,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
   const T* CO = PF ? (const T*)sCoef : a.lv.coef;
   for (int n = t; n < N; n += TAIL_THREADS) {
     int I, J, K;
-    tail_ijk(n, g.nx + 1, g.ny + 1, I, J, K);
+    node_g(n, I, J, K);
     TAcc<T> sp, stt;
     restrict_taps(gu, I, J, K, a.ru, sp, stt);
     const T bp = g.pfix(I, J, K) ? (T)0 : (T)sp;
@@ -707,7 +730,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
   for (int q = 0; q < passes; ++q) {
     for (int e = t; e < E; e += TAIL_THREADS) {
       int i, j, k;
-      tail_ijk(e, g.nx, g.ny, i, j, k);
+      elem_g(e, i, j, k);
       T P[8], Tn[8], p[8], w[8];
 #pragma unroll
       for (int c8 = 0; c8 < 8; ++c8) {
@@ -733,7 +756,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
     const bool resid = q == pre;
     for (int n = t; n < N; n += TAIL_THREADS) {
       int I, J, K;
-      tail_ijk(n, g.nx + 1, g.ny + 1, I, J, K);
+      node_g(n, I, J, K);
       T vp = (T)0, vt = (T)0;
 #pragma unroll
       for (int c8 = 0; c8 < 8; ++c8) {
@@ -766,27 +789,29 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
     // coarse correction: restrict the residual, solve densely, prolong into x
     for (int n = t; n < Nc; n += TAIL_THREADS) {
       int I, J, K;
-      tail_ijk(n, gc.nx + 1, gc.ny + 1, I, J, K);
+      node_gc(n, I, J, K);
       TAcc<T> sp, stt;
       restrict_taps(g, I, J, K, (const T*)y, sp, stt);
       bc[2 * n] = gc.pfix(I, J, K) ? (T)0 : (T)sp;
       bc[2 * n + 1] = gc.tfix(I, J, K) ? (T)0 : (T)stt;
     }
     __syncthreads();
-    // eight lanes per row, four independent partial sums each, combined by a butterfly
-    // inside the eight lanes
+    // eight lanes per row, combined by a butterfly inside the eight lanes; each lane loads
+    // its next TAIL_DU entries of the row before it multiplies any, so that a row costs
+    // one memory latency per 8 x TAIL_DU columns (the inverse is read from memory on every
+    // launch)
+    constexpr int TAIL_DU = 20;
     for (int row = t >> 3; row < nc2; row += TAIL_THREADS / 8) {
       const double* arow = a.ainv + (long)row * nc2;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int col = t & 7;
-      for (; col + 24 < nc2; col += 32) {
-        s0 += arow[col] * (double)bc[col];
-        s1 += arow[col + 8] * (double)bc[col + 8];
-        s2 += arow[col + 16] * (double)bc[col + 16];
-        s3 += arow[col + 24] * (double)bc[col + 24];
+      double s = 0.0;
+      for (int c0 = t & 7; c0 < nc2; c0 += 8 * TAIL_DU) {
+        double av[TAIL_DU];
+#pragma unroll
+        for (int u = 0; u < TAIL_DU; ++u) av[u] = c0 + 8 * u < nc2 ? arow[c0 + 8 * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < TAIL_DU; ++u)
+          if (c0 + 8 * u < nc2) s += av[u] * (double)bc[c0 + 8 * u];
       }
-      for (; col < nc2; col += 8) s0 += arow[col] * (double)bc[col];
-      double s = (s0 + s1) + (s2 + s3);
       s += __shfl_xor(s, 1, 8);
       s += __shfl_xor(s, 2, 8);
       s += __shfl_xor(s, 4, 8);
@@ -795,7 +820,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
     __syncthreads();
     for (int n = t; n < N; n += TAIL_THREADS) {
       int I, J, K;
-      tail_ijk(n, g.nx + 1, g.ny + 1, I, J, K);
+      node_g(n, I, J, K);
       TAcc<T> sp, stt;
       prolong_taps(gc, I, J, K, (const T*)xc, sp, stt);
       if (!g.pfix(I, J, K)) x[2 * n] += (T)sp;
@@ -819,7 +844,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
       const int n = base + r * TAIL_THREADS + t;
       if (n < Nu) {
         int i, j, k;
-        tail_ijk(n, gu.nx + 1, gu.ny + 1, i, j, k);
+        node_gu(n, i, j, k);
         TAcc<T> sp, stt;
         prolong_taps(g, i, j, k, (const T*)x, sp, stt);
         if (!gu.pfix(i, j, k)) a.xu[2 * n] = up[r] + (T)sp;
