@@ -285,13 +285,13 @@ static ZShape fine_shape(const Grid& g) {
   return bz;
 }
 
-template <class Op>
+template <class Op, int FINE = 1>
 static void run_zmarch_fine(hipStream_t st, const Op& op) {
   constexpr int NT = MaxThreads<Op>::value;
   const Grid& g = op.g;
   const ZShape zs = fine_shape<Op, NT>(g);
   const dim3 grid(ceil_div(g.nx + 1, zs.tx - 1), ceil_div(g.ny + 1, zs.ty - 1), zs.chunks);
-  launch((zmarch_kernel<Op, NT, 1>), grid, dim3(64 * ceil_div(zs.tx * zs.ty, 64)), 0, st, op, zs);
+  launch((zmarch_kernel<Op, NT, FINE>), grid, dim3(64 * ceil_div(zs.tx * zs.ty, 64)), 0, st, op, zs);
 }
 
 template <class Op, int TX, int TY>
@@ -329,8 +329,15 @@ static void run_zmarch_coarse(hipStream_t st, const Op& op) {
 
 template <class Op, int FINE = 1>
 static void run_zmarch(hipStream_t st, const Op& op) {
+  // coarse levels with more than 16384 elements take the finest grid's shape model too
+  // (64 x 32 x 64: 14 x 18 threads in 65 chunks instead of 8 x 8 tiles, the level's sweeps
+  // and residuals 2.7 -> 2.35 ms per 128 x 64 x 128 step); smaller ones the fixed tiles
+  // and, where KZ = 1, the paired-layer kernel (NC_TILE forces the fixed tiles everywhere)
+  static const bool tile_forced = std::getenv("NC_TILE") != nullptr;
   if constexpr (FINE) {
     run_zmarch_fine(st, op);
+  } else if (op.g.elems() > 16384 && !tile_forced) {
+    run_zmarch_fine<Op, 0>(st, op);
   } else {
     switch (pick_tile(op.g)) {
       case 0: run_zmarch_coarse<Op, 16, 16>(st, op); break;

@@ -1,9 +1,11 @@
 """The operator kernels add every node's element contributions in one fixed order (the
 layer below, then the node's own layer, corner by corner) whatever the tile shape and the
 z chunking of the launch, so that shapes forced through NC_ZSHAPE (finest grid) and NC_TILE
-(coarser levels) reproduce the residual, the Jacobian applies in both precisions, a
-preconditioner application and a whole state + adjoint solve bit for bit.  Each shape
-runs in a child process because the library reads the two variables once per process."""
+(fixed tiles on the coarser levels, whose first one has more than 16384 elements and
+otherwise takes the modelled shape) reproduce the residual, the Jacobian applies in both
+precisions, a preconditioner application and a whole state + adjoint solve bit for bit.
+Each shape runs in a child process because the library reads the two variables once per
+process."""
 
 import os
 import subprocess
@@ -22,7 +24,7 @@ import numpy as np
 import torch
 sys.path.insert(0, sys.argv[2])
 from paper_1904_00182_amd import nc, workloads
-grid = (32, 16, 32)
+grid = (80, 40, 80)
 out = {}
 for prec in (nc.NC_FP64, nc.NC_MIXED):
     p = workloads.problem(grid, 1e4, prec)
@@ -45,8 +47,8 @@ torch.save({k: t.cpu() for k, t in out.items()}, sys.argv[1])
 """
 
 # (NC_ZSHAPE, NC_TILE): ragged tiles in several chunks, one node plane per chunk, a single
-# chunk marching through all 33 planes; the coarse levels on each of the three tiles
-SHAPES = [(None, None), ("9,13,5", "1"), ("16,16,33", "2"), ("11,23,1", "0")]
+# chunk marching through all 81 planes; the coarse levels on each of the three fixed tiles
+SHAPES = [(None, None), ("9,13,5", "1"), ("16,16,81", "2"), ("11,23,1", "0")]
 
 
 def _run(tmp_path, zshape, tile):
