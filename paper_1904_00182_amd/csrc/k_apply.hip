@@ -905,16 +905,27 @@ struct DiagOp {
     const long e = g.elem(i, j, k);
     LinM<T> L;
     lin_modal(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
-    for (int a = 0; a < 8; ++a) {
-      for (int fld = 0; fld < 2; ++fld) {
-        T p[8] = {0}, t[8] = {0}, yP[8] = {0}, yT[8] = {0}, yU[3][8];
-        if (fld == 0) p[a] = (T)1; else t[a] = (T)1;
-        elem_jv_m<T, false>(L, p, t, c, yP, yT, yU);
-        // row-major block [dRP/dP, dRP/dT; dRT/dP, dRT/dT]
-        out[a][fld] = yP[a];
-        out[a][2 + fld] = yT[a];
-      }
+    // float32: unrolled, so that the compiler folds the unit inputs through the transforms
+    // (the float64 instance would then hold too many values and spill, so it loops)
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int fld = 0; fld < 2; ++fld) column(L, a, fld, out);
+    } else {
+#pragma nounroll
+      for (int a = 0; a < 8; ++a)
+        for (int fld = 0; fld < 2; ++fld) column(L, a, fld, out);
     }
+  }
+  // the block entries of corner a from the element's response to a unit (P or T) input there
+  __device__ __attribute__((always_inline)) void column(const LinM<T>& L, int a, int fld, T out[8][NOUT]) const {
+    T p[8] = {0}, t[8] = {0}, yP[8] = {0}, yT[8] = {0}, yU[3][8];
+    if (fld == 0) p[a] = (T)1; else t[a] = (T)1;
+    elem_jv_m<T, false>(L, p, t, c, yP, yT, yU);
+    // row-major block [dRP/dP, dRP/dT; dRT/dP, dRT/dT]
+    out[a][fld] = yP[a];
+    out[a][2 + fld] = yT[a];
   }
   __device__ void finish(int i, int j, int k, const T v[NOUT]) const {
     T pp = v[0], pt = v[1], tp = v[2], tt = v[3];
