@@ -628,19 +628,22 @@ __device__ inline double hsum(double2 a, double2 b) { return a.x * b.x + a.y * b
 // device-scope fence per block, with the atomic ticket of a last-block scheme, costs far
 // more here).  The multi-axpy updates its sub-tile of w with all basis vectors in float64
 // and writes it back once, with the norm of the result reduced the same way.
-constexpr int KBS = 512;   // threads per block
-// 16-byte vectors per thread and sub-tile: 4096 elements per sub-tile in either precision
+constexpr int KBS = 256;   // threads per block
+// 16-byte vectors per thread and sub-tile: 3072 float32 / 2048 float64 elements per sub-tile
+// (the 529 sub-tiles of 4096 float32 elements that a 1M-element (P, T) vector made with
+// 512-thread blocks needed two rounds of the 512 resident blocks; 705 sub-tiles of 3072
+// fit in one round of 1024)
 template <typename T>
 struct KT {
-  static constexpr int U = sizeof(T) == 4 ? 2 : 4;
+  static constexpr int U = sizeof(T) == 4 ? 3 : 4;
 };
 // basis vectors per group; two groups are in flight at a time (the next group's loads are
 // issued before the current group is used), so that the memory system never waits for a
 // group's reductions
 template <typename T>
 struct KGT {
-  static constexpr int G = sizeof(T) == 4 ? 4 : 2;    // multi-dot
-  static constexpr int GA = sizeof(T) == 4 ? 2 : 1;   // multi-axpy (its float64 accumulators take the rest)
+  static constexpr int G = 2;                          // multi-dot
+  static constexpr int GA = 1;                         // multi-axpy (its float64 accumulators take the rest)
 };
 // blocks: at most RED_BLOCKS (partials of column c at part[c * RED_BLOCKS + b])
 
