@@ -402,7 +402,7 @@ def main():
            "bytes_per_launch": round(dom_bytes / max(dom_n, 1))}
     traffic = measured_traffic(dom, tname)
     if dom in FLOPS_PER_ELEM:
-        # operator kernels are bound by vector ALU issue (see DESIGN.md): exact flops of the
+        # operator kernels are bound by vector ALU issue: exact flops of the
         # element and node arithmetic, counted on the element code, against the vector peak
         fl = FLOPS_PER_ELEM[dom] * E + FLOPS_PER_NODE[dom] * N
         ach = fl / t_dom / 1e12
