@@ -310,8 +310,8 @@ def _cpu_model():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU execution is not part of "
-              f"this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path "
+              f"(how it would shard is described in the design notes)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1904_00182_amd import nc, workloads
