@@ -50,6 +50,19 @@ struct MaxThreads<Op, std::void_t<decltype(Op::MAX_THREADS)>> {
   static constexpr int value = Op::MAX_THREADS;
 };
 
+// Operators whose finish can take the node's own values loaded ahead (Op::prefetch,
+// Op::finish_pre), and the type that holds them (a placeholder for the others)
+template <class Op, class = void>
+struct PreOf {
+  using type = char;
+  static constexpr bool value = false;
+};
+template <class Op>
+struct PreOf<Op, std::void_t<typename Op::Pre>> {
+  using type = typename Op::Pre;
+  static constexpr bool value = true;
+};
+
 // Shape of a z-march launch: tiles of tx x ty threads (tx * ty <= the kernel's NT, the
 // workgroup rounded up to whole wavefronts) and the nz + 1 node planes split into `chunks`
 // z ranges of as equal length as possible.
@@ -158,6 +171,13 @@ __global__ __launch_bounds__(TX* TY * 2) void zpair_kernel(const Op op) {
   const int i = bx * (TX - 1) - 1 + tx;
   const int j = by * (TY - 1) - 1 + ty;
   const int kl = K - 1 + tz;
+  // the owner's own node values are loaded now, so that their latency hides behind the
+  // element arithmetic instead of following it
+  const bool own = tz == 1 && tx >= 1 && ty >= 1 && i <= nx && j <= ny;
+  typename PreOf<Op>::type pre{};
+  if constexpr (PreOf<Op>::value) {
+    if (own) pre = op.prefetch(i, j, K);
+  }
   T out[8][NO];
 #pragma unroll
   for (int a = 0; a < 8; ++a)
@@ -178,7 +198,7 @@ __global__ __launch_bounds__(TX* TY * 2) void zpair_kernel(const Op op) {
 #pragma unroll
     for (int f = 0; f < NO; ++f) xch[tz][(cc * NO + f) * NT + tid] = out[cc + 4 * (1 - tz)][f];
   __syncthreads();
-  if (tz == 1 && tx >= 1 && ty >= 1 && i <= nx && j <= ny) {
+  if (own) {
     const int tl = tid - 1, td = tid - TX, tld = tid - TX - 1;
     T v[NO];
 #pragma unroll
@@ -188,7 +208,8 @@ __global__ __launch_bounds__(TX* TY * 2) void zpair_kernel(const Op op) {
       v[f] = acc + xch[1][(0 * NO + f) * NT + tid] + xch[1][(1 * NO + f) * NT + tl] +
              xch[1][(2 * NO + f) * NT + td] + xch[1][(3 * NO + f) * NT + tld];
     }
-    op.finish(i, j, K, v);
+    if constexpr (PreOf<Op>::value) op.finish_pre(i, j, K, v, pre);
+    else op.finish(i, j, K, v);
   }
 }
 
@@ -454,7 +475,26 @@ struct JvOp {
       out[a][NF - 1] = yT[a];
     }
   }
-  __device__ void finish(int i, int j, int k, const T v[NOUT]) const {
+  // the node's own values that finish reads (x for a sweep, b, D^-1), loadable ahead of it
+  struct Pre {
+    typename Pair<T>::type xn{}, bn{};
+    typename Quad<T>::type D{};
+  };
+  __device__ Pre prefetch(int i, int j, int k) const {
+    Pre q;
+    if constexpr (NF == 2) {
+      using P2 = typename Pair<T>::type;
+      const unsigned n = g.col(i, j);
+      if constexpr (MODE == MODE_SMOOTH) {
+        q.xn = g.layer(x, 2, k).template ld<P2>(2 * n);
+        q.D = g.layer(dinv, 4, k).template ld<typename Quad<T>::type>(4 * n);
+      }
+      if constexpr (MODE != MODE_STORE) q.bn = g.layer(b, 2, k).template ld<P2>(2 * n);
+    }
+    return q;
+  }
+  __device__ void finish(int i, int j, int k, const T v[NOUT]) const { finish_pre(i, j, k, v, prefetch(i, j, k)); }
+  __device__ void finish_pre(int i, int j, int k, const T v[NOUT], const Pre& pre) const {
     using P2 = typename Pair<T>::type;
     const unsigned n = g.col(i, j);
     const auto xk = g.layer(x, NF, k);
@@ -470,19 +510,18 @@ struct JvOp {
       yk.template st<T>(5 * n + 4, rs.s[4] * at);
     } else {
       // x at the node itself: needed by the sweep, otherwise only at constrained dofs
-      P2 xn{};
-      if (MODE == MODE_SMOOTH) xn = xk.template ld<P2>(2 * n);
+      const P2 xn = pre.xn;
       const T ap = pf ? (MODE == MODE_SMOOTH ? xn.x : xk.template ld<T>(2 * n)) : v[0];
       const T at = tf ? (MODE == MODE_SMOOTH ? xn.y : xk.template ld<T>(2 * n + 1)) : v[1];
       if (MODE == MODE_STORE) {
         yk.template st<P2>(2 * n, P2{rs.s[3] * ap, rs.s[4] * at});
       } else {
-        const P2 bn = g.layer(b, 2, k).template ld<P2>(2 * n);
+        const P2 bn = pre.bn;
         const T rp = bn.x - ap, rt = bn.y - at;
         if (MODE == MODE_RESID) {
           yk.template st<P2>(2 * n, P2{rp, rt});
         } else {
-          const auto D = g.layer(dinv, 4, k).template ld<typename Quad<T>::type>(4 * n);
+          const auto D = pre.D;
           yk.template st<P2>(2 * n, P2{xn.x + omega * (D.x * rp + D.y * rt), xn.y + omega * (D.z * rp + D.w * rt)});
         }
       }
@@ -544,7 +583,26 @@ struct JtwOp {
 #pragma unroll
     for (int a = 0; a < 8; ++a) { out[a][0] = yP[a]; out[a][1] = yT[a]; }
   }
-  __device__ void finish(int i, int j, int k, const T v[NOUT]) const {
+  // the node's own values that finish reads (x for a sweep, b, D^-1), loadable ahead of it
+  struct Pre {
+    typename Pair<T>::type xn{}, bn{};
+    typename Quad<T>::type D{};
+  };
+  __device__ Pre prefetch(int i, int j, int k) const {
+    Pre q;
+    if constexpr (NF == 2) {
+      using P2 = typename Pair<T>::type;
+      const unsigned n = g.col(i, j);
+      if constexpr (MODE == MODE_SMOOTH) {
+        q.xn = g.layer(x, 2, k).template ld<P2>(2 * n);
+        q.D = g.layer(dinv, 4, k).template ld<typename Quad<T>::type>(4 * n);
+      }
+      if constexpr (MODE != MODE_STORE) q.bn = g.layer(b, 2, k).template ld<P2>(2 * n);
+    }
+    return q;
+  }
+  __device__ void finish(int i, int j, int k, const T v[NOUT]) const { finish_pre(i, j, k, v, prefetch(i, j, k)); }
+  __device__ void finish_pre(int i, int j, int k, const T v[NOUT], const Pre& pre) const {
     using P2 = typename Pair<T>::type;
     const unsigned n = g.col(i, j);
     const auto xk = g.layer(x, NF, k);
@@ -560,19 +618,18 @@ struct JtwOp {
       yk.template st<T>(5 * n + 4, rs.s[4] * at);
     } else {
       // x at the node itself: needed by the sweep, otherwise only at constrained dofs
-      P2 xn{};
-      if (MODE == MODE_SMOOTH) xn = xk.template ld<P2>(2 * n);
+      const P2 xn = pre.xn;
       const T ap = pf ? (MODE == MODE_SMOOTH ? xn.x : xk.template ld<T>(2 * n)) : v[0];
       const T at = tf ? (MODE == MODE_SMOOTH ? xn.y : xk.template ld<T>(2 * n + 1)) : v[1];
       if (MODE == MODE_STORE) {
         yk.template st<P2>(2 * n, P2{rs.s[3] * ap, rs.s[4] * at});
       } else {
-        const P2 bn = g.layer(b, 2, k).template ld<P2>(2 * n);
+        const P2 bn = pre.bn;
         const T rp = bn.x - ap, rt = bn.y - at;
         if (MODE == MODE_RESID) {
           yk.template st<P2>(2 * n, P2{rp, rt});
         } else {
-          const auto D = g.layer(dinv, 4, k).template ld<typename Quad<T>::type>(4 * n);   // (D^-1)^T
+          const auto D = pre.D;   // (D^-1)^T
           yk.template st<P2>(2 * n, P2{xn.x + omega * (D.x * rp + D.z * rt), xn.y + omega * (D.y * rp + D.w * rt)});
         }
       }
