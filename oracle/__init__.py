@@ -20,7 +20,10 @@ What it computes (all in float64, plain and unblocked):
 * the closed-form permeability tuning of Sec. 3 (eqs. nusselt1-nusselt5).
 
 Parity status: every function is pinned by tests under tests/ (closed forms,
-invariants, brute-force finite differences, the paper's Table tab:2).
+invariants, brute-force finite differences, the paper's Table tab:2); the SUPG
+parameter by the closed form of 1D advection-diffusion at three cell Peclet numbers.
+One choice is not pinned: which velocity (centroid or Gauss point) enters the SUPG
+weight (the pins that exercise it have uniform flow, where the two coincide).
 """
 
 from .problem import Params, Mesh, default_constraints, patch_flux

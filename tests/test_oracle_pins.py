@@ -363,3 +363,91 @@ def test_mirror_symmetry():
     for f, sign in ((0, -1), (1, 1), (2, 1), (FIELD_P, 1), (FIELD_T, 1)):
         scale = np.abs(s[:, f]).max()
         assert np.abs(s[:, f] - sign * s[mirror, f]).max() < 1e-12 * scale, f
+
+
+# --------------------------------------------------------------------------- P13
+def _advection_diffusion_model(nx, ny, nz, U):
+    """Gr = 0, uniform fluid permeability, P fixed at both x ends so that the Darcy
+    velocity is U e_x everywhere; T = 0 at x = 0 and T = 1 at x = Lx, every other wall
+    insulated, uniform conductivity."""
+    p = Params(nx, ny, nz, alpha=0.0, q_h=0.0)
+    m = Mesh(p)
+    i = m.node_ijk[:, 0]
+    G = U * p.mu / p.kappa_f                                  # eq. finaldarcy: U = kappa G / mu
+    mask = np.zeros((m.n_nodes, NFIELD), dtype=bool)
+    vals = np.zeros((m.n_nodes, NFIELD))
+    mask[:, FIELD_P] = (i == 0) | (i == nx)
+    vals[i == nx, FIELD_P] = -G * nx * p.h
+    mask[:, FIELD_T] = (i == 0) | (i == nx)
+    vals[i == nx, FIELD_T] = 1.0
+    model = Model(p, None, constraints=(mask, vals), flux=np.zeros(m.n_nodes), gamma=np.zeros(m.n_elems))
+    return model, p, m
+
+
+def _supg_1d_closed_form(n, h, U, k, tau):
+    """Nodal temperatures of the 1D Q1 + SUPG scheme U (T+ - T-)/2 = (k + tau U^2)
+    (T+ - 2T + T-)/h with T_0 = 0, T_n = 1: T_i = (r^i - 1)/(r^n - 1) with
+    r = (D + U h/2)/(D - U h/2), D = k + tau U^2 (rho0 = c_p = 1)."""
+    D = k + tau * U * U
+    r = (D + 0.5 * U * h) / (D - 0.5 * U * h)
+    i = np.arange(n + 1)
+    return (r ** i - 1.0) / (r ** n - 1.0)
+
+
+@pytest.mark.parametrize("peclet", [0.1, 1.0, 10.0])
+def test_supg_weight_and_tau_closed_form(peclet):
+    """The SUPG weight N* = N + tau u0 . grad N and tau of App. A against a closed form.
+
+    With uniform flow U e_x and T depending on x only (linear in x inside each
+    element), the energy rows of one node plane reduce exactly to a three-point
+    scheme: per element the Galerkin convection term puts U dT h^2 / 2 on each of its two
+    node planes, the SUPG term -/+ tau U^2 dT h (its weight's x-derivative is -/+ 1/h
+    over a volume h^3), and diffusion -/+ k dT h.  The nodal solution is then the
+    discrete exponential of _supg_1d_closed_form, with tau = (tau1^-2 + tau3^-2)^(-1/2),
+    tau1 = h_e/(2 U), tau3 = h_e^2/4 and h_e^2 = 3 h^2 (the element diagonal).  The
+    cell Peclet numbers U h / (2k) of 0.1, 1 and 10 put the weight on tau3, on both and
+    on tau1; the readings of tau that a slip would produce (h_e = h, tau3 cubed, no
+    SUPG, the weight's sign flipped) miss the oracle by far more than the tolerance."""
+    nx, ny, nz = 8, 2, 3
+    h = 1.0 / nx
+    k = 1.0
+    U = 2.0 * peclet * k / h
+    model, p, m = _advection_diffusion_model(nx, ny, nz, U)
+    s, _ = model.solve_state()
+    assert rel(s[:, 0], np.full(m.n_nodes, U)) < 1e-12          # the flow is the uniform one
+    he2 = 3.0 * h * h
+    tau = (4.0 * U * U / he2 + 16.0 / he2 ** 2) ** -0.5
+    T_exact = _supg_1d_closed_form(nx, h, U, k, tau)[m.node_ijk[:, 0]]
+    assert np.abs(s[:, FIELD_T] - T_exact).max() < 1e-12
+    wrong = {
+        "h_e = h": (4.0 * U * U / h ** 2 + 16.0 / h ** 4) ** -0.5,
+        "tau3 cubed": (4.0 * U * U / he2 + (4.0 / he2) ** 3) ** -0.5,
+        "no SUPG": 0.0,
+        "weight sign flipped": -tau,
+    }
+    for name, t in wrong.items():
+        D = k + t * U * U
+        if D <= 0.5 * U * h:                                   # that scheme would oscillate
+            continue
+        alt = _supg_1d_closed_form(nx, h, U, k, t)[m.node_ijk[:, 0]]
+        assert np.abs(s[:, FIELD_T] - alt).max() > 1e-4, name
+
+
+@pytest.mark.parametrize("grid", [(16, 8, 16), (24, 12, 24), (32, 16, 32)])
+def test_patch_flux_total_and_layout(grid):
+    """The flux load of the centred 0.25 x 0.25 patch: total q_h * 0.0625 on every grid,
+    only on bottom nodes inside the patch, with the bilinear face weights q_h h^2 / 4 per
+    face (interior patch nodes q_h h^2, edges q_h h^2 / 2, corners q_h h^2 / 4)."""
+    from oracle import patch_flux
+    q_h = 1.7
+    p = Params(*grid, q_h=q_h)
+    m = Mesh(p)
+    f = patch_flux(m, p)
+    assert abs(f.sum() - q_h * 0.25 * 0.25) < 1e-14
+    x, y, z = m.node_xyz[:, 0], m.node_xyz[:, 1], m.node_xyz[:, 2]
+    inside = (z == 0) & (x >= 0.375 - 1e-12) & (x <= 0.625 + 1e-12) & (y >= 0.125 - 1e-12) & (y <= 0.375 + 1e-12)
+    assert np.all(f[~inside] == 0.0) and np.all(f[inside] > 0.0)
+    on_x_edge = np.isclose(x, 0.375) | np.isclose(x, 0.625)
+    on_y_edge = np.isclose(y, 0.125) | np.isclose(y, 0.375)
+    faces = np.where(on_x_edge & on_y_edge, 1, np.where(on_x_edge | on_y_edge, 2, 4))
+    assert np.allclose(f[inside], q_h * p.h ** 2 / 4.0 * faces[inside], rtol=1e-14, atol=0)
