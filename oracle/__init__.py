@@ -21,9 +21,9 @@ What it computes (all in float64, plain and unblocked):
 
 Parity status: every function is pinned by tests under tests/ (closed forms,
 invariants, brute-force finite differences, the paper's Table tab:2); the SUPG
-parameter by the closed form of 1D advection-diffusion at three cell Peclet numbers.
-One choice is not pinned: which velocity (centroid or Gauss point) enters the SUPG
-weight (the pins that exercise it have uniform flow, where the two coincide).
+parameter by the closed form of 1D advection-diffusion at three cell Peclet numbers,
+and the centroid velocity of the SUPG weight by a pressure mode whose centroid
+velocity vanishes (the energy row is then the Galerkin row).
 """
 
 from .problem import Params, Mesh, default_constraints, patch_flux

@@ -451,3 +451,49 @@ def test_patch_flux_total_and_layout(grid):
     on_y_edge = np.isclose(y, 0.125) | np.isclose(y, 0.375)
     faces = np.where(on_x_edge & on_y_edge, 1, np.where(on_x_edge | on_y_edge, 2, 4))
     assert np.allclose(f[inside], q_h * p.h ** 2 / 4.0 * faces[inside], rtol=1e-14, atol=0)
+
+
+# --------------------------------------------------------------------------- P14
+def test_supg_velocity_is_the_centroid_velocity():
+    """App. A evaluates the velocity of the SUPG weight at the element centroid.  For the
+    pressure mode P = c (x - xc)(y - yc) the Darcy velocity vanishes at the centroid but
+    not at the Gauss points, so the energy row must reduce to the plain Galerkin row
+    int N_a rho0 c_p u . grad T + k grad N_a . grad T, integrated here on its own with a
+    3-point Gauss-Legendre rule (exact for this polynomial integrand) and shape functions
+    written as products of 1D hat functions.  A weight built from the Gauss-point
+    velocity would add tau (u . grad N_a)(u . grad T), which is far above the tolerance."""
+    from oracle import element_residual
+    h = 0.125
+    p = Params(8, 8, 8, alpha=0.0, h=h)
+    c, kap, kcond = 900.0, 0.02, 1.3
+    a_T = np.array([0.7, -1.1, 0.4])                          # T = a_T . (x - origin) + 0.2
+    nodes = np.array([[(a >> d) & 1 for d in range(3)] for a in range(8)], dtype=float) * h
+    Pe = c * (nodes[:, 0] - h / 2) * (nodes[:, 1] - h / 2)
+    Te = nodes @ a_T + 0.2
+    _, RT, _ = element_residual(Pe[None], Te[None], np.zeros((1, 8, 3)), np.array([kcond]), np.array([kap]), p)
+
+    g, w = np.polynomial.legendre.leggauss(3)
+    pts = 0.5 * h * (1.0 + g)
+    wts = 0.5 * h * w
+    ref = np.zeros(8)
+    alt_extra = np.zeros(8)
+    for ix, x in enumerate(pts):
+        for iy, y in enumerate(pts):
+            for iz, z in enumerate(pts):
+                wq = wts[ix] * wts[iy] * wts[iz]
+                hat = [(1 - x / h, x / h), (1 - y / h, y / h), (1 - z / h, z / h)]
+                dhat = [(-1 / h, 1 / h)] * 3
+                u = -kap / p.mu * c * np.array([y - h / 2, x - h / 2, 0.0])
+                for a in range(8):
+                    ia, ja, ka = a & 1, (a >> 1) & 1, (a >> 2) & 1
+                    N = hat[0][ia] * hat[1][ja] * hat[2][ka]
+                    dN = np.array([dhat[0][ia] * hat[1][ja] * hat[2][ka],
+                                   hat[0][ia] * dhat[1][ja] * hat[2][ka],
+                                   hat[0][ia] * hat[1][ja] * dhat[2][ka]])
+                    ref[a] += wq * (N * p.rho0 * p.cp * (u @ a_T) + kcond * (dN @ a_T))
+                    he2 = 3 * h * h
+                    tq = (4 * (u @ u) / he2 + 16 / he2 ** 2) ** -0.5
+                    alt_extra[a] += wq * tq * (u @ dN) * p.rho0 * p.cp * (u @ a_T)
+    scale = np.abs(ref).max()
+    assert np.abs(RT[0] - ref).max() < 1e-13 * scale
+    assert np.abs(alt_extra).max() > 1e-3 * scale
