@@ -89,7 +89,11 @@ def parse():
     ap.add_argument("--workload", default="cavity128mixed")
     ap.add_argument("--apply-iters", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-grid", default="20,10,20")
+    ap.add_argument("--cpu-grid", default="24,12,24")
+    ap.add_argument("--no-fp64-leg", action="store_true", help="skip the float64 solve of the same workload")
+    ap.add_argument("--no-oracle-pair", action="store_true",
+                    help="skip the oracle-vs-GPU float64 pair on the 32x16x32 cavity")
+    ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--report", default=None,
                     help="also write extended measurements (operator sweep, float64 baseline, warm re-solve, "
@@ -167,6 +171,150 @@ def cpu_baseline(args, E_target):
         "host_cores_available": len(os.sched_getaffinity(0)),
         "phases_s": {k: round(v, 3) for k, v in m.timing.items()},
     }
+
+
+def nc_status(code):
+    from paper_1904_00182_amd import nc
+    return nc.load().nc_status_string(code).decode()
+
+
+def field_errors(a, b, names):
+    """Per field: relative l2 error and element-wise max|a - b| / max|b|."""
+    import torch
+    out = {}
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    for k, nm in enumerate(names):
+        if nm is None:
+            continue
+        d = (a[:, k] - b[:, k]).abs()
+        nb = float(torch.linalg.vector_norm(b[:, k]))
+        mb = float(b[:, k].abs().max())
+        out[nm] = {"rel_l2": float(torch.linalg.vector_norm(d)) / nb if nb > 0 else None,
+                   "rel_max": float(d.max()) / mb if mb > 0 else None}
+    return out
+
+
+def fp64_leg(args, mixed_result):
+    """The plain float64 GPU solve of the same workload (float64 operator, multigrid and
+    FGMRES): step time and iteration counts, and the per-field error of the mixed-precision
+    results against it."""
+    import torch
+    from paper_1904_00182_amd import nc, workloads
+    dev = "cuda:0"
+    p, x, cfg = workloads.config("cavity128", dev)
+    sol = nc.Solver(p, dev)
+    sol.set_design(x)
+    g = sol.objective_grad()
+    N = sol.N
+    s = torch.zeros((N, 5), dtype=torch.float64, device=dev)
+    lam = torch.zeros_like(s)
+    info = []
+
+    def step():
+        sol.set_design(x)
+        s.zero_()
+        sol.solve_state(out=s)
+        i1 = dict(sol.last_info)
+        sol.solve_adjoint(s, g, out=lam)
+        i2 = dict(sol.last_info)
+        if i1["status"] != nc.NC_OK or i2["status"] != nc.NC_OK:
+            raise RuntimeError(f"float64 solve did not converge: {i1['status']} {i2['status']}")
+        info.append((i1, i2))
+        return sol.sensitivity(s, lam)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.fp64_steps):
+        dfdx = step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.fp64_steps
+    i1, i2 = info[-1]
+    sm, lm, gm = mixed_result
+    out = {
+        "workload": "the same 128x64x128 cavity and design, float64 throughout",
+        "ms_per_step": round(t * 1e3, 3), "steps": args.fp64_steps,
+        "state_status": nc_status(i1["status"]), "adjoint_status": nc_status(i2["status"]),
+        "newton_its": i1["newton_its"], "state_krylov_its": i1["krylov_its"],
+        "adjoint_krylov_its": i2["krylov_its"], "adjoint_refinements": i2["refine_its"],
+        "mixed_speedup": None,
+        "mixed_vs_fp64": {
+            "state": field_errors(sm, s, ("u", "v", "w", "P", "T")),
+            "adjoint": field_errors(lm, lam, (None, None, None, "P", "T")),
+            "dfdx": field_errors(gm.reshape(-1, 1), dfdx.reshape(-1, 1), ("dfdx",)),
+        },
+    }
+    sol.close()
+    del sol
+    torch.cuda.empty_cache()
+    log(args, "fp64 leg", out)
+    return out
+
+
+def oracle_pair(args):
+    """Like for like on the 32x16x32 cavity (Gr 1e3, thresholded filtered-noise design,
+    seed 1): the float64 oracle (assembled complex-step Jacobian, SuperLU) and the float64
+    GPU solve of the same problem, timed in the same run, with the GPU's per-field error
+    against the oracle."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1904_00182_amd import inputs, nc, workloads
+    dev = "cuda:0"
+    grid = (32, 16, 32)
+    prm = oracle.Params(*grid, alpha=1e3, kappa_f=0.00513)
+    F = oracle.cone_filter_matrix(oracle.Mesh(prm), 2.0)
+    xo = (F @ inputs.uniform_design(prm.nx * prm.ny * prm.nz, 1) >= 0.5).astype(np.float64)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    m = oracle.Model(prm, xo)
+    so, _ = m.solve_state()
+    lo = m.solve_adjoint(so, m.dfds())
+    _, go = m.sensitivity(so, lo)
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    p = workloads.problem(grid, 1e3, nc.NC_FP64)
+    sol = nc.Solver(p, dev)
+    xd = torch.as_tensor(xo, device=dev)
+    sol.set_design(xd)
+    gg = sol.objective_grad()
+    res = {}
+
+    def gpu():
+        sol.set_design(xd)
+        s = sol.solve_state()
+        if sol.last_info["status"] != nc.NC_OK:
+            raise RuntimeError("GPU state solve did not converge")
+        lam = sol.solve_adjoint(s, gg)
+        if sol.last_info["status"] != nc.NC_OK:
+            raise RuntimeError("GPU adjoint solve did not converge")
+        res.update(s=s, lam=lam, dfdx=sol.sensitivity(s, lam))
+
+    gpu()
+    torch.cuda.synchronize()
+    reps = 5
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        gpu()
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - t1) / reps
+    sol.close()
+    out = {
+        "workload": "cavity 32x16x32 (16384 elements, 92565 dofs), Gr 1e3, U(0,1) design cone-filtered (R=2) "
+                    "and thresholded at 0.5 (seed 1), float64 on both sides; state + adjoint + sensitivities",
+        "oracle_s": round(wall, 3), "oracle_cores": max(1, int(round(cpu / wall))),
+        "oracle_phases_s": {k: round(v, 3) for k, v in m.timing.items()},
+        "gpu_fp64_s": round(tg, 5), "ratio": round(wall / tg, 1),
+        "gpu_vs_oracle": {
+            "state": field_errors(res["s"].cpu(), torch.as_tensor(so), ("u", "v", "w", "P", "T")),
+            "adjoint": field_errors(res["lam"].cpu(), torch.as_tensor(lo), (None, None, None, "P", "T")),
+            "dfdx": field_errors(res["dfdx"].cpu().reshape(-1, 1), torch.as_tensor(go).reshape(-1, 1), ("dfdx",)),
+        },
+    }
+    log(args, "oracle pair", out)
+    return out
 
 
 def _rel(a, b):
@@ -337,11 +485,16 @@ def main():
     infos = []
 
     def step():
+        # one design iteration's solve path: design chain (filter + RAMP), cold state
+        # solve, adjoint, sensitivities
+        sol.set_design(x)
         s.zero_()
         sol.solve_state(out=s)
         i_state = dict(sol.last_info)
         sol.solve_adjoint(s, g, out=lam)
         i_adj = dict(sol.last_info)
+        if i_state["status"] != nc.NC_OK or i_adj["status"] != nc.NC_OK:
+            raise RuntimeError(f"solve did not converge: state {i_state['status']} adjoint {i_adj['status']}")
         dfdx = sol.sensitivity(s, lam)
         infos.append((i_state, i_adj))
         return dfdx
@@ -357,6 +510,14 @@ def main():
     i_state, i_adj = infos[-1]
     f_val = sol.objective(s)
     log(args, f"step {t_step * 1e3:.1f} ms  state {i_state}  adjoint {i_adj}  f={f_val:.6e}")
+    # the design chain on its own (part of every step above)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        sol.set_design(x)
+    torch.cuda.synchronize()
+    t_design = (time.perf_counter() - t0) / 20
+    mixed_result = (s.clone(), lam.clone(), dfdx.clone())
 
     # the same steps again with HIP-event timing of every kernel class on the solver's
     # stream: the per-launch durations of the dominant operator kernel inside the solve
@@ -454,15 +615,27 @@ def main():
             "jv_f64_hbm_frac": round(bytes_jv64 / t_jv64 / 1e9 / HBM_PEAK_GBS, 4),
         },
         "solve": {
+            "state_status": nc_status(i_state["status"]), "adjoint_status": nc_status(i_adj["status"]),
             "newton_its": i_state["newton_its"], "state_krylov_its": i_state["krylov_its"],
+            "state_krylov_per_newton_step": i_state["hist_krylov"],
             "adjoint_krylov_its": i_adj["krylov_its"], "adjoint_refinements": i_adj["refine_its"],
             "levels": i_state["levels"], "state_s": round(i_state["t_total"], 4),
-            "adjoint_s": round(i_adj["t_total"], 4), "objective": f_val,
+            "state_setup_s": round(i_state["t_setup"], 5),
+            "adjoint_s": round(i_adj["t_total"], 4), "set_design_ms": round(t_design * 1e3, 3),
+            "objective": f_val,
+            "state_residual_per_field": {"initial": i_state["res0"], "final": i_state["res"]},
         },
     }
+    sol.close()
+    del sol
+    torch.cuda.empty_cache()
+    if mixed and not args.no_fp64_leg:
+        result["fp64_baseline"] = fp64_leg(args, mixed_result)
+        result["fp64_baseline"]["mixed_speedup"] = round(result["fp64_baseline"]["ms_per_step"] / (t_step * 1e3), 3)
+    if not args.no_oracle_pair:
+        result["oracle_pair"] = oracle_pair(args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args, E)
-    sol.close()
     if args.report:
         report(args, args.report)
     print(json.dumps(result), flush=True)

@@ -92,14 +92,27 @@ typedef struct nc_problem {
                                  this (Eisenstat-Walker); 0: the Krylov tolerance always   */
 } nc_problem;
 
+#define NC_HIST_MAX 32  /* Newton steps / refinement sweeps recorded in nc_info */
+
 typedef struct nc_info {
   int    newton_its;          /* Newton steps taken                                      */
   int    krylov_its;          /* total FGMRES iterations (state or adjoint)              */
-  int    refine_its;          /* outer refinement sweeps (adjoint; mixed mode)           */
+  int    refine_its;          /* outer refinement sweeps (adjoint)                       */
   int    levels;              /* multigrid levels used                                   */
-  double res[5];              /* final residual 2-norm per field (u, v, w, P, T)         */
+  double res0[5];             /* residual 2-norm per field (u, v, w, P, T) before the first
+                                 step: R~(s0) for the state, the masked rhs for the adjoint */
+  double res[5];              /* final residual 2-norm per field                         */
   double rel_res;             /* final relative residual of the last linear solve        */
+  double t_setup;             /* seconds of device time spent rebuilding the multigrid
+                                 hierarchy (state injection, node-block inverses, coarsest
+                                 inverse), summed over rebuilds; it partly overlaps the
+                                 first V-cycle, which runs beside it on the solver's stream */
+  double t_solve;             /* t_total - t_setup                                       */
   double t_total;             /* seconds, host wall clock of the call                    */
+  int    hist_len;            /* entries filled in hist_krylov / hist_res (<= NC_HIST_MAX) */
+  int    hist_krylov[NC_HIST_MAX];   /* FGMRES iterations of each Newton step (state) or
+                                        refinement sweep (adjoint)                        */
+  double hist_res[NC_HIST_MAX][5];   /* residual 2-norm per field after that step / sweep */
 } nc_info;
 
 typedef struct nc_ctx nc_ctx;
@@ -121,44 +134,62 @@ int    nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* s
 int    nc_destroy(nc_ctx* ctx);
 const char* nc_status_string(int status);
 
-/* Design chain (row a1): gamma = F_R x (cone filter, identity if radius 0), then the
- * RAMP coefficients k(gamma), kappa(gamma) and their derivatives on every level.
+/* Design chain: gamma = F_R x (the density filter of Sec. 5.1; here a cone filter of
+ * radius filter_radius element lengths, identity if 0), then the RAMP conductivity and
+ * permeability of Sec. 5.2 (eqs. condRAMP, permRAMP) and their derivatives, on the
+ * finest level and averaged onto the coarser multigrid levels.
  * x_dev: [E] float64 in [0, 1].  Enqueue only. */
 int    nc_set_design(nc_ctx* ctx, const double* x_dev);
 /* Copy the filtered density gamma [E] into gamma_dev. */
 int    nc_get_gamma(nc_ctx* ctx, double* gamma_dev);
 
-/* Nonlinear residual R~(s) of the constrained system (row a2), [N][5] -> [N][5].
- * Constrained rows hold s - s_bar (s_bar = 0). */
+/* Nonlinear residual R~(s) = M(s) s - f of App. A (eq. finalsyseq, assembled from the
+ * element integrals of eq. weakstable with the SUPG weight N* of App. A), [N][5] ->
+ * [N][5]; the velocity rows are the lumped projection of the Darcy velocity of Sec. 2.1
+ * (eq. finaldarcy).  Constrained rows hold s - s_bar (s_bar = 0).  Enqueue only. */
 int    nc_residual(nc_ctx* ctx, const double* s_dev, double* r_dev);
 
 /* Store the linearisation state (P, T of s) used by the Jacobian applies. */
 int    nc_linearize(nc_ctx* ctx, const double* s_dev);
-/* y = J~ v and y = J~^T w at the stored linearisation (rows a4, a5); J~ is the exact
- * Newton Jacobian with constrained rows and columns replaced by the identity.
- * Float64 and float32 variants ([N][5] each). */
+/* y = J~ v and y = J~^T w at the stored linearisation: J~ = dR/ds, the exact Newton
+ * Jacobian of eq. finalsyseq (Sec. 5.4), including the derivatives of the SUPG weight
+ * and tau of App. A through the centroid velocity, with constrained rows and columns
+ * replaced by the identity; J~^T is the operator of the adjoint problem of Sec. 5.1.
+ * Matrix-free, element by element.  Float64 and float32 variants ([N][5] each; the
+ * float32 ones use the float32 copy of the state and coefficients).  Enqueue only. */
 int    nc_jac_apply(nc_ctx* ctx, const double* v_dev, double* y_dev);
 int    nc_jacT_apply(nc_ctx* ctx, const double* w_dev, double* y_dev);
 int    nc_jac_apply_f32(nc_ctx* ctx, const float* v_dev, float* y_dev);
 int    nc_jacT_apply_f32(nc_ctx* ctx, const float* w_dev, float* y_dev);
 
-/* Newton state solve (rows a2-a4, a6-a9).  s_dev [N][5]: in = initial guess (zeros
- * for a cold start; constrained entries are overwritten), out = solution.
- * Synchronises; fills *info if non-NULL.  NC_NOT_CONVERGED leaves the last iterate. */
+/* State solve R~(s) = 0 by damped Newton (Sec. 5.4: full steps, damped when the
+ * residual norm grows), each linear step solved by flexible GMRES (Sec. 5.4) with a
+ * geometric-multigrid preconditioner; constraints of Sec. 6.1 (T = 0 walls, one pressure
+ * pin) fused into every kernel.  s_dev [N][5]: in = initial guess (zeros for a cold start,
+ * a previous solution for a warm start; constrained entries are overwritten), out =
+ * solution.  Synchronises; fills *info if non-NULL.  NC_NOT_CONVERGED leaves the last
+ * iterate; NC_ENAN on a non-finite residual. */
 int    nc_solve_state(nc_ctx* ctx, double* s_dev, nc_info* info);
 
-/* Objective f = f_qh^T t (the flux-weighted patch temperature; Sec. 5.1 eq. objdiscr
- * with the boundary-flux load), to *f_host.  Synchronises. */
+/* Objective f = f_qh^T t (the thermal compliance of Sec. 5.1, eq. objdiscr, with the
+ * boundary-flux load of App. A in place of the volumetric one), to *f_host.
+ * Synchronises. */
 int    nc_objective(nc_ctx* ctx, const double* s_dev, double* f_host);
 /* d f / d s, [N][5] (f_qh on the T entries of the patch nodes, 0 elsewhere). */
 int    nc_objective_grad(nc_ctx* ctx, double* g_dev);
 
-/* Adjoint solve J~^T lambda = rhs at the state s (rows a10, a11).  rhs_dev, lam_dev
- * [N][5]; the rhs is zeroed on constrained dofs, so lambda is 0 there.  Synchronises. */
+/* Adjoint solve J~^T lambda = rhs at the state s (the adjoint sensitivity analysis of
+ * Sec. 5.1; rhs = df/ds, e.g. from nc_objective_grad, Sec. 5.1 eq. objdiscr).  rhs_dev,
+ * lam_dev [N][5]; the rhs is zeroed on constrained dofs, so lambda is 0 there.  In
+ * NC_MIXED the float32 Krylov solves are refined in float64 to adjoint_rtol.
+ * Synchronises; fills *info if non-NULL. */
 int    nc_solve_adjoint(nc_ctx* ctx, const double* s_dev, const double* rhs_dev, double* lam_dev, nc_info* info);
 
-/* Sensitivities (row a12): dfdgamma_e = -lambda_e^T dR_e/dgamma_e through RAMP, then
- * dfdx = F_R^T dfdgamma.  dfdx_dev [E] (required), dfdgamma_dev [E] (may be NULL). */
+/* Design sensitivities of Sec. 5.1 (the adjoint method; the explicit df/dgamma term is
+ * zero for the flux objective): dfdgamma_e = -lambda_e^T dR_e/dgamma_e through the RAMP
+ * derivatives of Sec. 5.2, then dfdx = F_R^T dfdgamma (the chain rule through the
+ * density filter).  dfdx_dev [E] (required), dfdgamma_dev [E] (may be NULL).  Enqueue
+ * only. */
 int    nc_sensitivity(nc_ctx* ctx, const double* s_dev, const double* lam_dev, double* dfdx_dev, double* dfdgamma_dev);
 
 /* Optional per-context timing of the solver's kernels with HIP events on the context's
@@ -177,8 +208,8 @@ int    nc_sensitivity(nc_ctx* ctx, const double* s_dev, const double* lam_dev, d
 int    nc_set_timing(nc_ctx* ctx, int enable);
 int    nc_get_timing(nc_ctx* ctx, double* ms, long* counts, double* bytes, int n);
 
-/* One application of the multigrid preconditioner of the (P, T) Krylov solves (rows
- * a3, a6; the paper leaves the preconditioner to its references): the hierarchy is
+/* One application of the multigrid preconditioner of the (P, T) Krylov solves (the
+ * paper's F-GMRES of Sec. 5.4 leaves the preconditioner to its references): the hierarchy is
  * rebuilt at the linearisation state s_dev [N][5] (state injection, node-block
  * inverses, coarsest inverse), then z = M^-1 v, or M^-T v when transpose != 0, by one
  * V-cycle in the working precision.  v_dev, z_dev: [N][2] float64 (P, T) pairs; the
@@ -186,8 +217,11 @@ int    nc_get_timing(nc_ctx* ctx, double* ms, long* counts, double* bytes, int n
  * Enqueue only. */
 int    nc_precondition(nc_ctx* ctx, int transpose, const double* s_dev, const double* v_dev, double* z_dev);
 
-/* Stand-alone cone filter on an nx*ny*nz element grid (y = F_R x, or F_R^T x when
- * transpose != 0); used to build filtered designs.  Enqueued on stream. */
+/* Stand-alone cone density filter (Sec. 5.1 regularises the design by filtering; the
+ * normalised cone weights max(0, R - |c_e - c_j| / h)) on an nx*ny*nz element grid:
+ * y = F_R x.  transpose != 0 with radius > 0 is NC_EINVAL here (the transpose needs a
+ * temporary; nc_sensitivity applies it).  Used to build filtered designs.  Enqueued on
+ * stream. */
 int    nc_cone_filter(int nx, int ny, int nz, double radius, const double* x_dev, double* y_dev, int transpose, void* stream);
 
 /* Coarsest-grid solve of the multigrid preconditioner, exposed on its own (the paper
@@ -200,6 +234,7 @@ int    nc_cone_filter(int nx, int ny, int nz, double radius, const double* x_dev
  * zero pivot) leaves non-finite entries; nothing is checked on the device.  NC_EINVAL for
  * a bad n or NULL pointer.  Enqueued on stream. */
 int    nc_dense_inverse(double* a_dev, int n, int* iwork_dev, double* dwork_dev, void* stream);
+
 
 #ifdef __cplusplus
 }

@@ -58,6 +58,7 @@ enum TimerClass {
   TC_COARSE, TC_MDOT, TC_MAXPY, TC_VECTOR, TC_SETUP, TC_SMOOTH_COARSE, TC_PT_RESID_COARSE, TC_COUNT
 };
 constexpr int TIMER_EVENTS = 8192;
+constexpr int SETUP_REC = 8;   // hierarchy rebuilds timed before the event pool is drained
 
 inline void ck(hipError_t e) {
   if (e != hipSuccess) throw HipError{e};
@@ -92,6 +93,11 @@ struct nc_ctx {
   hipStream_t side, side2;
   hipEvent_t fork, join, join2;
   bool join_pending, join2_pending;
+  // device time of the hierarchy rebuilds of one solve call (nc_info.t_setup): per
+  // rebuild a start event on stream and an end event on each of the three streams
+  hipEvent_t setup_ev[SETUP_REC][4];
+  int setup_used;
+  double setup_s;
   // Krylov space in the working precision
   void *V, *Z, *kx, *kb;
   // reductions
@@ -296,6 +302,22 @@ void join_levels(nc_ctx* c) {
   c->join2_pending = false;
 }
 
+// Adds the device time of the recorded hierarchy rebuilds to setup_s (each rebuild: from
+// its start on stream to the last of its three streams' ends) and frees the event slots.
+void setup_drain(nc_ctx* c) {
+  for (int r = 0; r < c->setup_used; ++r) {
+    float worst = 0.f;
+    for (int k = 1; k < 4; ++k) {
+      ck(hipEventSynchronize(c->setup_ev[r][k]));
+      float ms = 0.f;
+      ck(hipEventElapsedTime(&ms, c->setup_ev[r][0], c->setup_ev[r][k]));
+      worst = std::max(worst, ms);
+    }
+    c->setup_s += 1e-3 * worst;
+  }
+  c->setup_used = 0;
+}
+
 // ------------------------------------------------------------------ linearisation
 template <typename T>
 void linearize_levels(nc_ctx* c) {
@@ -303,6 +325,9 @@ void linearize_levels(nc_ctx* c) {
   // the injection below overwrites what the previous setup on the side streams read
   join_coarse(c);
   join_levels(c);
+  if (c->setup_used == SETUP_REC) setup_drain(c);
+  hipEvent_t* sev = c->setup_ev[c->setup_used++];
+  ck(hipEventRecord(sev[0], st));
   for (int l = 1; l < c->L; ++l) {
     if (sizeof(T) == 8)
       launch_inject_state<double>(st, c->lev[l - 1].g, c->lev[l].g, c->lev[l - 1].st64, c->lev[l].st64);
@@ -320,6 +345,7 @@ void linearize_levels(nc_ctx* c) {
     ck(hipEventRecord(c->join2, c->side2));
     c->join2_pending = true;
   }
+  ck(hipEventRecord(sev[2], c->L > 1 ? c->side2 : st));
   if (c->dense) {
     ck(hipStreamWaitEvent(c->side, c->fork, 0));
     { Timed tm(c, TC_SETUP); launch_coarse_assemble<T>(c->side, view<T>(c, c->L - 1), c->emats, c->A); }
@@ -328,10 +354,12 @@ void linearize_levels(nc_ctx* c) {
     ck(hipEventRecord(c->join, c->side));
     c->join_pending = true;
   }
+  ck(hipEventRecord(sev[3], c->dense ? c->side : st));
   {
     Timed tm(c, TC_SETUP);
     launch_diag_inverse<T>(st, view<T>(c, 0), (T*)c->lev[0].dinv, true);
   }
+  ck(hipEventRecord(sev[1], st));
 }
 
 // Packs the (P, T) state used by the Jacobian applies; with `levels` also rebuilds the
@@ -726,6 +754,10 @@ int newton(nc_ctx* c, double* s, nc_info* info) {
   // row scales (the same root; the scaling keeps the small pressure rows visible)
   double rn = scaled_norm(c, c->R);
   if (!std::isfinite(rn)) return NC_ENAN;
+  if (info) {
+    for (int f = 0; f < 5; ++f) info->res0[f] = c->hbuf[f];   // per-field norms fetched by scaled_norm
+    info->hist_len = 0;
+  }
   const double lin_rtol = c->mixed ? p.krylov_rtol_mixed : p.krylov_rtol;
   int status = NC_NOT_CONVERGED;
   int kits = 0, it = 0;
@@ -777,11 +809,14 @@ int newton(nc_ctx* c, double* s, nc_info* info) {
     // is needed
     const bool predicted = relres <= 10.0 * lin_rtol && std::max(relres, step_pt) * step_pt <= p.newton_step_rtol;
     double lam = 1.0, rt = scaled_from(c, c->hbuf + 16);
+    double fres[5];   // per-field norms of the accepted trial's residual
+    for (int f = 0; f < 5; ++f) fres[f] = c->hbuf[16 + f];
     while (true) {
       if (lam < 1.0) {
         launch_axpy(st, -lam, c->d, s, c->strial, c->n5);
         { Timed tm(c, TC_RESIDUAL, 8.0 * (10 * nn(L0.g) + 2 * ne(L0.g))); launch_residual(st, L0.g, L0.c64, c->patch, L0.coef64, c->strial, c->tmp5); }
         rt = scaled_norm(c, c->tmp5);
+        for (int f = 0; f < 5; ++f) fres[f] = c->hbuf[f];
       }
       if (!std::isfinite(rt)) return NC_ENAN;
       if (rt <= rn || rt <= floor || tiny || lam < 1.0 / 64) break;
@@ -789,6 +824,11 @@ int newton(nc_ctx* c, double* s, nc_info* info) {
     }
     ck(hipMemcpyAsync(s, c->strial, sizeof(double) * c->n5, hipMemcpyDeviceToDevice, st));
     std::swap(c->R, c->tmp5);
+    if (info && info->hist_len < NC_HIST_MAX) {
+      info->hist_krylov[info->hist_len] = its;
+      for (int f = 0; f < 5; ++f) info->hist_res[info->hist_len][f] = fres[f];
+      ++info->hist_len;
+    }
     const double rn_prev = rn;
     rn = rt;
     // converged: a full step below the step tolerance in every field, a residual at the
@@ -828,6 +868,14 @@ int adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info*
   launch_mask_state(st, L0.g, c->ra);
   const double bn = scaled_norm(c, c->ra);
   if (!std::isfinite(bn)) return NC_ENAN;
+  if (info) {
+    for (int f = 0; f < 5; ++f) info->res0[f] = c->hbuf[f];
+    for (int f = 0; f < 5; ++f) info->res[f] = c->hbuf[f];
+    info->hist_len = 0;
+    info->newton_its = info->krylov_its = info->refine_its = 0;
+    info->levels = c->L;
+    info->rel_res = bn == 0.0 ? 0.0 : 1.0;
+  }
   ck(hipMemsetAsync(lam, 0, sizeof(double) * c->n5, st));
   if (bn == 0.0) return NC_OK;
   const double lin_rtol = c->mixed ? p.krylov_rtol_mixed : std::min(p.krylov_rtol, p.adjoint_rtol);
@@ -864,6 +912,11 @@ int adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info*
     }
     rel = scaled_from(c, c->hbuf + 16) / bn;
     if (!std::isfinite(rel)) return NC_ENAN;
+    if (info && info->hist_len < NC_HIST_MAX) {
+      info->hist_krylov[info->hist_len] = its;
+      for (int f = 0; f < 5; ++f) info->hist_res[info->hist_len][f] = c->hbuf[16 + f];
+      ++info->hist_len;
+    }
     // converged when the (row-scaled) residual is small and one preconditioner application
     // predicts a per-field relative error below the same tolerance; when refinement stops
     // gaining (round-off floor) the error estimate alone decides
@@ -964,6 +1017,9 @@ static void release(nc_ctx* c) {
     }
   for (hipEvent_t e : {c->fork, c->join, c->join2})
     if (e) (void)hipEventDestroy(e);
+  for (auto& r : c->setup_ev)
+    for (hipEvent_t e : r)
+      if (e) (void)hipEventDestroy(e);
   for (auto& e : c->ev) (void)hipEventDestroy(e);
   for (auto& e : c->kev)
     if (e) (void)hipEventDestroy(e);
@@ -1000,7 +1056,13 @@ int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stre
     c->side = c->side2 = nullptr;
     c->fork = c->join = c->join2 = nullptr;
     c->hslots = c->hbuf = nullptr;
+    c->setup_used = 0;
+    c->setup_s = 0.0;
+    for (auto& r : c->setup_ev)
+      for (hipEvent_t& e : r) e = nullptr;
     bool ok = true;
+    for (auto& r : c->setup_ev)
+      for (hipEvent_t& e : r) ok = ok && hipEventCreate(&e) == hipSuccess;
     for (auto& e : c->kev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking) == hipSuccess;
@@ -1109,9 +1171,17 @@ int nc_solve_state(nc_ctx* c, double* s, nc_info* info) {
   if (!c || !s || !c->design_set) return NC_EINVAL;
   return guarded([&]() {
     const double t0 = now();
+    c->setup_s = 0.0;
+    c->setup_used = 0;   // rebuilds recorded by earlier calls are not this call's
+    if (info) std::memset(info, 0, sizeof(*info));
     const int r = newton(c, s, info);
     sync(c);
-    if (info) info->t_total = now() - t0;
+    setup_drain(c);
+    if (info) {
+      info->t_total = now() - t0;
+      info->t_setup = c->setup_s;
+      info->t_solve = info->t_total - info->t_setup;
+    }
     return r;
   });
 }
@@ -1135,9 +1205,17 @@ int nc_solve_adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam,
   if (!c || !s || !rhs || !lam || !c->design_set) return NC_EINVAL;
   return guarded([&]() {
     const double t0 = now();
+    c->setup_s = 0.0;
+    c->setup_used = 0;   // rebuilds recorded by earlier calls are not this call's
+    if (info) std::memset(info, 0, sizeof(*info));
     const int r = adjoint(c, s, rhs, lam, info);
     sync(c);
-    if (info) info->t_total = now() - t0;
+    setup_drain(c);
+    if (info) {
+      info->t_total = now() - t0;
+      info->t_setup = c->setup_s;
+      info->t_solve = info->t_total - info->t_setup;
+    }
     return r;
   });
 }

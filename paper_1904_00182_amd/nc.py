@@ -16,12 +16,14 @@ NC_OK, NC_NOT_CONVERGED = 0, 1
 NC_EINVAL, NC_ENOMEM, NC_EHIP, NC_ENAN = -1, -2, -3, -4
 NC_FP64, NC_MIXED = 0, 1
 NC_DENSE_MAX = 2000   # largest coarsest-grid system inverted densely
+NC_HIST_MAX = 32      # Newton steps / refinement sweeps recorded per solve
 
 EXPORTED = [
     "nc_problem_default", "nc_workspace_bytes", "nc_create", "nc_destroy", "nc_status_string",
     "nc_set_design", "nc_get_gamma", "nc_residual", "nc_linearize", "nc_jac_apply", "nc_jacT_apply",
     "nc_jac_apply_f32", "nc_jacT_apply_f32", "nc_solve_state", "nc_objective", "nc_objective_grad",
-    "nc_solve_adjoint", "nc_sensitivity", "nc_precondition", "nc_cone_filter", "nc_dense_inverse", "nc_set_timing", "nc_get_timing",
+    "nc_solve_adjoint", "nc_sensitivity", "nc_precondition", "nc_cone_filter", "nc_dense_inverse",
+    "nc_set_timing", "nc_get_timing",
 ]
 
 TIMER_CLASSES = ["residual", "jv", "jtw", "smooth", "smooth_T", "pt_residual", "diag", "uproj", "transfer",
@@ -57,12 +59,18 @@ class NCInfo(ctypes.Structure):
     _fields_ = [
         ("newton_its", ctypes.c_int), ("krylov_its", ctypes.c_int), ("refine_its", ctypes.c_int),
         ("levels", ctypes.c_int),
-        ("res", ctypes.c_double * 5), ("rel_res", ctypes.c_double), ("t_total", ctypes.c_double),
+        ("res0", ctypes.c_double * 5), ("res", ctypes.c_double * 5), ("rel_res", ctypes.c_double),
+        ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double), ("t_total", ctypes.c_double),
+        ("hist_len", ctypes.c_int), ("hist_krylov", ctypes.c_int * NC_HIST_MAX),
+        ("hist_res", (ctypes.c_double * 5) * NC_HIST_MAX),
     ]
 
     def as_dict(self):
+        n = self.hist_len
         return {"newton_its": self.newton_its, "krylov_its": self.krylov_its, "refine_its": self.refine_its,
-                "levels": self.levels, "res": list(self.res), "rel_res": self.rel_res, "t_total": self.t_total}
+                "levels": self.levels, "res0": list(self.res0), "res": list(self.res), "rel_res": self.rel_res,
+                "t_setup": self.t_setup, "t_solve": self.t_solve, "t_total": self.t_total,
+                "hist_krylov": list(self.hist_krylov[:n]), "hist_res": [list(self.hist_res[k]) for k in range(n)]}
 
 
 _LIB = None
@@ -310,3 +318,4 @@ def dense_inverse(a, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream(a.device)
     _check(load().nc_dense_inverse(_ptr(buf), n, _ptr(iwork), _ptr(dwork), _stream_handle(st)), "nc_dense_inverse")
     return buf[: n * n].view(n, n), buf[n * n:].view(n, n)
+

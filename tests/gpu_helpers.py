@@ -39,6 +39,37 @@ def rel_fields(a, b):
     return [float(np.linalg.norm(a[:, f] - b[:, f]) / max(np.linalg.norm(b[:, f]), 1e-300)) for f in range(NFIELD)]
 
 
+def field_errors(a, b):
+    """Per field of [N][F] arrays: (relative l2 error, element-wise max|a - b| / max|b|);
+    None for a field that is zero in b (it must then be zero in a as well)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    a = a.reshape(len(a), -1)
+    b = b.reshape(len(b), -1)
+    out = []
+    for f in range(b.shape[1]):
+        nb = np.linalg.norm(b[:, f])
+        if nb == 0.0:
+            assert np.abs(a[:, f]).max() == 0.0, ("field", f, "must be zero")
+            out.append(None)
+            continue
+        d = a[:, f] - b[:, f]
+        out.append((float(np.linalg.norm(d) / nb), float(np.abs(d).max() / np.abs(b[:, f]).max())))
+    return out
+
+
+def check_fields(a, b, tol, what="", max_tol=None):
+    """Asserts relative l2 <= tol and element-wise max|a - b| / max|b| <= max_tol (default
+    tol) in every field that is not identically zero in b; returns the errors."""
+    max_tol = tol if max_tol is None else max_tol
+    errs = field_errors(a, b)
+    for f, e in enumerate(errs):
+        if e is not None:
+            assert e[0] <= tol and e[1] <= max_tol, (what, "field", f, "l2, max", e, "tol", tol, max_tol)
+    print(what, "errors (l2, max) per field:", errs, flush=True)
+    return errs
+
+
 def to_dev(a, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
 

@@ -8,12 +8,14 @@ import torch
 import oracle
 from oracle.problem import NFIELD
 from paper_1904_00182_amd import nc, inputs, workloads
-from gpu_helpers import oracle_params, local_rows, sample_nodes, to_dev, DEV
+from gpu_helpers import oracle_params, oracle_blob_design, local_rows, sample_nodes, check_fields, to_dev, DEV
 
 pytestmark = pytest.mark.gpu
 
-# stated accuracy of mixed-precision results against the float64 solve, per field
-MIXED_BOUND = 1e-8
+# stated accuracy of mixed-precision results against the float64 solve, per field (relative
+# l2 and element-wise max|d| / max|ref|): about ten times the worst error observed at
+# 128x64x128 (the pressure adjoint)
+MIXED_BOUND = 5e-9
 
 FULL = [("cavity64", 1e-11), ("cavity96filtered", 1e-11), ("cavity128mixed", 1e-11)]
 
@@ -22,11 +24,15 @@ FULL = [("cavity64", 1e-11), ("cavity96filtered", 1e-11), ("cavity128mixed", 1e-
 def test_sampled_rows_full_size(name, tol):
     """R(s), J v and J^T w at ~40 sampled nodes (corners, walls, top, pin, patch, random)
     of the full grid, at a random state, against the oracle's element rows there."""
-    p, x, cfg = workloads.config(name, DEV)
-    sol = nc.Solver(p, DEV)
-    sol.set_design(x)
-    gam = sol.gamma().cpu().numpy()
+    p, _, cfg = workloads.config(name, DEV)
+    grid, E = cfg["grid"], p.nx * p.ny * p.nz
+    # the raw design and its filtered density built on the oracle's side
+    x = oracle_blob_design(grid, cfg["seed"]) if cfg["design"] == "blobs" else inputs.noise_design(E, cfg["seed"])
     op = oracle_params(p)
+    gam = oracle.cone_filter_matrix(oracle.Mesh(op), op.filter_radius) @ x
+    sol = nc.Solver(p, DEV)
+    sol.set_design(to_dev(x))
+    assert np.abs(sol.gamma().cpu().numpy() - gam).max() <= 1e-14
     k = oracle.ramp_k(gam, op.k_f, op.k_s, op.q_c)
     kap = oracle.ramp_kappa(gam, op.kappa_f, op.kappa_s, op.q_p)
     N = sol.N
@@ -99,13 +105,15 @@ def test_full_size_solution_properties(name):
     assert abs(total + heat_in) < 1e-9 * heat_in, (total, heat_in)
     flux = np.abs(oracle.patch_flux(oracle.Mesh(oracle_params(p)), oracle_params(p))).max()
     acc = p.newton_step_rtol if p.precision == nc.NC_FP64 else MIXED_BOUND
+    print(name, "max |R_T| / patch flux per node:", np.abs(r[:, 4]).max() / flux, flush=True)
     assert np.abs(r[:, 4]).max() < acc * flux, (np.abs(r[:, 4]).max(), flux)
     assert np.all(np.isfinite(sn))
 
 
 def test_mixed_precision_error_vs_fp64_at_1m_elements():
     """128x64x128, Gr 1e4: the mixed-precision state, adjoint and df/dx agree with the
-    float64 GPU solve to 1e-8 per field (iterative refinement restores float64 accuracy)."""
+    float64 GPU solve to MIXED_BOUND per field, in relative l2 and element by element
+    (iterative refinement restores float64 accuracy)."""
     out = {}
     for name in ("cavity128mixed", "cavity128"):
         p, x, cfg = workloads.config(name, DEV)
@@ -118,11 +126,34 @@ def test_mixed_precision_error_vs_fp64_at_1m_elements():
         out[name] = (s.cpu().numpy(), lam.cpu().numpy(), sol.sensitivity(s, lam).cpu().numpy())
         del sol
         torch.cuda.empty_cache()
-    for a, b in zip(out["cavity128mixed"], out["cavity128"]):
-        a2, b2 = a.reshape(len(a), -1), b.reshape(len(b), -1)
-        for f in range(a2.shape[1]):
-            nb = np.linalg.norm(b2[:, f])
-            if nb > 0:
-                err = np.linalg.norm(a2[:, f] - b2[:, f]) / nb
-                print("mixed vs fp64 field", f, err)
-                assert err < MIXED_BOUND
+    for what, a, b in zip(("state", "adjoint", "dfdx"), out["cavity128mixed"], out["cavity128"]):
+        check_fields(a, b, MIXED_BOUND, "mixed vs fp64 " + what)
+
+
+def test_cavity64_fp64_solve_with_four_levels():
+    """64x32x64 float64 Newton-FGMRES with the 4-level multigrid of its workload: converged,
+    discrete energy balance, and the same state and adjoint as the solve with the
+    automatically chosen depth (5 levels here) to 1e-9 per field."""
+    res = {}
+    for levels in (4, 0):
+        p, x, cfg = workloads.config("cavity64", DEV)
+        p.levels = levels
+        sol = nc.Solver(p, DEV)
+        sol.set_design(x)
+        s = sol.solve_state()
+        info = dict(sol.last_info)
+        assert info["status"] == nc.NC_OK, info
+        lam = sol.solve_adjoint(s, sol.objective_grad())
+        ainfo = dict(sol.last_info)
+        assert ainfo["status"] == nc.NC_OK, ainfo
+        print("levels", info["levels"], "newton", info["newton_its"], "state its", info["krylov_its"],
+              "adjoint its", ainfo["krylov_its"], flush=True)
+        if levels:
+            assert info["levels"] == levels
+        sn = s.cpu().numpy()
+        total, heat_in = _energy_balance(p, sol.gamma().cpu().numpy(), sn)
+        assert abs(total + heat_in) < 1e-9 * heat_in, (total, heat_in)
+        res[levels] = (sn, lam.cpu().numpy())
+        del sol
+    check_fields(res[4][0], res[0][0], 1e-9, "state 4 vs auto levels")
+    check_fields(res[4][1], res[0][1], 1e-9, "adjoint 4 vs auto levels")

@@ -6,7 +6,7 @@ import torch
 
 import oracle
 from paper_1904_00182_amd import nc, inputs, workloads
-from gpu_helpers import oracle_params, oracle_blob_design, random_state, rel_fields, to_dev, DEV
+from gpu_helpers import oracle_params, oracle_blob_design, random_state, check_fields, to_dev, DEV
 
 pytestmark = pytest.mark.gpu
 
@@ -39,17 +39,17 @@ def test_residual_and_jacobian_applies(grid, gr, radius, Q):
     g = sol.gamma().cpu().numpy()
     assert np.max(np.abs(g - m.gamma)) < 1e-14
     r = sol.residual(to_dev(s)).cpu().numpy()
-    assert max(rel_fields(r, m.residual(s))) < 1e-12
+    check_fields(r, m.residual(s), 1e-12, "residual")
     J = m.jacobian(s)
     sol.linearize(to_dev(s))
     y = sol.jac_apply(to_dev(v)).cpu().numpy()
-    assert max(rel_fields(y, J @ v.reshape(-1))) < 1e-12
+    check_fields(y, (J @ v.reshape(-1)).reshape(-1, 5), 1e-12, "J v")
     y = sol.jac_apply(to_dev(w), transpose=True).cpu().numpy()
-    assert max(rel_fields(y, J.T @ w.reshape(-1))) < 1e-12
+    check_fields(y, (J.T @ w.reshape(-1)).reshape(-1, 5), 1e-12, "J^T w")
     y32 = sol.jac_apply(to_dev(v, torch.float32)).cpu().numpy()
-    assert max(rel_fields(y32, J @ v.reshape(-1))) < 1e-5
+    check_fields(y32, (J @ v.reshape(-1)).reshape(-1, 5), 1e-5, "J v float32", max_tol=2e-5)
     y32 = sol.jac_apply(to_dev(w, torch.float32), transpose=True).cpu().numpy()
-    assert max(rel_fields(y32, J.T @ w.reshape(-1))) < 1e-5
+    check_fields(y32, (J.T @ w.reshape(-1)).reshape(-1, 5), 1e-5, "J^T w float32", max_tol=2e-5)
 
 
 def test_applies_are_bitwise_deterministic():
@@ -83,13 +83,11 @@ def test_state_adjoint_sensitivity_cavity16(precision, tol):
     so, _ = m.solve_state()
     lo = m.solve_adjoint(so, m.dfds())
     go, gx = m.sensitivity(so, lo)
-    errs = rel_fields(s.cpu().numpy(), so)
-    assert max(errs) < tol, errs
-    lerr = rel_fields(lam.cpu().numpy(), lo)
-    assert max(e for f, e in enumerate(lerr) if np.linalg.norm(lo[:, f]) > 0) < tol, lerr
+    check_fields(s.cpu().numpy(), so, tol, "state")
+    check_fields(lam.cpu().numpy(), lo, tol, "adjoint")
     assert np.abs(lam[:, :3].cpu().numpy()).max() == 0.0
-    assert np.linalg.norm(dfdx.cpu().numpy() - gx) / np.linalg.norm(gx) < tol
-    assert np.linalg.norm(dfdg.cpu().numpy() - go) / np.linalg.norm(go) < tol
+    check_fields(dfdx.cpu().numpy(), gx, tol, "dfdx")
+    check_fields(dfdg.cpu().numpy(), go, tol, "dfdgamma")
     assert abs(sol.objective(s) - m.objective(so)) < tol * abs(m.objective(so))
     print("newton", info, "adjoint", sol.last_info)
 
@@ -114,9 +112,40 @@ def test_stress_case_paper_regime(precision):
     assert so[:, 4].max() > 0.5   # the coupled regime: temperature rise of order one
     lo = m.solve_adjoint(so, m.dfds())
     go, gx = m.sensitivity(so, lo)
-    errs = rel_fields(s.cpu().numpy(), so)
-    assert max(errs) < 1e-8, errs
-    lerr = rel_fields(lam.cpu().numpy(), lo)
-    assert max(e for f, e in enumerate(lerr) if np.linalg.norm(lo[:, f]) > 0) < 1e-8, lerr
-    assert np.linalg.norm(dfdx.cpu().numpy() - gx) / np.linalg.norm(gx) < 1e-8
+    check_fields(s.cpu().numpy(), so, 1e-8, "state")
+    check_fields(lam.cpu().numpy(), lo, 1e-8, "adjoint")
+    check_fields(dfdx.cpu().numpy(), gx, 1e-8, "dfdx")
     print("newton", info, "adjoint", sol.last_info)
+
+
+@pytest.mark.parametrize("precision", [nc.NC_FP64, nc.NC_MIXED], ids=["fp64", "mixed"])
+def test_solve_info_history_and_setup_time(precision):
+    """nc_info of a state and an adjoint solve: res0 is the residual of the initial guess
+    (checked against nc_residual), one history entry per Newton step / refinement sweep
+    whose FGMRES counts add up to krylov_its and whose last per-field residual is the
+    final one, and a positive hierarchy-setup time within the call's wall clock."""
+    p = workloads.problem((16, 8, 16), 1e4, precision=precision, q_h=3.0)
+    x = inputs.noise_design(16 * 8 * 16, 2)
+    sol = _solver(p, x)
+    r0 = sol.residual(torch.zeros((sol.N, 5), dtype=torch.float64, device=DEV)).cpu().numpy()
+    s = sol.solve_state()
+    i = dict(sol.last_info)
+    assert i["status"] == nc.NC_OK
+    for f in range(5):
+        assert abs(i["res0"][f] - np.linalg.norm(r0[:, f])) <= 1e-12 * max(np.linalg.norm(r0[:, f]), 1e-300)
+    assert len(i["hist_krylov"]) == i["newton_its"] and sum(i["hist_krylov"]) == i["krylov_its"]
+    assert i["hist_res"][-1] == i["res"]
+    rend = sol.residual(s).cpu().numpy()
+    for f in range(5):
+        assert abs(i["res"][f] - np.linalg.norm(rend[:, f])) <= 1e-10 * max(i["res0"][f], 1e-300)
+    assert 0.0 < i["t_setup"] <= i["t_total"] and abs(i["t_solve"] + i["t_setup"] - i["t_total"]) < 1e-9
+    sol.solve_adjoint(s, sol.objective_grad())
+    a = dict(sol.last_info)
+    assert a["status"] == nc.NC_OK
+    g = sol.objective_grad().cpu().numpy()
+    for f in range(5):
+        assert abs(a["res0"][f] - np.linalg.norm(g[:, f])) <= 1e-14 * max(np.linalg.norm(g[:, f]), 1e-300)
+    assert len(a["hist_krylov"]) == a["refine_its"] and sum(a["hist_krylov"]) == a["krylov_its"]
+    assert a["hist_res"][-1] == a["res"]
+    assert 0.0 <= a["t_setup"] <= a["t_total"]
+    print("state", i, "adjoint", a)

@@ -66,3 +66,31 @@ def test_ctypes_struct_matches_header_fields():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = re.findall(r"\b([a-zA-Z_][a-zA-Z0-9_]*)\s*[,;]", body)
     assert names == [f[0] for f in nc.NCProblem._fields_]
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """sizeof and field offsets of nc_problem and nc_info as the C compiler lays them out
+    from include/nc.h, against the ctypes mirrors of the binding."""
+    import subprocess
+    nc, _ = _lib()
+    fields = {"nc_problem": [f for f, _ in nc.NCProblem._fields_], "nc_info": [f for f, _ in nc.NCInfo._fields_]}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "nc.h"', "int main(void) {"]
+    for st, names in fields.items():
+        src.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
+        for f in names:
+            src.append(f'  printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    src.append("  return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    py = {"nc_problem": nc.NCProblem, "nc_info": nc.NCInfo}
+    seen = 0
+    for line in filter(None, out):
+        st, what, val = line.split()
+        cls = py[st]
+        want = ctypes.sizeof(cls) if what == "size" else getattr(cls, what).offset
+        assert int(val) == want, (st, what, int(val), want)
+        seen += 1
+    assert seen == 2 + sum(len(v) for v in fields.values())
