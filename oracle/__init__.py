@@ -11,7 +11,8 @@ What it computes (all in float64, plain and unblocked):
   (eq. weakstable), with the Darcy velocity of Sec. 2.1 (eq. finaldarcy) and the
   Tezduyar SUPG weight of App. A, assembled element by element;
 * RAMP interpolation of conductivity and permeability (Sec. 5.2,
-  eqs. condRAMP / permRAMP) and a cone density filter;
+  eqs. condRAMP / permRAMP), a cone density filter and the PDE (Helmholtz) density
+  filter of Sec. 5.1, solved directly;
 * a damped Newton iteration (Sec. 5.4) whose Jacobian is assembled from
   complex-step element Jacobians into a SciPy CSR matrix and solved directly
   with SuperLU;
@@ -29,10 +30,11 @@ velocity vanishes (the energy row is then the Galerkin row).
 from .problem import Params, Mesh, default_constraints, patch_flux
 from .material import ramp_k, ramp_kappa, ramp_k_deriv, ramp_kappa_deriv, cone_filter_matrix, kappa_f_tuning
 from .element import element_residual, reference_element
+from .pde_filter import PDEFilter, pde_length_scale
 from .fem import Model
 
 __all__ = [
     "Params", "Mesh", "default_constraints", "patch_flux",
     "ramp_k", "ramp_kappa", "ramp_k_deriv", "ramp_kappa_deriv", "cone_filter_matrix", "kappa_f_tuning",
-    "element_residual", "reference_element", "Model",
+    "element_residual", "reference_element", "Model", "PDEFilter", "pde_length_scale",
 ]

@@ -19,6 +19,7 @@ import scipy.sparse.linalg as spla
 
 from .problem import Mesh, default_constraints, patch_flux, NFIELD, FIELD_P, FIELD_T
 from .material import cone_filter_matrix, ramp_k, ramp_kappa
+from .pde_filter import PDEFilter
 from .element import element_residual
 
 CSTEP = 1.0e-30     # complex-step size: derivative exact to round-off
@@ -30,7 +31,10 @@ class Model:
         gamma = F x feeds RAMP (if `gamma` is given it is used as is, without a filter)."""
         self.prm = prm
         self.mesh = Mesh(prm)
-        self.F = cone_filter_matrix(self.mesh, prm.filter_radius)
+        if prm.filter_kind == "pde" and prm.filter_radius > 0.0:
+            self.F = PDEFilter(self.mesh, prm.filter_radius)         # Sec. 5.1 PDE filter
+        else:
+            self.F = cone_filter_matrix(self.mesh, prm.filter_radius)
         self.x = np.asarray(x, dtype=float)
         self.gamma = np.asarray(gamma, dtype=float) if gamma is not None else self.F @ self.x
         self.k = ramp_k(self.gamma, prm.k_f, prm.k_s, prm.q_c)

@@ -41,7 +41,8 @@ class Params:
     q_h: float = 1.0            # heat flux into the bottom patch
     patch: tuple = (0.375, 0.625, 0.125, 0.375)   # x0, x1, y0, y1 of the bottom heated patch
     Q: float = 0.0              # uniform volumetric heat source
-    filter_radius: float = 0.0  # cone-filter radius in element lengths; 0 = identity
+    filter_radius: float = 0.0  # density-filter radius in element lengths; 0 = identity
+    filter_kind: str = "cone"   # "cone" (normalised hat weights) or "pde" (Helmholtz, Sec. 5.1)
 
     def __post_init__(self):
         if self.h <= 0.0:

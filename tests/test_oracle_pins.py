@@ -497,3 +497,107 @@ def test_supg_velocity_is_the_centroid_velocity():
     scale = np.abs(ref).max()
     assert np.abs(RT[0] - ref).max() < 1e-13 * scale
     assert np.abs(alt_extra).max() > 1e-3 * scale
+
+
+# --------------------------------------------------------------------------- P15
+def _cosine_mode(m, kx, ky, kz):
+    """Element field prod_d cos(theta_d (i_d + 1/2)), theta_d = k_d pi / n_d."""
+    th = np.array([kx * np.pi / m.nx, ky * np.pi / m.ny, kz * np.pi / m.nz])
+    return np.prod(np.cos(th[None, :] * (m.elem_ijk + 0.5)), axis=1), th
+
+
+def _pde_mode_multiplier(th, h, r):
+    """Exact eigenvalue of the discrete PDE filter for a cosine mode.  On a uniform grid
+    with Neumann walls the nodal vectors prod_d cos(theta_d i_d) are eigenvectors of the 1D
+    linear-element stiffness (2/h)(1 - cos theta) and consistent mass (h/3)(2 + cos theta)
+    (the wall rows are half rows of the same stencil), K_F is r^2 (K x M x M + M x K x M
+    + M x M x K) + M x M x M, the element-to-node load of a cosine element field carries
+    h cos(theta/2) per direction and the node-to-element average cos(theta/2), so
+    F x = mu x with mu = prod_d h cos^2(theta_d/2) / (r^2 sum_d k_d prod_(d' != d) m_d'
+    + prod_d m_d)."""
+    k = 2.0 / h * (1.0 - np.cos(th))
+    mm = h / 3.0 * (2.0 + np.cos(th))
+    lam = r * r * (k[0] * mm[1] * mm[2] + mm[0] * k[1] * mm[2] + mm[0] * mm[1] * k[2]) + mm.prod()
+    return np.prod(h * np.cos(th / 2.0) ** 2) / lam
+
+
+@pytest.mark.parametrize("radius", [1.5, 2.5, 6.0])
+def test_pde_filter_cosine_modes(radius):
+    """The PDE (Helmholtz) filter of Sec. 5.1 with r = R h / (2 sqrt 3), consistent mass,
+    Neumann walls: every cosine mode (constant, wall-to-wall, highest) is scaled by its
+    exact discrete multiplier; the constant mode is preserved."""
+    from oracle import PDEFilter
+    p = Params(6, 5, 7)
+    m = Mesh(p)
+    F = PDEFilter(m, radius)
+    r = radius * p.h / (2.0 * np.sqrt(3.0))
+    for kx, ky, kz in [(0, 0, 0), (1, 0, 0), (0, 2, 0), (0, 0, 7), (1, 1, 1), (3, 4, 2), (6, 5, 7), (2, 0, 5)]:
+        x, th = _cosine_mode(m, kx, ky, kz)
+        y = F @ x
+        mu = _pde_mode_multiplier(th, p.h, r)
+        assert np.abs(y - mu * x).max() < 1e-13, (kx, ky, kz)
+        if (kx, ky, kz) == (0, 0, 0):
+            assert abs(mu - 1.0) < 1e-15
+    # a wrong length scale or a lumped mass would change the multipliers
+    x, th = _cosine_mode(m, 2, 1, 3)
+    y = F @ x
+    assert np.abs(y - _pde_mode_multiplier(th, p.h, radius * p.h) * x).max() > 1e-3
+    k = 2.0 / p.h * (1.0 - np.cos(th))
+    lumped = np.prod(p.h * np.cos(th / 2) ** 2) / (r * r * p.h ** 2 * k.sum() + p.h ** 3)
+    assert np.abs(y - lumped * x).max() > 1e-3
+
+
+def test_pde_filter_continuum_limit():
+    """Fixed length scale r, z mode cos(pi z / L) on 1 x 1 x n grids: the filtered field
+    approaches the continuum solution of -r^2 y'' + y = x with Neumann ends,
+    x / (1 + (r pi / L)^2), at second order in h."""
+    from oracle import PDEFilter
+    rr = 0.08
+    errs = []
+    for n in (8, 16, 32, 64):
+        p = Params(1, 1, n, h=1.0 / n)
+        m = Mesh(p)
+        R = rr * 2 * np.sqrt(3) / p.h                           # radius in element lengths
+        x, _ = _cosine_mode(m, 0, 0, 1)
+        y = PDEFilter(m, R) @ x
+        zc = (m.elem_ijk[:, 2] + 0.5) * p.h
+        exact = np.cos(np.pi * zc) / (1 + (rr * np.pi) ** 2)
+        errs.append(np.abs(y - exact).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.9), (errs, rates)
+
+
+def test_pde_filter_constants_and_symmetry():
+    from oracle import PDEFilter
+    p = Params(7, 4, 5)
+    m = Mesh(p)
+    F = PDEFilter(m, 2.5)
+    assert np.abs(F @ np.ones(m.n_elems) - 1.0).max() < 1e-14
+    a = rng(41).standard_normal(m.n_elems)
+    b = rng(42).standard_normal(m.n_elems)
+    assert abs((F @ a) @ b - a @ (F @ b)) < 1e-14 * np.abs(a).sum() * np.abs(b).max()
+    # smoothing: the filtered field has a smaller spread than the input
+    assert (F @ a).std() < 0.8 * a.std()
+
+
+def test_adjoint_gradient_through_pde_filter_vs_brute_force_fd():
+    """df/dx through the adjoint, RAMP and the PDE filter (R = 2.5) against central finite
+    differences of f(x) from full Newton solves on an 8x4x8 cavity."""
+    p = Params(8, 4, 8, alpha=1e3, q_h=80.0, filter_radius=2.5, filter_kind="pde")
+    m = Mesh(p)
+    x = noise_design(m.n_elems, 3)
+    model = Model(p, x)
+    s, _ = model.solve_state()
+    lam = model.solve_adjoint(s, model.dfds())
+    _, dfdx = model.sensitivity(s, lam)
+    eps = 1e-5
+    for j in rng(8).choice(m.n_elems, 10, replace=False):
+        vals = []
+        for sgn in (1, -1):
+            xx = x.copy()
+            xx[j] += sgn * eps
+            mm = Model(p, xx)
+            ss, _ = mm.solve_state(s0=s)
+            vals.append(mm.objective(ss))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert abs(fd - dfdx[j]) <= 1e-6 * np.abs(dfdx).max() + 1e-6 * abs(dfdx[j]), (j, fd, dfdx[j])
