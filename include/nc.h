@@ -235,6 +235,18 @@ int    nc_cone_filter(int nx, int ny, int nz, double radius, const double* x_dev
  * a bad n or NULL pointer.  Enqueued on stream. */
 int    nc_dense_inverse(double* a_dev, int n, int* iwork_dev, double* dwork_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): nc_dense_inverse without the two
+ * scratch arguments.  The pivot rows and step columns live in a library-owned static
+ * device buffer of NC_DENSE_NOALLOC_SCRATCH bytes per GPU (enough for n = NC_DENSE_MAX),
+ * held until the process ends; nothing is allocated.  The buffer of the device current
+ * at the call is used, so stream must belong to that device.  Every call on one GPU
+ * shares that buffer and leaves its contents behind: calls that overlap on one GPU
+ * (other streams, other threads) race and must be ordered by the caller.  Results are
+ * those of nc_dense_inverse.  NC_EINVAL for n outside [1, NC_DENSE_MAX] or a NULL a_dev;
+ * NC_EHIP if the buffer's device address cannot be obtained.  Enqueued on stream. */
+#define NC_DENSE_NOALLOC_SCRATCH 49152
+int    nc_dense_inverse_noalloc(double* a_dev, int n, void* stream);
 
 #ifdef __cplusplus
 }

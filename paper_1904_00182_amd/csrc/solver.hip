@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -966,6 +967,34 @@ double now() {
 
 }  // namespace
 
+// ------------------------------------------------------------------ static scratch
+// Scratch of nc_dense_inverse_noalloc: 2 n doubles (step columns), then 2 n ints (pivot
+// rows), for n up to NC_DENSE_MAX.  Each GPU holds its own copy until the process ends.
+static_assert(2 * NC_DENSE_MAX * (sizeof(double) + sizeof(int)) <= NC_DENSE_NOALLOC_SCRATCH, "scratch too small");
+static __device__ __align__(256) unsigned char scratch[NC_DENSE_NOALLOC_SCRATCH];
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per device (host code
+// must not pass the array's name itself: on the host it is only a stand-in symbol).
+unsigned char* scratch_ptr() {
+  static std::mutex mu;
+  static std::vector<unsigned char*> ptrs;
+  int dev = 0;
+  ck(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)ptrs.size() <= dev) ptrs.resize(dev + 1, nullptr);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    ck(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw HipError{hipErrorInvalidSymbol};
+    ptrs[dev] = (unsigned char*)p;
+  }
+  return ptrs[dev];
+}
+
+}  // namespace
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -1295,6 +1324,20 @@ int nc_precondition(nc_ctx* c, int transpose, const double* s, const double* v, 
 int nc_dense_inverse(double* a, int n, int* iwork, double* dwork, void* stream) {
   if (n < 1 || n > NC_DENSE_MAX || !a || !iwork || !dwork) return NC_EINVAL;
   return guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    launch_gauss_jordan(st, a, n, iwork, dwork);
+    launch_dense_transpose(st, a, a + (size_t)n * n, n);
+    ck(hipGetLastError());
+    return NC_OK;
+  });
+}
+
+int nc_dense_inverse_noalloc(double* a, int n, void* stream) {
+  if (n < 1 || n > NC_DENSE_MAX || !a) return NC_EINVAL;
+  return guarded([&]() {
+    unsigned char* base = scratch_ptr();
+    double* dwork = (double*)base;
+    int* iwork = (int*)(base + 2 * (size_t)NC_DENSE_MAX * sizeof(double));
     hipStream_t st = (hipStream_t)stream;
     launch_gauss_jordan(st, a, n, iwork, dwork);
     launch_dense_transpose(st, a, a + (size_t)n * n, n);

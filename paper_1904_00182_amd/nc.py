@@ -23,7 +23,7 @@ EXPORTED = [
     "nc_set_design", "nc_get_gamma", "nc_residual", "nc_linearize", "nc_jac_apply", "nc_jacT_apply",
     "nc_jac_apply_f32", "nc_jacT_apply_f32", "nc_solve_state", "nc_objective", "nc_objective_grad",
     "nc_solve_adjoint", "nc_sensitivity", "nc_precondition", "nc_cone_filter", "nc_dense_inverse",
-    "nc_set_timing", "nc_get_timing",
+    "nc_dense_inverse_noalloc", "nc_set_timing", "nc_get_timing",
 ]
 
 TIMER_CLASSES = ["residual", "jv", "jtw", "smooth", "smooth_T", "pt_residual", "diag", "uproj", "transfer",
@@ -107,6 +107,7 @@ def load():
             "nc_sensitivity": (I, [V, V, V, V, V]),
             "nc_cone_filter": (I, [I, I, I, D, V, V, I, V]),
             "nc_dense_inverse": (I, [V, I, V, V, V]),
+            "nc_dense_inverse_noalloc": (I, [V, I, V]),
             "nc_set_timing": (I, [V, I]),
             "nc_get_timing": (I, [V, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D), I]),
         }
@@ -319,3 +320,13 @@ def dense_inverse(a, stream=None):
     _check(load().nc_dense_inverse(_ptr(buf), n, _ptr(iwork), _ptr(dwork), _stream_handle(st)), "nc_dense_inverse")
     return buf[: n * n].view(n, n), buf[n * n:].view(n, n)
 
+
+def dense_inverse_noalloc(buf, n, stream=None):
+    """In-place nc_dense_inverse_noalloc on a float64 device buffer of 2 n^2 entries whose
+    first n^2 hold A: afterwards they hold A^-1 and the next n^2 (A^-1)^T.  No device
+    memory is allocated (the library's static scratch is used)."""
+    if buf.dtype != torch.float64 or buf.numel() < 2 * n * n or not buf.is_contiguous():
+        raise ValueError("dense_inverse_noalloc needs a contiguous float64 buffer of 2 n^2 entries")
+    st = stream if stream is not None else torch.cuda.current_stream(buf.device)
+    _check(load().nc_dense_inverse_noalloc(_ptr(buf), n, _stream_handle(st)), "nc_dense_inverse_noalloc")
+    return buf

@@ -68,6 +68,13 @@ def test_ctypes_struct_matches_header_fields():
     assert names == [f[0] for f in nc.NCProblem._fields_]
 
 
+def test_noalloc_entry_point_rejects_bad_sizes():
+    nc, lib = _lib()
+    for n in (0, -1, nc.NC_DENSE_MAX + 1):
+        assert lib.nc_dense_inverse_noalloc(None, n, None) == nc.NC_EINVAL
+    assert lib.nc_dense_inverse_noalloc(None, 10, None) == nc.NC_EINVAL
+
+
 def test_ctypes_structs_match_the_header(tmp_path):
     """sizeof and field offsets of nc_problem and nc_info as the C compiler lays them out
     from include/nc.h, against the ctypes mirrors of the binding."""
