@@ -26,6 +26,21 @@ def _shape(xi):
     return N, dN
 
 
+def supg_weights(Pe, Te, kap, prm):
+    """Integrated SUPG weights int_e N*_a = int_e (N_a + tau u0 . grad N_a), (E, 8), at
+    the centroid velocity u0 of each element (App. A); complex-safe."""
+    h = prm.h
+    N, G, Nc, Gc, detJ, _ = reference_element(h)
+    buoy = prm.rho0 * prm.alpha * np.array([0.0, 0.0, -prm.g0])
+    gradPc = np.einsum("ad,ea->ed", Gc, Pe)
+    Tc = np.einsum("a,ea->e", Nc, Te)
+    u0 = -(kap / prm.mu)[:, None] * (gradPc + Tc[:, None] * buoy)
+    he2 = 3.0 * h * h
+    tau = (4.0 * np.einsum("ed,ed->e", u0, u0) / he2 + 16.0 / (he2 * he2)) ** (-0.5)
+    Nstar = N[None, :, :] + tau[:, None, None] * np.einsum("ed,qad->eqa", u0, G)
+    return detJ * Nstar.sum(axis=1)
+
+
 def reference_element(h):
     """Gauss points, weights and shape data of a cube of edge h.
 
@@ -45,12 +60,13 @@ def reference_element(h):
     return N, G, nc, dnc * (2.0 / h), h ** 3 / 8.0, xq
 
 
-def element_residual(Pe, Te, Ue, k, kap, prm, src_P=None, src_T=None, x0=None):
+def element_residual(Pe, Te, Ue, k, kap, prm, src_P=None, src_T=None, x0=None, Qe=None):
     """Element rows of R(s) for every element at once.
 
     Pe, Te : (E, 8) nodal modified pressure and temperature
     Ue     : (E, 8, 3) nodal velocity unknowns
     k, kap : (E,) element conductivity and permeability
+    Qe     : optional (E,) volumetric source per element (default: prm.Q everywhere)
     src_P, src_T : optional callables f(x) -> (E, 8) giving volumetric sources at the
              physical Gauss points x (E, 8, 3); x0 (E, 3) is each element's origin.
     Returns RP (E, 8), RT (E, 8), RU (E, 8, 3).
@@ -88,7 +104,8 @@ def element_residual(Pe, Te, Ue, k, kap, prm, src_P=None, src_T=None, x0=None):
     tau = (4.0 * np.einsum("ed,ed->e", u0, u0) / he2 + 16.0 / (he2 * he2)) ** (-0.5)
     Nstar = N[None, :, :] + tau[:, None, None] * np.einsum("ed,qad->eqa", u0, G)
 
-    conv = prm.rho0 * prm.cp * np.einsum("eqd,eqd->eq", uq, gradT) - prm.Q
+    Q = prm.Q if Qe is None else np.asarray(Qe)[:, None]
+    conv = prm.rho0 * prm.cp * np.einsum("eqd,eqd->eq", uq, gradT) - Q
     RP = detJ * np.einsum("qad,eqd->ea", G, -uq)
     RT = detJ * (np.einsum("eqa,eq->ea", Nstar, conv) + k[:, None] * np.einsum("qad,eqd->ea", G, gradT))
     mass = detJ * N.sum(axis=0)                              # lumped element mass per node

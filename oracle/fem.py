@@ -17,10 +17,10 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .problem import Mesh, default_constraints, patch_flux, NFIELD, FIELD_P, FIELD_T
+from .problem import Mesh, default_constraints, patch_flux, element_regions, NFIELD, FIELD_P, FIELD_T
 from .material import cone_filter_matrix, ramp_k, ramp_kappa
 from .pde_filter import PDEFilter
-from .element import element_residual
+from .element import element_residual, supg_weights
 
 CSTEP = 1.0e-30     # complex-step size: derivative exact to round-off
 
@@ -36,11 +36,20 @@ class Model:
         else:
             self.F = cone_filter_matrix(self.mesh, prm.filter_radius)
         self.x = np.asarray(x, dtype=float)
-        self.gamma = np.asarray(gamma, dtype=float) if gamma is not None else self.F @ self.x
+        # passive regions of Sec. 6.1 (heat-source block solid, outside the design domain
+        # fluid) and the volumetric source per element
+        self.Qe, self.solid, self.fluid = element_regions(self.mesh, prm)
+        self.design = ~(self.solid | self.fluid)
+        if gamma is not None:
+            self.gamma = np.asarray(gamma, dtype=float)
+        else:
+            self.gamma = self.F @ self.x
+            self.gamma[self.solid] = 1.0
+            self.gamma[self.fluid] = 0.0
         self.k = ramp_k(self.gamma, prm.k_f, prm.k_s, prm.q_c)
         self.kap = ramp_kappa(self.gamma, prm.kappa_f, prm.kappa_s, prm.q_p)
         if constraints is None:
-            constraints = default_constraints(self.mesh)
+            constraints = default_constraints(self.mesh, prm)
         self.mask, self.sbar = constraints
         self.flux = patch_flux(self.mesh, prm) if flux is None else np.asarray(flux, dtype=float)
         self.src_P, self.src_T = src_P, src_T
@@ -58,7 +67,7 @@ class Model:
         k = self.k if k is None else k
         kap = self.kap if kap is None else kap
         RP, RT, RU = element_residual(v[:, :, FIELD_P], v[:, :, FIELD_T], v[:, :, 0:3], k, kap, self.prm,
-                                      self.src_P, self.src_T, self.x0)
+                                      self.src_P, self.src_T, self.x0, self.Qe)
         out = np.empty(v.shape, dtype=np.result_type(se, k, kap))
         out[:, :, 0:3] = RU
         out[:, :, FIELD_P] = RP
@@ -157,16 +166,65 @@ class Model:
         return s, hist
 
     # ---------------------------------------------------------------- objective / adjoint
-    def objective(self, s):
-        """Thermal compliance with the boundary-flux load: f = f_qh^T t (Sec. 5.1
-        eq. objdiscr with the flux vector in place of f_tQ)."""
-        return float(self.flux @ np.asarray(s).reshape(-1, NFIELD)[:, FIELD_T])
+    def _objective_q(self, s, kap=None):
+        """Volumetric part of the thermal compliance, sum_e f_tQ,e^T t_e (Sec. 5.1
+        eq. objdiscr; f_tQ,e = int N*^T Q of App. A, with the SUPG weight); complex-safe."""
+        s = np.asarray(s).reshape(-1, NFIELD)
+        src = np.nonzero(self.Qe != 0.0)[0]
+        if src.size == 0:
+            return 0.0
+        conn = self.mesh.conn[src]
+        kap = self.kap if kap is None else kap
+        w = supg_weights(s[:, FIELD_P][conn], s[:, FIELD_T][conn], kap[src], self.prm)
+        return np.sum(self.Qe[src][:, None] * w * s[:, FIELD_T][conn])
 
-    def dfds(self):
+    def objective(self, s):
+        """Thermal compliance f = f_qh^T t + sum_e f_tQ,e^T t_e (Sec. 5.1 eq. objdiscr with
+        the volumetric load of App. A, plus the boundary-flux load)."""
+        q = self._objective_q(s)
+        return float(self.flux @ np.asarray(s).reshape(-1, NFIELD)[:, FIELD_T] + np.real(q))
+
+    def dfds(self, s=None):
+        """d f / d s: the flux load on the T entries, plus the derivative of the volumetric
+        part (which depends on P and T through the SUPG weight) by the complex step."""
         g = np.zeros((self.mesh.n_nodes, NFIELD))
         g[:, FIELD_T] = self.flux
+        src = np.nonzero(self.Qe != 0.0)[0]
+        if src.size:
+            if s is None:
+                raise ValueError("the volumetric objective's gradient depends on the state")
+            s = np.asarray(s, dtype=float).reshape(-1, NFIELD)
+            nodes = np.unique(self.mesh.conn[src])
+            for f in (FIELD_P, FIELD_T):
+                for n in nodes:
+                    sc = s.astype(complex)
+                    sc[n, f] += 1j * CSTEP
+                    g[n, f] += self._objective_q(sc).imag / CSTEP
         g[self.mask] = 0.0
         return g
+
+    def dfdgamma_explicit(self, s):
+        """Explicit d f / d gamma_e (the volumetric objective depends on the permeability
+        through the SUPG weight), by the complex step through RAMP, element by element."""
+        out = np.zeros(self.mesh.n_elems)
+        p = self.prm
+        for e in np.nonzero(self.Qe != 0.0)[0]:
+            g = self.gamma.astype(complex)
+            g[e] += 1j * CSTEP
+            kap = ramp_kappa(g, p.kappa_f, p.kappa_s, p.q_p)
+            out[e] = self._objective_q(s, kap).imag / CSTEP
+        return out
+
+    def volume(self):
+        """Volume constraint of Sec. 5.1 (eq. constr): g = sum_D gamma_e v_e / sum_D v_e - g*
+        is returned without g*, as the solid fraction of the design domain D, with its
+        gradient with respect to the raw design x (through the filter; zero off D)."""
+        D = self.design
+        frac = float(self.gamma[D].sum() / D.sum())
+        dg = np.where(D, 1.0 / D.sum(), 0.0)
+        dx = self.F.T @ dg
+        dx[~D] = 0.0
+        return frac, dx
 
     def solve_adjoint(self, s, rhs):
         """Solve J~^T lambda = rhs (rhs zeroed on constrained dofs) with SuperLU."""
@@ -191,10 +249,17 @@ class Model:
         kap = ramp_kappa(g, p.kappa_f, p.kappa_s, p.q_p)
         return self._elem_rows(s[self.ldof].astype(complex), k, kap).imag / CSTEP
 
-    def sensitivity(self, s, lam):
-        """Returns (dfdgamma, dfdx): -lambda_e^T dR_e/dgamma_e per element, and its image
-        under the filter transpose (the design chain gamma = F x)."""
+    def sensitivity(self, s, lam, explicit=False):
+        """Returns (dfdgamma, dfdx): -lambda_e^T dR_e/dgamma_e per element (plus the
+        objective's explicit d f/d gamma_e when `explicit`), zero on passive elements, and
+        its image under the filter transpose (the design chain gamma = F x), zero off the
+        design domain (passive elements are not design variables)."""
         lam = np.asarray(lam, dtype=float).reshape(-1)
         dR = self.elem_dR_dgamma(s)
         dfdg = -np.einsum("ej,ej->e", lam[self.ldof], dR)
-        return dfdg, self.F.T @ dfdg
+        if explicit:
+            dfdg = dfdg + self.dfdgamma_explicit(s)
+        dfdg[~self.design] = 0.0
+        dfdx = self.F.T @ dfdg
+        dfdx[~self.design] = 0.0
+        return dfdg, dfdx

@@ -40,7 +40,13 @@ class Params:
     q_p: float = 8.0
     q_h: float = 1.0            # heat flux into the bottom patch
     patch: tuple = (0.375, 0.625, 0.125, 0.375)   # x0, x1, y0, y1 of the bottom heated patch
-    Q: float = 0.0              # uniform volumetric heat source
+    Q: float = 0.0              # volumetric heat source (on q_box, or everywhere if q_box is None)
+    q_box: tuple = None         # (x0, x1, y0, y1, z0, z1): elements whose centre is inside carry Q
+    solid_box: tuple = None     # passive solid: gamma = 1 on elements whose centre is inside
+    design_box: tuple = None    # design domain; elements outside it (and outside solid_box) are
+                                # passive fluid, gamma = 0.  None: every element is a design element
+    sym_x: bool = False         # the wall x = Lx is a symmetry plane (insulated, u.n = 0), not T = 0
+    sym_y: bool = False         # the wall y = Ly likewise
     filter_radius: float = 0.0  # density-filter radius in element lengths; 0 = identity
     filter_kind: str = "cone"   # "cone" (normalised hat weights) or "pde" (Helmholtz, Sec. 5.1)
 
@@ -80,17 +86,46 @@ class Mesh:
         return i + self.nx * (j + self.ny * k)
 
 
-def default_constraints(mesh: Mesh):
+def in_box(points, box):
+    """Points (n, 3) inside the closed box (x0, x1, y0, y1, z0, z1)."""
+    x0, x1, y0, y1, z0, z1 = box
+    x, y, z = points[:, 0], points[:, 1], points[:, 2]
+    return (x >= x0) & (x <= x1) & (y >= y0) & (y <= y1) & (z >= z0) & (z <= z1)
+
+
+def element_regions(mesh: Mesh, p: Params):
+    """Per element: volumetric source Q_e, passive-solid mask, passive-fluid mask (Sec. 6.1:
+    the heat source block is solid and carries Q, the region outside the design domain is
+    fluid; membership by element centre)."""
+    c = mesh.elem_centre
+    Qe = np.full(mesh.n_elems, p.Q) if p.q_box is None else np.where(in_box(c, p.q_box), p.Q, 0.0)
+    solid = np.zeros(mesh.n_elems, dtype=bool) if p.solid_box is None else in_box(c, p.solid_box)
+    fluid = np.zeros(mesh.n_elems, dtype=bool) if p.design_box is None else ~in_box(c, p.design_box) & ~solid
+    return Qe, solid, fluid
+
+
+def default_constraints(mesh: Mesh, p: Params = None):
     """Dirichlet mask [N, 5] and prescribed values for the cavity of Sec. 6.1.
 
     T = 0 on the vertical walls and the top (the bottom is insulated except for the
     heated patch); the pressure level is fixed by P = 0 at the single top corner node
-    (0, 0, nz), where T is fixed as well.  Velocity is never constrained: it is the
+    (0, 0, nz), where T is fixed as well.  With the quarter domain of Sec. 6.1 the walls
+    x = Lx and y = Ly can be symmetry planes instead (p.sym_x, p.sym_y): insulated, u.n = 0.  Velocity is never constrained: it is the
     lumped projection of the Darcy velocity and the walls carry u.n = 0 naturally.
     """
     i, j, k = mesh.node_ijk[:, 0], mesh.node_ijk[:, 1], mesh.node_ijk[:, 2]
+    sx = p is not None and p.sym_x
+    sy = p is not None and p.sym_y
     mask = np.zeros((mesh.n_nodes, NFIELD), dtype=bool)
-    mask[:, FIELD_T] = (i == 0) | (i == mesh.nx) | (j == 0) | (j == mesh.ny) | (k == mesh.nz)
+    # a symmetry plane is insulated (natural condition), so T stays free there
+    mask[:, FIELD_T] = (i == 0) | ((i == mesh.nx) & (not sx)) | (j == 0) | ((j == mesh.ny) & (not sy)) | (k == mesh.nz)
+    # u.n = 0 on a symmetry plane: the normal velocity is odd across it, so its nodal
+    # projection there (the mean over both sides) is zero; the tangential components are
+    # even, so the one-sided projection is already the mean over both sides
+    if sx:
+        mask[:, 0] = i == mesh.nx
+    if sy:
+        mask[:, 1] = j == mesh.ny
     mask[mesh.node_id(0, 0, mesh.nz), FIELD_P] = True
     values = np.zeros((mesh.n_nodes, NFIELD))
     return mask, values

@@ -601,3 +601,147 @@ def test_adjoint_gradient_through_pde_filter_vs_brute_force_fd():
             vals.append(mm.objective(ss))
         fd = (vals[0] - vals[1]) / (2 * eps)
         assert abs(fd - dfdx[j]) <= 1e-6 * np.abs(dfdx).max() + 1e-6 * abs(dfdx[j]), (j, fd, dfdx[j])
+
+
+# --------------------------------------------------------------------------- P16
+def _benchmark_boxes(L):
+    """Heat-source block and design domain of a cavity of edge L, centred on the floor, as
+    multiples of the element grid used below."""
+    src = (0.375 * L, 0.625 * L, 0.375 * L, 0.625 * L, 0.0, 0.125 * L)
+    des = (0.125 * L, 0.875 * L, 0.125 * L, 0.875 * L, 0.125 * L, 0.875 * L)
+    return src, des
+
+
+def _quarter(box, L):
+    x0, x1, y0, y1, z0, z1 = box
+    return (x0, min(x1, L / 2), y0, min(y1, L / 2), z0, z1)
+
+
+def test_quarter_domain_with_symmetry_planes_equals_full_domain():
+    """Sec. 6.1 solves a quarter of the symmetric cavity with symmetry conditions.  The full
+    8x8x8 cavity with a heat-source block (Q, passive solid), a design domain (passive
+    fluid outside) and a design mirror-symmetric in x and y gives a solution that the 4x4x8
+    quarter with symmetry planes at x = Lx and y = Ly (insulated, u.n = 0) reproduces node
+    for node, adjoint and sensitivities included."""
+    L, n = 1.0, 8
+    src, des = _benchmark_boxes(L)
+    pf = Params(n, n, n, alpha=1e4, kappa_f=0.00206, q_h=0.0, Q=40.0, q_box=src, solid_box=src, design_box=des)
+    x = noise_design(n ** 3, 21).reshape(n, n, n)
+    x = 0.25 * (x + x[:, :, ::-1] + x[:, ::-1, :] + x[:, ::-1, ::-1])
+    mf = Model(pf, x.ravel())
+    sf, _ = mf.solve_state()
+    lf = mf.solve_adjoint(sf, mf.dfds(sf))
+    gf, _ = mf.sensitivity(sf, lf, explicit=True)
+    h = pf.h
+    pq = Params(n // 2, n // 2, n, h=h, alpha=1e4, kappa_f=0.00206, q_h=0.0, Q=40.0, q_box=_quarter(src, L),
+                solid_box=_quarter(src, L), design_box=_quarter(des, L), sym_x=True, sym_y=True)
+    xq = x[:, : n // 2, : n // 2]
+    mq = Model(pq, xq.ravel())
+    assert mq.solid.sum() * 4 == mf.solid.sum() and mq.design.sum() * 4 == mf.design.sum()
+    sq, _ = mq.solve_state()
+    lq = mq.solve_adjoint(sq, mq.dfds(sq))
+    gq, _ = mq.sensitivity(sq, lq, explicit=True)
+    ijk = mq.mesh.node_ijk
+    full_ids = mf.mesh.node_id(ijk[:, 0], ijk[:, 1], ijk[:, 2])
+    for f in range(5):
+        scale = np.abs(sf[:, f]).max()
+        assert np.abs(sq[:, f] - sf[full_ids, f]).max() <= 1e-10 * scale, f
+    for f in (3, 4):
+        assert np.abs(lq[:, f] - lf[full_ids, f]).max() <= 1e-10 * np.abs(lf[:, f]).max(), f
+    e = mq.mesh.elem_ijk
+    full_e = mf.mesh.elem_id(e[:, 0], e[:, 1], e[:, 2])
+    assert np.abs(gq - gf[full_e]).max() <= 1e-9 * np.abs(gf).max()
+    assert abs(4 * mq.objective(sq) - mf.objective(sf)) <= 1e-11 * abs(mf.objective(sf))
+    # the full solution is symmetric, so its normal velocity vanishes on the mirror planes
+    mid = mf.mesh.node_ijk[:, 0] == n // 2
+    assert np.abs(sf[mid, 0]).max() <= 1e-12 * np.abs(sf[:, 0]).max()
+
+
+def test_energy_balance_and_conduction_adjoint_with_source_block():
+    """Heat-source block Q (passive solid), passive fluid outside the design domain,
+    symmetry planes: the heat leaving through the isothermal walls equals Q V_block (the
+    SUPG weights sum to one over an element); and at Gr = 0 (no flow, so N* = N) the
+    compliance sum_e f_tQ,e^T t_e is a symmetric conduction problem, whose adjoint
+    temperature equals the temperature."""
+    L = 1.0
+    src, des = _benchmark_boxes(L)
+    n = 8
+    kw = dict(q_h=0.0, Q=40.0, q_box=_quarter(src, L), solid_box=_quarter(src, L), design_box=_quarter(des, L),
+              sym_x=True, sym_y=True, h=1.0 / n)
+    p = Params(n // 2, n // 2, n, alpha=1e4, kappa_f=0.00206, **kw)
+    m = Model(p, noise_design(n * n * n // 4, 22))
+    s, _ = m.solve_state()
+    Ru = m.residual_unconstrained(s)
+    iso = m.mask[:, 4]
+    vol = (m.Qe != 0).sum() * p.h ** 3
+    assert abs(Ru[iso, 4].sum() + p.Q * vol) <= 1e-11 * p.Q * vol
+    p0 = Params(n // 2, n // 2, n, alpha=0.0, **kw)
+    m0 = Model(p0, noise_design(n * n * n // 4, 22))
+    s0, _ = m0.solve_state()
+    assert np.abs(s0[:, 3]).max() < 1e-14
+    lam = m0.solve_adjoint(s0, m0.dfds(s0))
+    assert rel(lam[:, 4], s0[:, 4]) < 1e-12
+    # and the compliance is then the plain Galerkin load times T
+    N, _, _, _, detJ, _ = reference_element(p0.h)
+    Te = s0[:, 4][m0.mesh.conn]
+    fq = np.sum(m0.Qe[:, None] * detJ * N.sum(axis=0)[None, :] * Te)
+    assert abs(m0.objective(s0) - fq) <= 1e-13 * abs(fq)
+
+
+def test_source_objective_gradient_vs_brute_force_fd():
+    """The volumetric compliance of Sec. 5.1 on the quarter cavity with passive regions and
+    symmetry planes: df/dx from the adjoint (with the SUPG-dependent d f/d s and the explicit
+    d f/d gamma) against central differences of f(x) from full Newton solves; passive
+    elements have zero sensitivity."""
+    L = 1.0
+    src, des = _benchmark_boxes(L)
+    n = 8
+    p = Params(n // 2, n // 2, n, h=1.0 / n, alpha=1e4, kappa_f=0.00206, q_h=0.0, Q=400.0, q_box=_quarter(src, L),
+               solid_box=_quarter(src, L), design_box=_quarter(des, L), sym_x=True, sym_y=True,
+               filter_radius=1.5)
+    m = Model(p, noise_design(n * n * n // 4, 23))
+    x = m.x
+    s, _ = m.solve_state()
+    lam = m.solve_adjoint(s, m.dfds(s))
+    _, dfdx = m.sensitivity(s, lam, explicit=True)
+    assert np.all(dfdx[~m.design] == 0.0)
+    eps = 1e-5
+    design_ids = np.nonzero(m.design)[0]
+    for j in rng(9).choice(design_ids, 10, replace=False):
+        vals = []
+        for sgn in (1, -1):
+            xx = x.copy()
+            xx[j] += sgn * eps
+            mm = Model(p, xx)
+            ss, _ = mm.solve_state(s0=s)
+            vals.append(mm.objective(ss))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert abs(fd - dfdx[j]) <= 1e-6 * np.abs(dfdx).max() + 1e-6 * abs(dfdx[j]), (j, fd, dfdx[j])
+    # the explicit term matters: leaving it out changes the gradient of a source element's
+    # neighbourhood only through passive (zeroed) elements here, so check it on its own
+    ex = m.dfdgamma_explicit(s)
+    assert np.all(ex[m.Qe == 0] == 0.0) and np.abs(ex).max() > 0
+
+
+def test_source_objective_uses_the_residual_source_load():
+    """eq. objdiscr takes f_tQ of App. A, the same N*-weighted load that the energy rows
+    subtract: at any state, -(R(s; Q) - R(s; 0)) restricted to the T rows, dotted with t,
+    is the volumetric compliance (R is affine in Q).  Together with the pins of the SUPG
+    weight this fixes the objective's weights."""
+    L = 1.0
+    src, des = _benchmark_boxes(L)
+    n = 8
+    kw = dict(h=1.0 / n, alpha=1e4, kappa_f=0.00206, q_h=0.0, q_box=_quarter(src, L), solid_box=_quarter(src, L),
+              design_box=_quarter(des, L), sym_x=True, sym_y=True)
+    x = noise_design(n * n * n // 4, 24)
+    mQ = Model(Params(n // 2, n // 2, n, Q=40.0, **kw), x)
+    m0 = Model(Params(n // 2, n // 2, n, Q=0.0, **kw), x)
+    s = 0.02 * rng(25).standard_normal((mQ.mesh.n_nodes, NFIELD))
+    s[:, FIELD_P] *= 50.0
+    load = -(mQ.residual_unconstrained(s)[:, FIELD_T] - m0.residual_unconstrained(s)[:, FIELD_T])
+    f = mQ.objective(s)
+    assert abs(load @ s[:, FIELD_T] - f) <= 1e-12 * np.abs(load).sum() * np.abs(s[:, FIELD_T]).max()
+    # the SUPG part of the load is not negligible at this state
+    N, _, _, _, detJ, _ = reference_element(kw["h"])
+    galerkin = np.sum(mQ.Qe[:, None] * detJ * N.sum(axis=0)[None, :] * s[:, FIELD_T][mQ.mesh.conn])
+    assert abs(f - galerkin) > 1e-6 * abs(f)
