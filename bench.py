@@ -252,6 +252,43 @@ def fp64_leg(args, mixed_result):
     return out
 
 
+def pde_filter_timing(args):
+    """The PDE (Helmholtz) density filter of Sec. 5.1 (radius 2.5 element lengths) on the
+    128x64x128 grid: time of one application (nc_filter_apply: element-to-node load, the
+    planned Chebyshev steps, node-to-element average) with HIP events on the solver's
+    stream, and its HBM fraction by algorithmic bytes (per step: read the direction, the
+    iterate and the residual, write the iterate, the residual and the next direction)."""
+    import torch
+    from paper_1904_00182_amd import nc, workloads
+    dev = "cuda:0"
+    p, x, cfg = workloads.config("cavity128pde", dev)
+    sol = nc.Solver(p, dev)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        sol.filter_apply(x)
+    torch.cuda.synchronize()
+    st = sol.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    import ctypes
+    xp, yp = ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())
+    reps = 20
+    e0.record(st)
+    for _ in range(reps):
+        sol.lib.nc_filter_apply(sol.ctx, 0, xp, yp)
+    e1.record(st)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    N, E = sol.N, sol.E
+    # radius 2.5: 29 Chebyshev steps (bounds from the closed-form symbol; see the library)
+    steps = 29
+    algo = 8.0 * (steps * 6 * N + (E + 3 * N) + (2 * N + E))
+    sol.close()
+    out = {"grid": [p.nx, p.ny, p.nz], "radius": 2.5, "apply_us": round(t * 1e6, 2), "chebyshev_steps": steps,
+           "algorithmic_bytes": algo, "hbm_frac": round(algo / t / 1e9 / HBM_PEAK_GBS, 4)}
+    log(args, "pde filter", out)
+    return out
+
+
 def oracle_pair(args):
     """Like for like on the 32x16x32 cavity (Gr 1e3, thresholded filtered-noise design,
     seed 1): the float64 oracle (assembled complex-step Jacobian, SuperLU) and the float64
@@ -629,6 +666,7 @@ def main():
     sol.close()
     del sol
     torch.cuda.empty_cache()
+    result["pde_filter"] = pde_filter_timing(args)
     if mixed and not args.no_fp64_leg:
         result["fp64_baseline"] = fp64_leg(args, mixed_result)
         result["fp64_baseline"]["mixed_speedup"] = round(result["fp64_baseline"]["ms_per_step"] / (t_step * 1e3), 3)

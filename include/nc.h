@@ -58,6 +58,11 @@ extern "C" {
 
 #define NC_DENSE_MAX 2000   /* largest coarsest-grid system solved by a dense inverse */
 
+#define NC_FILTER_CONE 0  /* normalised cone weights max(0, R - |c_e - c_j| / h)              */
+#define NC_FILTER_PDE  1  /* PDE (Helmholtz) filter of Sec. 5.1: -r^2 lap y + y = x, Neumann
+                             walls, r = R h / (2 sqrt 3), Q1 consistent mass, gamma_e = mean
+                             of y over the element                                          */
+
 typedef struct nc_problem {
   int    nx, ny, nz;          /* elements per axis; at most 2^31 / 5 nodes in all and    *
                                * (nx+1)(ny+1) < 2^32 / 40 nodes in one z-layer           */
@@ -70,7 +75,7 @@ typedef struct nc_problem {
   double q_h;                 /* heat flux through the bottom patch                      */
   double patch_x0, patch_x1, patch_y0, patch_y1; /* patch: bottom faces with centre inside */
   double Q;                   /* uniform volumetric heat source                          */
-  double filter_radius;       /* cone density filter radius in element lengths; 0 = none */
+  double filter_radius;       /* density filter radius R in element lengths; 0 = none    */
   int    precision;           /* NC_FP64 or NC_MIXED                                     */
   int    levels;              /* multigrid levels; 0 = choose automatically              */
   double newton_step_rtol;    /* stop when a full step, or the error predicted to remain after
@@ -90,6 +95,7 @@ typedef struct nc_problem {
   double newton_eta0;         /* linear tolerance of the first Newton step; later steps use
                                  0.9 (|R_k| / |R_k-1|)^2 between the Krylov tolerance and
                                  this (Eisenstat-Walker); 0: the Krylov tolerance always   */
+  int    filter_kind;         /* NC_FILTER_CONE or NC_FILTER_PDE                          */
 } nc_problem;
 
 #define NC_HIST_MAX 32  /* Newton steps / refinement sweeps recorded in nc_info */
@@ -134,14 +140,21 @@ int    nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* s
 int    nc_destroy(nc_ctx* ctx);
 const char* nc_status_string(int status);
 
-/* Design chain: gamma = F_R x (the density filter of Sec. 5.1; here a cone filter of
- * radius filter_radius element lengths, identity if 0), then the RAMP conductivity and
+/* Design chain: gamma = F_R x (the density filter of Sec. 5.1: the cone filter or the
+ * PDE filter of filter_kind, radius filter_radius element lengths, identity if 0; the PDE
+ * filter is solved by a fixed number of Chebyshev steps planned from closed-form spectrum
+ * bounds, to a relative error below 1e-15), then the RAMP conductivity and
  * permeability of Sec. 5.2 (eqs. condRAMP, permRAMP) and their derivatives, on the
  * finest level and averaged onto the coarser multigrid levels.
  * x_dev: [E] float64 in [0, 1].  Enqueue only. */
 int    nc_set_design(nc_ctx* ctx, const double* x_dev);
 /* Copy the filtered density gamma [E] into gamma_dev. */
 int    nc_get_gamma(nc_ctx* ctx, double* gamma_dev);
+/* The context's density filter on its own (Sec. 5.1): y = F_R x, or y = F_R^T x when
+ * transpose != 0 (the map of element sensitivities back to the raw design; the PDE filter
+ * is symmetric, so both are the same there).  x_dev, y_dev: [E] float64, distinct.  The
+ * identity for radius 0.  Enqueue only. */
+int    nc_filter_apply(nc_ctx* ctx, int transpose, const double* x_dev, double* y_dev);
 
 /* Nonlinear residual R~(s) = M(s) s - f of App. A (eq. finalsyseq, assembled from the
  * element integrals of eq. weakstable with the SUPG weight N* of App. A), [N][5] ->

@@ -128,6 +128,18 @@ void launch_ramp(hipStream_t st, long E, const double* gamma, double k_f, double
                  double kap_s, double q_p, double* coef64, float* coef32, double* dk, double* dkap);
 void launch_sensitivity(hipStream_t st, const Grid& g, const ElemConst<double>& c, const double* coef,
                         const double* dk, const double* dkap, const double* s5, const double* lam5, double* out);
+// PDE (Helmholtz) density filter of Sec. 5.1 (k_filter.hip): Chebyshev steps planned from
+// closed-form spectrum bounds of the Jacobi-preconditioned operator
+constexpr int HELM_MAX_STEPS = 400;
+struct HelmholtzPlan {
+  double h, r;        // element edge, length scale r = R h / (2 sqrt 3)
+  double lmin, lmax;  // spectrum bounds of D^-1 K_F
+  int steps;          // Chebyshev steps for the error bound tol
+};
+HelmholtzPlan helmholtz_plan(double h, double radius, double tol);
+// y = F x (F symmetric); work: 4 node vectors
+void launch_pde_filter(hipStream_t st, const Grid& g, const HelmholtzPlan& pl, const double* x, double* y,
+                       double* work);
 // out[0] = sum_e k_e, out[1] = sum_e kappa_e
 void launch_coef_sums(hipStream_t st, const double* coef, long E, double* part, double* out);
 void launch_objective(hipStream_t st, const Grid& g, const Patch& patch, const double* s5, double* part, double* out);

@@ -79,6 +79,9 @@ struct nc_ctx {
   int m;                 // Krylov restart length
   // design chain
   double *gamma, *dk, *dkap, *ftmp, *sens;
+  bool pde;              // PDE (Helmholtz) density filter
+  HelmholtzPlan helm;
+  double* helm_work;     // its four node vectors
   // coarsest level
   double *emats, *A;
   int* perm;
@@ -193,6 +196,8 @@ bool valid_problem(const nc_problem* p) {
   if (p->coarse_tail != 0 && p->coarse_tail != 1) return false;
   if (!(p->newton_eta0 >= 0.0 && p->newton_eta0 < 1.0)) return false;
   if (p->smooth_pre < 1 || p->smooth_post < 0 || p->smooth_pre_coarse < 1 || p->smooth_post_coarse < 0) return false;
+  if (p->filter_kind != NC_FILTER_CONE && p->filter_kind != NC_FILTER_PDE) return false;
+  if (!(p->filter_radius >= 0.0)) return false;
   return true;
 }
 
@@ -247,6 +252,9 @@ size_t carve(nc_ctx* c, char* base) {
   c->dkap = cv.take<double>(c->E);
   c->ftmp = cv.take<double>(c->E);
   c->sens = cv.take<double>(c->E);
+  c->pde = p.filter_kind == NC_FILTER_PDE && p.filter_radius > 0.0;
+  c->helm_work = cv.take<double>(c->pde ? 4 * c->N : 1);
+  if (c->pde) c->helm = helmholtz_plan(h0, p.filter_radius, 1e-15);
   const Grid& gc = c->lev[c->L - 1].g;
   c->ncoarse = (int)(2 * gc.nodes());
   c->dense = c->ncoarse <= NC_DENSE_MAX;
@@ -301,6 +309,14 @@ void join_levels(nc_ctx* c) {
   if (!c->join2_pending) return;
   ck(hipStreamWaitEvent(c->stream, c->join2, 0));
   c->join2_pending = false;
+}
+
+// The context's density filter: y = F x, or F^T x when transpose (the PDE filter is
+// symmetric; the cone filter's transpose goes through ftmp).
+void apply_filter(nc_ctx* c, const double* x, double* y, bool transpose) {
+  const Grid& g = c->lev[0].g;
+  if (c->pde) launch_pde_filter(c->stream, g, c->helm, x, y, c->helm_work);
+  else launch_cone_filter(c->stream, g, c->p.filter_radius, x, y, transpose, c->ftmp);
 }
 
 // Adds the device time of the recorded hierarchy rebuilds to setup_s (each rebuild: from
@@ -1028,6 +1044,7 @@ void nc_problem_default(nc_problem* p, int nx, int ny, int nz) {
   p->smooth_omega = 1.0;
   p->smooth_pre_coarse = 1;
   p->smooth_post_coarse = 1;
+  p->filter_kind = NC_FILTER_CONE;
 }
 
 size_t nc_workspace_bytes(const nc_problem* p) {
@@ -1137,7 +1154,7 @@ int nc_set_design(nc_ctx* c, const double* x) {
     // the setup streams may still read the coefficients of the previous design
     join_coarse(c);
     join_levels(c);
-    launch_cone_filter(st, L0.g, p.filter_radius, x, c->gamma, false, c->ftmp);
+    apply_filter(c, x, c->gamma, false);
     launch_ramp(st, c->E, c->gamma, p.k_f, p.k_s, p.q_c, p.kappa_f, p.kappa_s, p.q_p, L0.coef64, L0.coef32, c->dk,
                 c->dkap);
     for (int l = 1; l < c->L; ++l) {
@@ -1156,6 +1173,15 @@ int nc_get_gamma(nc_ctx* c, double* gamma) {
   if (!c || !gamma || !c->design_set) return NC_EINVAL;
   return guarded([&]() {
     ck(hipMemcpyAsync(gamma, c->gamma, sizeof(double) * c->E, hipMemcpyDeviceToDevice, c->stream));
+    return NC_OK;
+  });
+}
+
+int nc_filter_apply(nc_ctx* c, int transpose, const double* x, double* y) {
+  if (!c || !x || !y || x == y) return NC_EINVAL;
+  return guarded([&]() {
+    apply_filter(c, x, y, transpose != 0);
+    ck(hipGetLastError());
     return NC_OK;
   });
 }
@@ -1256,7 +1282,7 @@ int nc_sensitivity(nc_ctx* c, const double* s, const double* lam, double* dfdx, 
     const Level& L0 = c->lev[0];
     double* g = dfdgamma ? dfdgamma : c->sens;
     launch_sensitivity(st, L0.g, L0.c64, L0.coef64, c->dk, c->dkap, s, lam, g);
-    launch_cone_filter(st, L0.g, c->p.filter_radius, g, dfdx, true, c->ftmp);
+    apply_filter(c, g, dfdx, true);
     ck(hipGetLastError());
     return NC_OK;
   });

@@ -17,10 +17,11 @@ NC_EINVAL, NC_ENOMEM, NC_EHIP, NC_ENAN = -1, -2, -3, -4
 NC_FP64, NC_MIXED = 0, 1
 NC_DENSE_MAX = 2000   # largest coarsest-grid system inverted densely
 NC_HIST_MAX = 32      # Newton steps / refinement sweeps recorded per solve
+NC_FILTER_CONE, NC_FILTER_PDE = 0, 1
 
 EXPORTED = [
     "nc_problem_default", "nc_workspace_bytes", "nc_create", "nc_destroy", "nc_status_string",
-    "nc_set_design", "nc_get_gamma", "nc_residual", "nc_linearize", "nc_jac_apply", "nc_jacT_apply",
+    "nc_set_design", "nc_get_gamma", "nc_filter_apply", "nc_residual", "nc_linearize", "nc_jac_apply", "nc_jacT_apply",
     "nc_jac_apply_f32", "nc_jacT_apply_f32", "nc_solve_state", "nc_objective", "nc_objective_grad",
     "nc_solve_adjoint", "nc_sensitivity", "nc_precondition", "nc_cone_filter", "nc_dense_inverse",
     "nc_dense_inverse_noalloc", "nc_set_timing", "nc_get_timing",
@@ -52,6 +53,7 @@ class NCProblem(ctypes.Structure):
         ("smooth_pre_coarse", ctypes.c_int), ("smooth_post_coarse", ctypes.c_int),
         ("krylov_rtol_mixed", ctypes.c_double), ("gs_passes", ctypes.c_int),
         ("coarse_tail", ctypes.c_int), ("newton_eta0", ctypes.c_double),
+        ("filter_kind", ctypes.c_int),
     ]
 
 
@@ -93,6 +95,7 @@ def load():
             "nc_status_string": (ctypes.c_char_p, [I]),
             "nc_set_design": (I, [V, V]),
             "nc_get_gamma": (I, [V, V]),
+            "nc_filter_apply": (I, [V, I, V, V]),
             "nc_residual": (I, [V, V, V]),
             "nc_linearize": (I, [V, V]),
             "nc_jac_apply": (I, [V, V, V]),
@@ -202,6 +205,13 @@ class Solver:
         g = torch.empty(self.E, dtype=torch.float64, device=self.device)
         _check(self.lib.nc_get_gamma(self.ctx, _ptr(g)), "nc_get_gamma")
         return g
+
+    def filter_apply(self, x, transpose=False):
+        """y = F x (F^T x) with the context's density filter, via nc_filter_apply."""
+        x = self._in(x, (self.E,))
+        y = torch.empty(self.E, dtype=torch.float64, device=self.device)
+        _check(self.lib.nc_filter_apply(self.ctx, 1 if transpose else 0, _ptr(x), _ptr(y)), "nc_filter_apply")
+        return y
 
     def residual(self, s):
         s = self._in(s, (self.N, 5))

@@ -23,6 +23,13 @@ CONFIGS = {
     "cavity128": dict(grid=(128, 64, 128), gr=1e4, precision=nc.NC_FP64, design="blobs", radius=0.0, seed=2),
     "cavity96filtered": dict(grid=(96, 48, 96), gr=1e3, precision=nc.NC_FP64, design="noise", radius=1.5, seed=3),
     "cavity24filtered": dict(grid=(24, 12, 24), gr=1e3, precision=nc.NC_FP64, design="noise", radius=1.5, seed=3),
+    # the paper's PDE filter with radius 2.5 element lengths (Sec. 6.3, Sec. 7.1)
+    "cavity24pde": dict(grid=(24, 12, 24), gr=1e3, precision=nc.NC_FP64, design="noise", radius=2.5, seed=3,
+                        filter="pde"),
+    "cavity96pde": dict(grid=(96, 48, 96), gr=1e3, precision=nc.NC_FP64, design="noise", radius=2.5, seed=3,
+                        filter="pde"),
+    "cavity128pde": dict(grid=(128, 64, 128), gr=1e4, precision=nc.NC_MIXED, design="noise", radius=2.5, seed=2,
+                         filter="pde"),
 }
 
 
@@ -53,6 +60,7 @@ def design(grid, recipe, seed, device="cuda:0"):
 def config(name, device="cuda:0", **over):
     c = dict(CONFIGS[name])
     c.update(over)
-    p = problem(c["grid"], c["gr"], c["precision"], c["radius"])
+    fk = nc.NC_FILTER_PDE if c.get("filter") == "pde" else nc.NC_FILTER_CONE
+    p = problem(c["grid"], c["gr"], c["precision"], c["radius"], filter_kind=fk)
     x = design(c["grid"], c["design"], c["seed"], device)
     return p, x, c

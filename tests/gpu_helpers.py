@@ -15,7 +15,7 @@ def oracle_params(p):
     return oracle.Params(p.nx, p.ny, p.nz, h=p.h, rho0=p.rho0, mu=p.mu, cp=p.cp, g0=p.g0, alpha=p.alpha,
                          k_f=p.k_f, k_s=p.k_s, kappa_f=p.kappa_f, kappa_s=p.kappa_s, q_c=p.q_c, q_p=p.q_p,
                          q_h=p.q_h, patch=(p.patch_x0, p.patch_x1, p.patch_y0, p.patch_y1), Q=p.Q,
-                         filter_radius=p.filter_radius)
+                         filter_radius=p.filter_radius, filter_kind="pde" if p.filter_kind == nc.NC_FILTER_PDE else "cone")
 
 
 def oracle_blob_design(grid, seed):
