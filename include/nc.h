@@ -74,7 +74,7 @@ typedef struct nc_problem {
   double q_c, q_p;            /* RAMP penalties of k and kappa                           */
   double q_h;                 /* heat flux through the bottom patch                      */
   double patch_x0, patch_x1, patch_y0, patch_y1; /* patch: bottom faces with centre inside */
-  double Q;                   /* uniform volumetric heat source                          */
+  double Q;                   /* volumetric heat source (on q_box, else everywhere)      */
   double filter_radius;       /* density filter radius R in element lengths; 0 = none    */
   int    precision;           /* NC_FP64 or NC_MIXED                                     */
   int    levels;              /* multigrid levels; 0 = choose automatically              */
@@ -96,6 +96,20 @@ typedef struct nc_problem {
                                  0.9 (|R_k| / |R_k-1|)^2 between the Krylov tolerance and
                                  this (Eisenstat-Walker); 0: the Krylov tolerance always   */
   int    filter_kind;         /* NC_FILTER_CONE or NC_FILTER_PDE                          */
+  /* The benchmark of Sec. 6.1: a quarter of the symmetric cavity, a heat-source block and
+   * a design domain.  A box (x0, x1, y0, y1, z0, z1) is in use when x1 > x0, y1 > y0 and
+   * z1 > z0; an element belongs to it when its centre lies in the closed box.           */
+  int    sym_x, sym_y;        /* 1: the wall x = Lx (y = Ly) is a symmetry plane: insulated,
+                                 u.n = 0 (the normal velocity unknowns there are held at 0) */
+  double q_box[6];            /* elements carrying Q; unused box: Q everywhere            */
+  double solid_box[6];        /* passive solid: gamma = 1 whatever the design              */
+  double design_box[6];       /* design domain; elements outside it and outside solid_box
+                                 are passive fluid (gamma = 0); unused box: all design     */
+  double smooth_omega_fallback; /* block-Jacobi damping used for good, in this context, once
+                                 an FGMRES solve has stalled (its first restart cycle did not
+                                 halve the residual: undamped block Jacobi diverges on
+                                 strongly convective blocks); the stalled solve is redone.
+                                 0: no fallback                                          */
 } nc_problem;
 
 #define NC_HIST_MAX 32  /* Newton steps / refinement sweeps recorded in nc_info */
@@ -143,7 +157,8 @@ const char* nc_status_string(int status);
 /* Design chain: gamma = F_R x (the density filter of Sec. 5.1: the cone filter or the
  * PDE filter of filter_kind, radius filter_radius element lengths, identity if 0; the PDE
  * filter is solved by a fixed number of Chebyshev steps planned from closed-form spectrum
- * bounds, to a relative error below 1e-15), then the RAMP conductivity and
+ * bounds, to a relative error below 1e-15), gamma set to 1 on passive solid and 0 on
+ * passive fluid elements (Sec. 6.1), then the RAMP conductivity and
  * permeability of Sec. 5.2 (eqs. condRAMP, permRAMP) and their derivatives, on the
  * finest level and averaged onto the coarser multigrid levels.
  * x_dev: [E] float64 in [0, 1].  Enqueue only. */
@@ -184,12 +199,16 @@ int    nc_jacT_apply_f32(nc_ctx* ctx, const float* w_dev, float* y_dev);
  * iterate; NC_ENAN on a non-finite residual. */
 int    nc_solve_state(nc_ctx* ctx, double* s_dev, nc_info* info);
 
-/* Objective f = f_qh^T t (the thermal compliance of Sec. 5.1, eq. objdiscr, with the
- * boundary-flux load of App. A in place of the volumetric one), to *f_host.
+/* Objective: the thermal compliance of Sec. 5.1 (eq. objdiscr), f = sum_e f_tQ,e^T t_e
+ * with the volumetric load f_tQ,e = int N*^T Q of App. A (its SUPG weight N* depends on
+ * the state), plus f_qh^T t for the boundary-flux load of the patch, to *f_host.
  * Synchronises. */
 int    nc_objective(nc_ctx* ctx, const double* s_dev, double* f_host);
-/* d f / d s, [N][5] (f_qh on the T entries of the patch nodes, 0 elsewhere). */
-int    nc_objective_grad(nc_ctx* ctx, double* g_dev);
+/* d f / d s at the state s_dev, [N][5]: f_qh on the T entries of the patch nodes plus the
+ * derivative of the volumetric part (P and T entries of the source elements' nodes), 0 on
+ * constrained entries.  s_dev may be NULL when Q = 0 (the gradient is then the constant
+ * flux load); NC_EINVAL otherwise.  Enqueue only. */
+int    nc_objective_grad(nc_ctx* ctx, const double* s_dev, double* g_dev);
 
 /* Adjoint solve J~^T lambda = rhs at the state s (the adjoint sensitivity analysis of
  * Sec. 5.1; rhs = df/ds, e.g. from nc_objective_grad, Sec. 5.1 eq. objdiscr).  rhs_dev,
@@ -198,12 +217,29 @@ int    nc_objective_grad(nc_ctx* ctx, double* g_dev);
  * Synchronises; fills *info if non-NULL. */
 int    nc_solve_adjoint(nc_ctx* ctx, const double* s_dev, const double* rhs_dev, double* lam_dev, nc_info* info);
 
-/* Design sensitivities of Sec. 5.1 (the adjoint method; the explicit df/dgamma term is
- * zero for the flux objective): dfdgamma_e = -lambda_e^T dR_e/dgamma_e through the RAMP
- * derivatives of Sec. 5.2, then dfdx = F_R^T dfdgamma (the chain rule through the
- * density filter).  dfdx_dev [E] (required), dfdgamma_dev [E] (may be NULL).  Enqueue
+/* Adjoint term of the design sensitivities of Sec. 5.1 for any objective whose d f / d s
+ * was the adjoint's right-hand side: dfdgamma_e = -lambda_e^T dR_e/dgamma_e through the
+ * RAMP derivatives of Sec. 5.2 (zero on passive elements), then dfdx = F_R^T dfdgamma (the
+ * chain rule through the density filter; zero off the design domain).  An objective with
+ * an explicit dependence on gamma adds it (nc_objective_sensitivity does for
+ * nc_objective).  dfdx_dev [E] (required), dfdgamma_dev [E] (may be NULL).  Enqueue
  * only. */
 int    nc_sensitivity(nc_ctx* ctx, const double* s_dev, const double* lam_dev, double* dfdx_dev, double* dfdgamma_dev);
+
+/* d f / d x of nc_objective (Sec. 5.1): the adjoint term of nc_sensitivity plus the
+ * objective's explicit dependence on gamma (the volumetric load's SUPG weight depends on
+ * the permeability), for lam_dev from nc_solve_adjoint with rhs = nc_objective_grad.
+ * Passive elements have zero dfdgamma, and dfdx is zero off the design domain.  Enqueue
+ * only. */
+int    nc_objective_sensitivity(nc_ctx* ctx, const double* s_dev, const double* lam_dev, double* dfdx_dev,
+                                double* dfdgamma_dev);
+
+/* Volume constraint of Sec. 5.1 (eq. constr) without its bound g*: the solid fraction
+ * sum_D gamma_e v_e / sum_D v_e of the filtered design over the design domain D (the
+ * design box minus the solid box), to *frac_host, and, when dgdx_dev [E] is not NULL, its
+ * gradient with respect to the raw design through the filter (zero off D).  NC_EINVAL
+ * for an empty design domain.  Synchronises. */
+int    nc_volume(nc_ctx* ctx, double* frac_host, double* dgdx_dev);
 
 /* Optional per-context timing of the solver's kernels with HIP events on the context's
  * stream (a tracing aid; adds one event pair per timed launch).  nc_set_timing(ctx, 1)

@@ -128,7 +128,8 @@ class Model:
 
         Stops after a full step whose every field-block is below step_rtol relative to
         that field of the iterate (quadratic convergence makes the following error
-        round-off).  Returns s (N, 5) and a history dict.
+        round-off); such a step is taken undamped (reading of the paper's stopping rule for
+        the float64 floor).  Returns s (N, 5) and a history dict.
         """
         s = np.zeros((self.mesh.n_nodes, NFIELD)) if s0 is None else np.array(s0, dtype=float).reshape(-1, NFIELD)
         s[self.mask] = self.sbar[self.mask]
@@ -146,12 +147,20 @@ class Model:
             t_asm, t_fac, t_sol = t_asm + t1 - t0, t_fac + t2 - t1, t_sol + t3 - t2
             nrm = np.linalg.norm(R)
             lam = 1.0
-            while True:
+            # a full step already below step_rtol in every field is at the round-off level of
+            # the root, where the residual norm is noise and no longer orders the iterates:
+            # it is taken undamped and ends the iteration
+            full = [np.linalg.norm(d[:, f]) / max(np.linalg.norm(s[:, f] + d[:, f]), 1e-300) for f in range(NFIELD)]
+            tiny = max(full) <= step_rtol
+            while not tiny:
                 st = s + lam * d
                 Rt = self.residual(st)
                 if np.linalg.norm(Rt) <= nrm or lam < 1.0 / 64:
                     break
                 lam *= 0.5
+            if tiny:
+                st = s + d
+                Rt = self.residual(st)
             s, R = st, Rt
             rel = [np.linalg.norm(d[:, f]) / max(np.linalg.norm(s[:, f]), 1e-300) for f in range(NFIELD)]
             hist["res"].append(np.linalg.norm(R))

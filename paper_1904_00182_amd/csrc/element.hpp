@@ -37,9 +37,14 @@ struct ElemConst {
   T inv_mu;    // 1 / mu
   T beta;      // rho0 alpha g0 (buoyancy per unit temperature, along +z)
   T rcp;       // rho0 c_p
-  T Q;         // uniform volumetric source
+  T Q;         // volumetric source on the source box (everywhere by default)
   T inv_he2;   // 1 / h_e^2, h_e^2 = dx^2 + dy^2 + dz^2 = 3 h^2
   T tau3inv2;  // tau3^-2 = 16 / h_e^4
+  int qi0, qi1, qj0, qj1, qk0, qk1;   // element index ranges (inclusive) carrying Q
+  // the volumetric source of element (i, j, k)
+  NC_HD T source(int i, int j, int k) const {
+    return (i >= qi0 && i <= qi1 && j >= qj0 && j <= qj1 && k >= qk0 && k <= qk1) ? Q : (T)0;
+  }
 };
 
 template <typename T>
@@ -54,6 +59,8 @@ NC_HD ElemConst<T> make_elem_const(double h, double rho0, double mu, double cp, 
   c.Q = (T)Q;
   c.inv_he2 = (T)(1.0 / he2);
   c.tau3inv2 = (T)(16.0 / (he2 * he2));
+  c.qi0 = c.qj0 = c.qk0 = -(1 << 30);
+  c.qi1 = c.qj1 = c.qk1 = 1 << 30;
   return c;
 }
 
@@ -202,7 +209,7 @@ struct Lin {
 };
 
 template <typename T>
-NC_HD void linearize(const T P[8], const T Tn[8], T k, T kap, const ElemConst<T>& c, Lin<T>& L) {
+NC_HD void linearize_q(const T P[8], const T Tn[8], T k, T kap, T Q, const ElemConst<T>& c, Lin<T>& L) {
   T mP[8], mT[8];
   hadamard_fwd(P, mP);
   hadamard_fwd(Tn, mT);
@@ -223,7 +230,7 @@ NC_HD void linearize(const T P[8], const T Tn[8], T k, T kap, const ElemConst<T>
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int jx = jx_of(q), jy = jy_of(q), jz = jz_of(q);
-    L.conv[q] = c.rcp * kap * (L.uhx[jx] * L.gTx[jx] + L.uhy[jy] * L.gTy[jy] + L.uhz[q] * L.gTz[jz]) - c.Q;
+    L.conv[q] = c.rcp * kap * (L.uhx[jx] * L.gTx[jx] + L.uhy[jy] * L.gTy[jy] + L.uhz[q] * L.gTz[jz]) - Q;
   }
   const T cm = kap * im;
   L.u0[0] = -cm * gPc[0];
@@ -233,6 +240,11 @@ NC_HD void linearize(const T P[8], const T Tn[8], T k, T kap, const ElemConst<T>
   const T tau = (T)1 / sqrt(s);
   L.tau = tau;
   L.dtau = (T)(-4) * tau * tau * tau * c.inv_he2;
+}
+// with the constant's source Q
+template <typename T>
+NC_HD void linearize(const T P[8], const T Tn[8], T k, T kap, const ElemConst<T>& c, Lin<T>& L) {
+  linearize_q(P, Tn, k, kap, c.Q, c, L);
 }
 
 // Element rows of the residual (without the boundary flux and without the lumped-mass
@@ -576,7 +588,7 @@ NC_HD void modal_velocity(const T mp[8], const T mt[8], T cm, const ElemConst<T>
 }
 
 template <typename T>
-NC_HD void lin_modal(const T P[8], const T Tn[8], T k, T kap, const ElemConst<T>& c, LinM<T>& L) {
+NC_HD void lin_modal_q(const T P[8], const T Tn[8], T k, T kap, T Q, const ElemConst<T>& c, LinM<T>& L) {
   hadamard_fwd(P, L.mP);
   hadamard_fwd(Tn, L.mT);
   L.k = k;
@@ -588,13 +600,18 @@ NC_HD void lin_modal(const T P[8], const T Tn[8], T k, T kap, const ElemConst<T>
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int jx = jx_of(q), jy = jy_of(q), jz = jz_of(q);
-    conv[q] = c.rcp * (L.ux[jx] * L.gTx[jx] + L.uy[jy] * L.gTy[jy] + L.uz[q] * L.gTz[jz]) - c.Q;
+    conv[q] = c.rcp * (L.ux[jx] * L.gTx[jx] + L.uy[jy] * L.gTy[jy] + L.uz[q] * L.gTz[jz]) - Q;
   }
   hadamard_fwd(conv, L.C);
   const T s = (T)4 * (L.u0[0] * L.u0[0] + L.u0[1] * L.u0[1] + L.u0[2] * L.u0[2]) * c.inv_he2 + c.tau3inv2;
   const T tau = (T)1 / sqrt(s);
   L.tau = tau;
   L.dtau = (T)(-4) * tau * tau * tau * c.inv_he2;
+}
+// with the constant's source Q
+template <typename T>
+NC_HD void lin_modal(const T P[8], const T Tn[8], T k, T kap, const ElemConst<T>& c, LinM<T>& L) {
+  lin_modal_q(P, Tn, k, kap, c.Q, c, L);
 }
 
 // Pressure rows in modal form: rho_m = W cm [dxi^2/64 K_m mp_m - beta dxi/64 B mt]

@@ -389,7 +389,7 @@ struct ResidualOp {
     for (int a = 0; a < 8; ++a) { P[a] = nd[a][0]; Tn[a] = nd[a][1]; }
     const long e = g.elem(i, j, k);
     LinM<double> L;
-    lin_modal(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    lin_modal_q(P, Tn, coef[2 * e], coef[2 * e + 1], c.source(i, j, k), c, L);
     double rP[8] = {0}, rT[8] = {0}, rU[3][8] = {{0}};
     elem_residual_m<double, true>(L, c, rP, rT, rU);
     if (k == 0 && patch.has(i, j)) {
@@ -407,7 +407,7 @@ struct ResidualOp {
     const long n = g.node(i, j, k);
     const double M = c.W * g.valence(i, j, k);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) r[5 * n + d] = v[d] + M * s[5 * n + d];
+    for (int d = 0; d < 3; ++d) r[5 * n + d] = g.ufix(i, j, d) ? s[5 * n + d] : v[d] + M * s[5 * n + d];
     r[5 * n + 3] = g.pfix(i, j, k) ? s[5 * n + 3] : v[3];
     r[5 * n + 4] = g.tfix(i, j, k) ? s[5 * n + 4] : v[4];
   }
@@ -465,7 +465,7 @@ struct JvOp {
     for (int a = 0; a < 8; ++a) { P[a] = nd[a][0]; Tn[a] = nd[a][1]; p[a] = nd[a][2]; t[a] = nd[a][3]; }
     const auto kc = g.elayer(coef, 2, k).template ld<typename Pair<T>::type>(2 * g.ecol(i, j));
     LinM<T> L;
-    lin_modal(P, Tn, kc.x, kc.y, c, L);
+    lin_modal_q(P, Tn, kc.x, kc.y, c.source(i, j, k), c, L);
     T yP[8] = {0}, yT[8] = {0}, yU[3][8] = {{0}};
     elem_jv_m<T, NF == 5>(L, p, t, c, yP, yT, yU);
 #pragma unroll
@@ -503,7 +503,10 @@ struct JvOp {
     if constexpr (NF == 5) {
       const T M = c.W * (T)g.valence(i, j, k);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) yk.template st<T>(5 * n + d, rs.s[d] * (v[d] + M * xk.template ld<T>(5 * n + d)));
+      for (int d = 0; d < 3; ++d) {
+        const T xd = xk.template ld<T>(5 * n + d);
+        yk.template st<T>(5 * n + d, rs.s[d] * (g.ufix(i, j, d) ? xd : v[d] + M * xd));
+      }
       const T ap = pf ? xk.template ld<T>(5 * n + 3) : v[3];
       const T at = tf ? xk.template ld<T>(5 * n + 4) : v[4];
       yk.template st<T>(5 * n + 3, rs.s[3] * ap);
@@ -559,7 +562,7 @@ struct JtwOp {
       p = xk.template ld<T>(NF * n + NF - 2);
       t = xk.template ld<T>(NF * n + NF - 1);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) in[4 + d] = xk.template ld<T>(5 * n + d);
+      for (int d = 0; d < 3; ++d) in[4 + d] = g.ufix(i, j, d) ? (T)0 : xk.template ld<T>(5 * n + d);
     }
     if (g.pfix(i, j, k)) p = (T)0;
     if (g.tfix(i, j, k)) t = (T)0;
@@ -577,7 +580,7 @@ struct JtwOp {
     }
     const auto kc = g.elayer(coef, 2, k).template ld<typename Pair<T>::type>(2 * g.ecol(i, j));
     LinM<T> L;
-    lin_modal(P, Tn, kc.x, kc.y, c, L);
+    lin_modal_q(P, Tn, kc.x, kc.y, c.source(i, j, k), c, L);
     T yP[8] = {0}, yT[8] = {0};
     elem_jtw_m<T, NF == 5>(L, wP, wT, wU, c, yP, yT);
 #pragma unroll
@@ -611,7 +614,10 @@ struct JtwOp {
     if constexpr (NF == 5) {
       const T M = c.W * (T)g.valence(i, j, k);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) yk.template st<T>(5 * n + d, rs.s[d] * M * xk.template ld<T>(5 * n + d));
+      for (int d = 0; d < 3; ++d) {
+        const T xd = xk.template ld<T>(5 * n + d);
+        yk.template st<T>(5 * n + d, rs.s[d] * (g.ufix(i, j, d) ? xd : M * xd));
+      }
       const T ap = pf ? xk.template ld<T>(5 * n + 3) : v[0];
       const T at = tf ? xk.template ld<T>(5 * n + 4) : v[1];
       yk.template st<T>(5 * n + 3, rs.s[3] * ap);
@@ -806,7 +812,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
         w[c8] = g.tfix(ni, nj, nk) ? (T)0 : x[2 * n + 1];
       }
       LinM<T> L;
-      lin_modal(P, Tn, CO[2 * e], CO[2 * e + 1], a.lv.c, L);
+      lin_modal_q(P, Tn, CO[2 * e], CO[2 * e + 1], a.lv.c.source(i, j, k), a.lv.c, L);
       T yP[8] = {0}, yT[8] = {0}, yU[3][8] = {{0}};
       if constexpr (TR) elem_jtw_m<T, false>(L, p, w, yU, a.lv.c, yP, yT);
       else elem_jv_m<T, false>(L, p, w, a.lv.c, yP, yT, yU);
@@ -961,7 +967,7 @@ struct DiagOp {
     for (int a = 0; a < 8; ++a) { P[a] = nd[a][0]; Tn[a] = nd[a][1]; }
     const long e = g.elem(i, j, k);
     LinM<T> L;
-    lin_modal(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+    lin_modal_q(P, Tn, coef[2 * e], coef[2 * e + 1], c.source(i, j, k), c, L);
     // float32: unrolled, so that the compiler folds the unit inputs through the transforms
     // (the float64 instance would then hold too many values and spill, so it loops)
     if constexpr (sizeof(T) == 4) {
@@ -1033,7 +1039,8 @@ struct UprojOp {
     const long n = g.node(i, j, k);
     const T iM = (T)1 / (c.W * (T)g.valence(i, j, k));
 #pragma unroll
-    for (int d = 0; d < 3; ++d) z5[5 * n + d] = (inv.s[d] * r5[5 * n + d] - v[d]) * iM;
+    for (int d = 0; d < 3; ++d)
+      z5[5 * n + d] = g.ufix(i, j, d) ? inv.s[d] * r5[5 * n + d] : (inv.s[d] * r5[5 * n + d] - v[d]) * iM;
     z5[5 * n + 3] = g.pfix(i, j, k) ? inv.s[3] * r5[5 * n + 3] : xpt[2 * n];
     z5[5 * n + 4] = g.tfix(i, j, k) ? inv.s[4] * r5[5 * n + 4] : xpt[2 * n + 1];
   }
@@ -1054,7 +1061,7 @@ struct UprojTOp {
     const long n = g.node(i, j, k);
     const T iM = (T)1 / (c.W * (T)g.valence(i, j, k));
 #pragma unroll
-    for (int d = 0; d < 3; ++d) in[d] = inv.s[d] * r5[5 * n + d] * iM;
+    for (int d = 0; d < 3; ++d) in[d] = g.ufix(i, j, d) ? (T)0 : inv.s[d] * r5[5 * n + d] * iM;
   }
   __device__ void element(int i, int j, int k, const T nd[8][NIN], T out[8][NOUT]) const {
     T zu[3][8], yP[8] = {0}, yT[8] = {0};
@@ -1068,7 +1075,7 @@ struct UprojTOp {
     const long n = g.node(i, j, k);
     const T iM = (T)1 / (c.W * (T)g.valence(i, j, k));
 #pragma unroll
-    for (int d = 0; d < 3; ++d) z5[5 * n + d] = inv.s[d] * r5[5 * n + d] * iM;
+    for (int d = 0; d < 3; ++d) z5[5 * n + d] = inv.s[d] * r5[5 * n + d] * (g.ufix(i, j, d) ? (T)1 : iM);
     bpt[2 * n] = g.pfix(i, j, k) ? (T)0 : inv.s[3] * r5[5 * n + 3] - v[0];
     bpt[2 * n + 1] = g.tfix(i, j, k) ? (T)0 : inv.s[4] * r5[5 * n + 4] - v[1];
   }

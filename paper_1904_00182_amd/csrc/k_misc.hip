@@ -153,7 +153,7 @@ __global__ __launch_bounds__(BS) void elem_matrix_kernel(LevelView<T> L, double*
   }
   if (col & 1) tt[col >> 1] = (T)1; else p[col >> 1] = (T)1;
   Lin<T> lin;
-  linearize(P, Tn, L.coef[2 * e], L.coef[2 * e + 1], L.c, lin);
+  linearize_q(P, Tn, L.coef[2 * e], L.coef[2 * e + 1], L.c.source(i, j, k), L.c, lin);
   T yP[8] = {0}, yT[8] = {0}, yU[3][8];
   elem_jv<T, false>(lin, p, tt, L.c, yP, yT, yU);
   double* m = mats + (e * 16 + col) * 16;
@@ -539,6 +539,8 @@ __global__ void mask_state_kernel(Grid g, double* __restrict__ s5) {
   const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)), k = (int)(n / ((long)(g.nx + 1) * (g.ny + 1)));
   if (g.pfix(i, j, k)) s5[5 * n + 3] = 0.0;
   if (g.tfix(i, j, k)) s5[5 * n + 4] = 0.0;
+  if (g.ufix(i, j, 0)) s5[5 * n] = 0.0;
+  if (g.ufix(i, j, 1)) s5[5 * n + 1] = 0.0;
 }
 void launch_mask_state(hipStream_t st, const Grid& g, double* s5) {
   launch(mask_state_kernel, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, s5);
@@ -1097,10 +1099,10 @@ __global__ __launch_bounds__(BS) void sensitivity_kernel(Grid g, ElemConst<doubl
     Tn[a] = s5[5 * n + 4];
     lP[a] = g.pfix(ii, jj, kk) ? 0.0 : l5[5 * n + 3];
     lT[a] = g.tfix(ii, jj, kk) ? 0.0 : l5[5 * n + 4];
-    for (int d = 0; d < 3; ++d) lU[d][a] = l5[5 * n + d];
+    for (int d = 0; d < 3; ++d) lU[d][a] = g.ufix(ii, jj, d) ? 0.0 : l5[5 * n + d];
   }
   Lin<double> L;
-  linearize(P, Tn, coef[2 * e], coef[2 * e + 1], c, L);
+  linearize_q(P, Tn, coef[2 * e], coef[2 * e + 1], c.source(i, j, k), c, L);
   out[e] = elem_sensitivity<double, true>(L, lP, lT, lU, dk[e], dkap[e], c);
 }
 void launch_sensitivity(hipStream_t st, const Grid& g, const ElemConst<double>& c, const double* coef,
@@ -1132,8 +1134,75 @@ void launch_coef_sums(hipStream_t st, const double* coef, long E, double* part, 
 }
 
 // ------------------------------------------------------------------ objective
-// f = sum over patch faces of q_h h^2/4 (T of the face's four nodes)
-__global__ __launch_bounds__(BS) void objective_kernel(Grid g, Patch pa, const double* __restrict__ s5, double* __restrict__ part) {
+// Volumetric compliance of one element, f_e = sum_a T_a int_e N*_a Q (Sec. 5.1 eq. objdiscr
+// with f_tQ of App. A).  For the trilinear element int_e N_a = h^3 / 8 and
+// int_e grad N_a = h^3 grad N_a(x_c), so f_e = Q h^3 (T_c + tau u0 . grad T_c) with the
+// centroid values; with its derivatives by the nodal P and T (u0 and tau depend on them)
+// and by the permeability (u0 = kappa w).
+struct QElem {
+  double f, dP[8], dT[8], dkap;
+};
+__device__ QElem q_element(const ElemConst<double>& c, double Q, double kap, const double P[8], const double Tn[8]) {
+  const double q4 = 0.125 * c.dxi;   // 1 / (4 h): |d N_a / d x_d| at the centroid
+  double gP[3] = {0.0, 0.0, 0.0}, G[3] = {0.0, 0.0, 0.0}, Tc = 0.0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const double sx = (a & 1) ? q4 : -q4, sy = (a & 2) ? q4 : -q4, sz = (a & 4) ? q4 : -q4;
+    gP[0] += sx * P[a]; gP[1] += sy * P[a]; gP[2] += sz * P[a];
+    G[0] += sx * Tn[a]; G[1] += sy * Tn[a]; G[2] += sz * Tn[a];
+    Tc += 0.125 * Tn[a];
+  }
+  const double im = c.inv_mu;
+  const double w[3] = {-im * gP[0], -im * gP[1], -im * (gP[2] - c.beta * Tc)};   // u0 / kappa
+  const double u0[3] = {kap * w[0], kap * w[1], kap * w[2]};
+  const double tau = 1.0 / sqrt(4.0 * (u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2]) * c.inv_he2 + c.tau3inv2);
+  const double t3 = -4.0 * tau * tau * tau * c.inv_he2;     // d tau = t3 (u0 . d u0)
+  const double uG = u0[0] * G[0] + u0[1] * G[1] + u0[2] * G[2];
+  const double QV = Q * 8.0 * c.W;                          // Q h^3
+  QElem r;
+  r.f = QV * (Tc + tau * uG);
+  const double cm = kap * im;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const double sx = (a & 1) ? q4 : -q4, sy = (a & 2) ? q4 : -q4, sz = (a & 4) ? q4 : -q4;
+    // d u0 / d P_a = -(kappa / mu) grad N_a(x_c)
+    const double dux = -cm * sx, duy = -cm * sy, duz = -cm * sz;
+    r.dP[a] = QV * (uG * t3 * (u0[0] * dux + u0[1] * duy + u0[2] * duz) + tau * (G[0] * dux + G[1] * duy + G[2] * duz));
+    // d u0 / d T_a = (kappa / mu) beta N_a(x_c) e_z
+    const double dTz = cm * c.beta * 0.125;
+    r.dT[a] = QV * (0.125 + tau * (u0[0] * sx + u0[1] * sy + u0[2] * sz) + uG * t3 * u0[2] * dTz + tau * G[2] * dTz);
+  }
+  r.dkap = QV * (uG * t3 * (u0[0] * w[0] + u0[1] * w[1] + u0[2] * w[2]) + tau * (G[0] * w[0] + G[1] * w[1] + G[2] * w[2]));
+  return r;
+}
+
+// the source box of c clamped to the grid: [i0, i1] x [j0, j1] x [k0, k1], count 0 if empty
+struct BoxRange {
+  int i0, i1, j0, j1, k0, k1;
+  long count;
+};
+__host__ __device__ inline BoxRange source_range(const Grid& g, const ElemConst<double>& c) {
+  BoxRange b;
+  b.i0 = c.qi0 < 0 ? 0 : c.qi0; b.i1 = c.qi1 > g.nx - 1 ? g.nx - 1 : c.qi1;
+  b.j0 = c.qj0 < 0 ? 0 : c.qj0; b.j1 = c.qj1 > g.ny - 1 ? g.ny - 1 : c.qj1;
+  b.k0 = c.qk0 < 0 ? 0 : c.qk0; b.k1 = c.qk1 > g.nz - 1 ? g.nz - 1 : c.qk1;
+  const long ni = b.i1 - b.i0 + 1, nj = b.j1 - b.j0 + 1, nk = b.k1 - b.k0 + 1;
+  b.count = (c.Q == 0.0 || ni <= 0 || nj <= 0 || nk <= 0) ? 0 : ni * nj * nk;
+  return b;
+}
+__device__ inline void element_nodes(const Grid& g, const double* s5, int i, int j, int k, double P[8], double Tn[8]) {
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const long n = g.node(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+    P[a] = s5[5 * n + 3];
+    Tn[a] = s5[5 * n + 4];
+  }
+}
+
+// f = sum over patch faces of q_h h^2/4 (T of the face's four nodes) + the volumetric
+// compliance of the source elements
+__global__ __launch_bounds__(BS) void objective_kernel(Grid g, Patch pa, ElemConst<double> c, const double* __restrict__ coef,
+                                                       const double* __restrict__ s5, double* __restrict__ part) {
   __shared__ double red[BS / 64];
   double s = 0.0;
   const long F = (long)g.nx * g.ny;
@@ -1142,6 +1211,14 @@ __global__ __launch_bounds__(BS) void objective_kernel(Grid g, Patch pa, const d
     if (!pa.has(i, j)) continue;
     const double w = pa.q_h * pa.h * pa.h * 0.25;
     for (int c = 0; c < 4; ++c) s += w * s5[5 * g.node(i + (c & 1), j + (c >> 1), 0) + 4];
+  }
+  const BoxRange b = source_range(g, c);
+  const long ni = b.i1 - b.i0 + 1, nj = b.j1 - b.j0 + 1;
+  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < b.count; t += (long)gridDim.x * BS) {
+    const int i = b.i0 + (int)(t % ni), j = b.j0 + (int)((t / ni) % nj), k = b.k0 + (int)(t / (ni * nj));
+    double P[8], Tn[8];
+    element_nodes(g, s5, i, j, k, P, Tn);
+    s += q_element(c, c.Q, coef[2 * g.elem(i, j, k) + 1], P, Tn).f;
   }
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -1152,8 +1229,9 @@ __global__ __launch_bounds__(BS) void objective_kernel(Grid g, Patch pa, const d
     part[blockIdx.x * MAXC] = tot;
   }
 }
-void launch_objective(hipStream_t st, const Grid& g, const Patch& patch, const double* s5, double* part, double* out) {
-  launch(objective_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, g, patch, s5, part);
+void launch_objective(hipStream_t st, const Grid& g, const Patch& patch, const ElemConst<double>& c, const double* coef,
+                      const double* s5, double* part, double* out) {
+  launch(objective_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, g, patch, c, coef, s5, part);
   launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 0, (double*)nullptr);
 }
 
@@ -1174,6 +1252,102 @@ __global__ void objective_grad_kernel(Grid g, Patch pa, double* __restrict__ g5)
 }
 void launch_objective_grad(hipStream_t st, const Grid& g, const Patch& patch, double* g5) {
   launch(objective_grad_kernel, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, patch, g5);
+}
+
+// g5 += d (volumetric compliance) / d (P, T): each node gathers the derivatives of the
+// source elements around it, in a fixed order; constrained entries are left to the caller
+__global__ __launch_bounds__(BS) void objective_grad_q_kernel(Grid g, ElemConst<double> c, const double* __restrict__ coef,
+                                                              const double* __restrict__ s5, double* __restrict__ g5) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.nodes()) return;
+  const int i = (int)(n % (g.nx + 1)), j = (int)((n / (g.nx + 1)) % (g.ny + 1)), k = (int)(n / ((long)(g.nx + 1) * (g.ny + 1)));
+  double dp = 0.0, dt = 0.0;
+  for (int a = 7; a >= 0; --a) {   // element (i, j, k) - offset(a) has this node as its corner a
+    const int ei = i - (a & 1), ej = j - ((a >> 1) & 1), ek = k - ((a >> 2) & 1);
+    if (ei < 0 || ei >= g.nx || ej < 0 || ej >= g.ny || ek < 0 || ek >= g.nz) continue;
+    const double Q = c.source(ei, ej, ek);
+    if (Q == 0.0) continue;
+    double P[8], Tn[8];
+    element_nodes(g, s5, ei, ej, ek, P, Tn);
+    const QElem r = q_element(c, Q, coef[2 * g.elem(ei, ej, ek) + 1], P, Tn);
+    dp += r.dP[a];
+    dt += r.dT[a];
+  }
+  g5[5 * n + 3] += dp;
+  g5[5 * n + 4] += dt;
+}
+void launch_objective_grad_q(hipStream_t st, const Grid& g, const ElemConst<double>& c, const double* coef,
+                             const double* s5, double* g5) {
+  launch(objective_grad_q_kernel, dim3(blocks_for(g.nodes())), dim3(BS), 0, st, g, c, coef, s5, g5);
+}
+
+// out[e] += d (volumetric compliance) / d gamma_e = d f_e / d kappa * d kappa / d gamma
+__global__ __launch_bounds__(BS) void objective_dgamma_kernel(Grid g, ElemConst<double> c, const double* __restrict__ coef,
+                                                              const double* __restrict__ dkap, const double* __restrict__ s5,
+                                                              double* __restrict__ out) {
+  const BoxRange b = source_range(g, c);
+  const long ni = b.i1 - b.i0 + 1, nj = b.j1 - b.j0 + 1;
+  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < b.count; t += (long)gridDim.x * BS) {
+    const int i = b.i0 + (int)(t % ni), j = b.j0 + (int)((t / ni) % nj), k = b.k0 + (int)(t / (ni * nj));
+    double P[8], Tn[8];
+    element_nodes(g, s5, i, j, k, P, Tn);
+    const long e = g.elem(i, j, k);
+    out[e] += q_element(c, c.Q, coef[2 * e + 1], P, Tn).dkap * dkap[e];
+  }
+}
+void launch_objective_dgamma(hipStream_t st, const Grid& g, const ElemConst<double>& c, const double* coef,
+                             const double* dkap, const double* s5, double* out) {
+  const long cnt = source_range(g, c).count;
+  if (cnt == 0) return;
+  launch(objective_dgamma_kernel, dim3(blocks_for(cnt)), dim3(BS), 0, st, g, c, coef, dkap, s5, out);
+}
+
+// ------------------------------------------------------------------ passive regions
+// gamma = 1 on passive solid, 0 on passive fluid (outside the design domain)
+__global__ __launch_bounds__(BS) void passive_kernel(Grid g, Regions rg, double* __restrict__ gamma) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.elems()) return;
+  const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((long)g.nx * g.ny));
+  if (rg.solid(i, j, k)) gamma[e] = 1.0;
+  else if (!rg.design(i, j, k)) gamma[e] = 0.0;
+}
+void launch_passive(hipStream_t st, const Grid& g, const Regions& rg, double* gamma) {
+  launch(passive_kernel, dim3(blocks_for(g.elems())), dim3(BS), 0, st, g, rg, gamma);
+}
+// a[e] = 0 off the design domain; with fill: a[e] = design ? fill : 0
+__global__ __launch_bounds__(BS) void design_mask_kernel(Grid g, Regions rg, double* __restrict__ a, int set, double fill) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.elems()) return;
+  const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((long)g.nx * g.ny));
+  const bool d = rg.design(i, j, k);
+  if (set) a[e] = d ? fill : 0.0;
+  else if (!d) a[e] = 0.0;
+}
+void launch_design_mask(hipStream_t st, const Grid& g, const Regions& rg, double* a, bool set, double fill) {
+  launch(design_mask_kernel, dim3(blocks_for(g.elems())), dim3(BS), 0, st, g, rg, a, set ? 1 : 0, fill);
+}
+// out[0] = sum of gamma over the design domain
+__global__ __launch_bounds__(BS) void design_sum_kernel(Grid g, Regions rg, const double* __restrict__ gamma,
+                                                        double* __restrict__ part) {
+  __shared__ double red[BS / 64];
+  double s = 0.0;
+  for (long e = (long)blockIdx.x * BS + threadIdx.x; e < g.elems(); e += (long)gridDim.x * BS) {
+    const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((long)g.nx * g.ny));
+    if (rg.design(i, j, k)) s += gamma[e];
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w2 = 0; w2 < BS / 64; ++w2) tot += red[w2];
+    part[blockIdx.x * MAXC] = tot;
+  }
+}
+void launch_design_sum(hipStream_t st, const Grid& g, const Regions& rg, const double* gamma, double* part,
+                       double* out) {
+  launch(design_sum_kernel, dim3(RED_BLOCKS), dim3(BS), 0, st, g, rg, gamma, part);
+  launch(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, 1, out, 0, (double*)nullptr);
 }
 
 // ------------------------------------------------------------------ instantiations

@@ -142,7 +142,36 @@ void launch_pde_filter(hipStream_t st, const Grid& g, const HelmholtzPlan& pl, c
                        double* work);
 // out[0] = sum_e k_e, out[1] = sum_e kappa_e
 void launch_coef_sums(hipStream_t st, const double* coef, long E, double* part, double* out);
-void launch_objective(hipStream_t st, const Grid& g, const Patch& patch, const double* s5, double* part, double* out);
+// objective: the patch-flux compliance plus the volumetric compliance of the source
+// elements (c.source), sum_e f_tQ,e^T t_e with the SUPG weight
+void launch_objective(hipStream_t st, const Grid& g, const Patch& patch, const ElemConst<double>& c, const double* coef,
+                      const double* s5, double* part, double* out);
 void launch_objective_grad(hipStream_t st, const Grid& g, const Patch& patch, double* g5);
+// g5 += d (volumetric compliance) / d (P, T)
+void launch_objective_grad_q(hipStream_t st, const Grid& g, const ElemConst<double>& c, const double* coef,
+                             const double* s5, double* g5);
+// out[e] += explicit d (volumetric compliance) / d gamma_e (through the permeability)
+void launch_objective_dgamma(hipStream_t st, const Grid& g, const ElemConst<double>& c, const double* coef,
+                             const double* dkap, const double* s5, double* out);
+
+// ---- passive regions of the benchmark (Sec. 6.1): inclusive element index ranges
+struct Regions {
+  int s[6];        // passive solid (gamma = 1): i0, i1, j0, j1, k0, k1
+  int d[6];        // design domain; outside it (and outside the solid) passive fluid
+  int has_s, has_d;
+  __host__ __device__ bool solid(int i, int j, int k) const {
+    return has_s && i >= s[0] && i <= s[1] && j >= s[2] && j <= s[3] && k >= s[4] && k <= s[5];
+  }
+  __host__ __device__ bool design(int i, int j, int k) const {
+    if (solid(i, j, k)) return false;
+    return !has_d || (i >= d[0] && i <= d[1] && j >= d[2] && j <= d[3] && k >= d[4] && k <= d[5]);
+  }
+};
+void launch_passive(hipStream_t st, const Grid& g, const Regions& rg, double* gamma);
+// a = 0 off the design domain (set: a = fill on it, 0 off it)
+void launch_design_mask(hipStream_t st, const Grid& g, const Regions& rg, double* a, bool set, double fill);
+// out[0] = sum of gamma over the design domain
+void launch_design_sum(hipStream_t st, const Grid& g, const Regions& rg, const double* gamma, double* part,
+                       double* out);
 
 }  // namespace nc

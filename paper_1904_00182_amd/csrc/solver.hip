@@ -79,6 +79,9 @@ struct nc_ctx {
   int m;                 // Krylov restart length
   // design chain
   double *gamma, *dk, *dkap, *ftmp, *sens;
+  Regions reg;           // passive solid / fluid regions on the finest grid
+  bool regions;          // any passive region
+  long n_design;         // elements of the design domain
   bool pde;              // PDE (Helmholtz) density filter
   HelmholtzPlan helm;
   double* helm_work;     // its four node vectors
@@ -124,6 +127,7 @@ struct nc_ctx {
   bool hier_valid;       // multigrid hierarchy (node-block inverses, coarse inverse) built for this design
   bool rows_valid;       // rows64 / rows32 and res_floor computed for this design
   double res_floor;      // round-off floor of the scaled residual
+  double omega;          // block-Jacobi damping in use: smooth_omega, or the fallback after a stall
   // optional event timing per kernel class
   bool timing;
   std::vector<hipEvent_t> ev;
@@ -184,6 +188,27 @@ double nn(const Grid& g) { return (double)(g.nx + 1) * (g.ny + 1) * (g.nz + 1); 
 double ne(const Grid& g) { return (double)g.nx * g.ny * g.nz; }
 
 // ------------------------------------------------------------------ setup helpers
+// A box (x0, x1, y0, y1, z0, z1) is in use when x1 > x0, y1 > y0 and z1 > z0.
+bool box_on(const double* b) { return b[1] > b[0] && b[3] > b[2] && b[5] > b[4]; }
+
+// Inclusive element index ranges of the elements whose centre ((i + 1/2) h, ...) lies in
+// the closed box; an empty range has lo > hi.
+void box_range(const double* b, const Grid& g, double h, int r[6]) {
+  const int n[3] = {g.nx, g.ny, g.nz};
+  for (int d = 0; d < 3; ++d) {
+    int lo = n[d], hi = -1;
+    for (int i = 0; i < n[d]; ++i) {
+      const double c = (i + 0.5) * h;
+      if (c >= b[2 * d] && c <= b[2 * d + 1]) {
+        lo = std::min(lo, i);
+        hi = std::max(hi, i);
+      }
+    }
+    r[2 * d] = lo;
+    r[2 * d + 1] = hi;
+  }
+}
+
 bool valid_problem(const nc_problem* p) {
   if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
   if ((double)(p->nx + 1) * (p->ny + 1) * (p->nz + 1) * 5 >= 2147483647.0) return false;   // 32-bit indices
@@ -196,13 +221,16 @@ bool valid_problem(const nc_problem* p) {
   if (p->coarse_tail != 0 && p->coarse_tail != 1) return false;
   if (!(p->newton_eta0 >= 0.0 && p->newton_eta0 < 1.0)) return false;
   if (p->smooth_pre < 1 || p->smooth_post < 0 || p->smooth_pre_coarse < 1 || p->smooth_post_coarse < 0) return false;
+  if (!(p->smooth_omega > 0.0 && p->smooth_omega <= 2.0) || !(p->smooth_omega_fallback >= 0.0 && p->smooth_omega_fallback <= 2.0))
+    return false;
   if (p->filter_kind != NC_FILTER_CONE && p->filter_kind != NC_FILTER_PDE) return false;
+  if ((p->sym_x != 0 && p->sym_x != 1) || (p->sym_y != 0 && p->sym_y != 1)) return false;
   if (!(p->filter_radius >= 0.0)) return false;
   return true;
 }
 
 int choose_levels(const nc_problem* p, Grid* gs) {
-  Grid g{p->nx, p->ny, p->nz};
+  Grid g{p->nx, p->ny, p->nz, (p->sym_x ? 1 : 0) | (p->sym_y ? 2 : 0)};
   gs[0] = g;
   int L = 1;
   const int cap = p->levels > 0 ? std::min(p->levels, MAXLEV) : MAXLEV;
@@ -211,7 +239,7 @@ int choose_levels(const nc_problem* p, Grid* gs) {
     if ((f.nx & 1) || (f.ny & 1) || (f.nz & 1)) break;
     if (f.nx / 2 < 2 || f.ny / 2 < 2 || f.nz / 2 < 2) break;
     if (p->levels <= 0 && 2 * f.nodes() <= 300) break;
-    gs[L] = Grid{f.nx / 2, f.ny / 2, f.nz / 2};
+    gs[L] = Grid{f.nx / 2, f.ny / 2, f.nz / 2, f.sym};
     ++L;
   }
   return L;
@@ -232,6 +260,13 @@ size_t carve(nc_ctx* c, char* base) {
     L.h = h0 * (1 << l);
     L.c64 = make_elem_const<double>(L.h, p.rho0, p.mu, p.cp, p.g0, p.alpha, p.Q);
     L.c32 = make_elem_const<float>(L.h, p.rho0, p.mu, p.cp, p.g0, p.alpha, p.Q);
+    if (box_on(p.q_box)) {   // the source only on the elements of the box (on every level)
+      int r[6];
+      box_range(p.q_box, L.g, L.h, r);
+      L.c64.qi0 = L.c32.qi0 = r[0]; L.c64.qi1 = L.c32.qi1 = r[1];
+      L.c64.qj0 = L.c32.qj0 = r[2]; L.c64.qj1 = L.c32.qj1 = r[3];
+      L.c64.qk0 = L.c32.qk0 = r[4]; L.c64.qk1 = L.c32.qk1 = r[5];
+    }
     const long N = L.g.nodes(), E = L.g.elems();
     L.coef64 = cv.take<double>(2 * E);
     L.coef32 = cv.take<float>(2 * E);
@@ -245,6 +280,17 @@ size_t carve(nc_ctx* c, char* base) {
   }
   c->N = gs[0].nodes();
   c->E = gs[0].elems();
+  // passive regions on the finest grid
+  c->reg = Regions{};
+  c->reg.has_s = box_on(p.solid_box) ? 1 : 0;
+  c->reg.has_d = box_on(p.design_box) ? 1 : 0;
+  if (c->reg.has_s) box_range(p.solid_box, gs[0], h0, c->reg.s);
+  if (c->reg.has_d) box_range(p.design_box, gs[0], h0, c->reg.d);
+  c->regions = c->reg.has_s || c->reg.has_d;
+  c->n_design = 0;
+  for (int k = 0; k < gs[0].nz; ++k)
+    for (int j = 0; j < gs[0].ny; ++j)
+      for (int i = 0; i < gs[0].nx; ++i) c->n_design += c->reg.design(i, j, k) ? 1 : 0;
   c->n5 = 5 * c->N;
   c->m = p.krylov_restart;
   c->gamma = cv.take<double>(c->E);
@@ -317,6 +363,16 @@ void apply_filter(nc_ctx* c, const double* x, double* y, bool transpose) {
   const Grid& g = c->lev[0].g;
   if (c->pde) launch_pde_filter(c->stream, g, c->helm, x, y, c->helm_work);
   else launch_cone_filter(c->stream, g, c->p.filter_radius, x, y, transpose, c->ftmp);
+}
+
+// dfdx = F^T dfdgamma for the filtered, passive-overwritten design: dfdgamma is zeroed
+// on passive elements (their gamma is fixed) and dfdx off the design domain (those x are
+// not design variables).
+void pull_back(nc_ctx* c, double* dfdgamma, double* dfdx) {
+  const Grid& g = c->lev[0].g;
+  if (c->regions) launch_design_mask(c->stream, g, c->reg, dfdgamma, false, 0.0);
+  apply_filter(c, dfdgamma, dfdx, true);
+  if (c->regions) launch_design_mask(c->stream, g, c->reg, dfdx, false, 0.0);
 }
 
 // Adds the device time of the recorded hierarchy rebuilds to setup_s (each rebuild: from
@@ -399,7 +455,7 @@ template <typename T>
 void vcycle(nc_ctx* c, int l, bool tr, bool x_ready = false) {
   hipStream_t st = c->stream;
   Level& L = c->lev[l];
-  const T om = (T)c->p.smooth_omega;
+  const T om = (T)c->omega;
   LevelView<T> v = view<T>(c, l);
   const double sweep_bytes = sizeof(T) * (12 * nn(L.g) + 2 * ne(L.g));
   const int sweep_class = l == 0 ? (tr ? TC_SMOOTH_T : TC_SMOOTH) : TC_SMOOTH_COARSE;
@@ -473,7 +529,7 @@ void precondition_pt(nc_ctx* c, bool tr, T* v, T* z, const Scale5<T>* rows, cons
   const T ip = rows ? (T)1 / rows->s[3] : (T)1, it = rows ? (T)1 / rows->s[4] : (T)1;
   {
     Timed tm(c, TC_VECTOR, sizeof(T) * 10 * nn(L0.g));
-    launch_pc_in<T>(st, L0.g, v, nrm, ip, it, (const T*)L0.dinv, tr, (T)c->p.smooth_omega, (T*)L0.b, (T*)L0.x);
+    launch_pc_in<T>(st, L0.g, v, nrm, ip, it, (const T*)L0.dinv, tr, (T)c->omega, (T*)L0.b, (T*)L0.x);
   }
   vcycle<T>(c, 0, tr, true);
   L0.x = xo;
@@ -528,8 +584,10 @@ constexpr int HSLOT = 2 * MAXC + 8;   // doubles per Hessenberg slot: h1 [MAXC],
 // test), so the device does not idle on the host's round trip -- except before a step
 // predicted to end the solve, where it waits rather than enqueue a step that would be
 // discarded.
+bool debug_on();
+
 template <typename T>
-int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double* relres) {
+int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double* relres, bool* stalled = nullptr) {
   hipStream_t st = c->stream;
   const Scale5<T>* rows = row_scales<T>(c);
   const long n = 2 * c->N, ld = c->ld;
@@ -651,6 +709,13 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
     ck(hipMemcpyAsync(dres + 3 * MAXC, c->hbuf, sizeof(double) * jend, hipMemcpyHostToDevice, st));
     launch_maxpy<T>(st, Z, ld, jend, dres + 3 * MAXC, 1.0, x, n, c->part, nullptr);
     if (done) break;
+    // a first cycle that has not halved the residual: the preconditioner does not work
+    // for this system (undamped block Jacobi diverges on strongly convective blocks); the
+    // caller may retry with more damping
+    if (stalled && total == jend && *relres > 0.5) {
+      *stalled = true;
+      return total;
+    }
     // restart from the true residual
     apply_pt<T>(c, tr, x, V, rows);
     launch_rsub<T>(st, b, V, n);
@@ -690,8 +755,19 @@ int reduced_solve(nc_ctx* c, bool tr, const double* r, double* d, bool krylov, d
   }
   int its = 0;
   if (krylov) {
-    its = fgmres<T>(c, tr, kb, kx, rtol, c->p.krylov_maxit, relres);
+    bool stalled = false;
+    its = fgmres<T>(c, tr, kb, kx, rtol, c->p.krylov_maxit, relres,
+                    c->p.smooth_omega_fallback > 0.0 && c->omega != c->p.smooth_omega_fallback ? &stalled : nullptr);
     if (its < 0) return its;
+    if (stalled) {
+      // switch this context to the fallback damping for good and solve again from zero
+      if (debug_on()) std::fprintf(stderr, "nc fgmres stalled (relres %.2e): block-Jacobi damping %g -> %g\n", *relres,
+                                   c->omega, c->p.smooth_omega_fallback);
+      c->omega = c->p.smooth_omega_fallback;
+      const int more = fgmres<T>(c, tr, kb, kx, rtol, c->p.krylov_maxit, relres);
+      if (more < 0) return more;
+      its += more;
+    }
   } else {
     precondition_pt<T>(c, tr, kb, kx, nullptr);
   }
@@ -746,10 +822,28 @@ double scaled_norm(nc_ctx* c, const double* a) {
   return scaled_from(c, c->hbuf);
 }
 
+// elements carrying the volumetric source on the finest grid
+struct BoxRangeCount {
+  long count;
+};
+BoxRangeCount source_count(const nc_ctx* c) {
+  const Grid& g = c->lev[0].g;
+  const ElemConst<double>& e = c->lev[0].c64;
+  const long ni = std::max(0, std::min(e.qi1, g.nx - 1) - std::max(e.qi0, 0) + 1);
+  const long nj = std::max(0, std::min(e.qj1, g.ny - 1) - std::max(e.qj0, 0) + 1);
+  const long nk = std::max(0, std::min(e.qk1, g.nz - 1) - std::max(e.qk0, 0) + 1);
+  return BoxRangeCount{ni * nj * nk};
+}
+
 // round-off floor of the scaled residual: 1e-12 of the scaled boundary-flux load
 double residual_floor(nc_ctx* c) {
   launch_objective_grad(c->stream, c->lev[0].g, c->patch, c->tmp5);
-  return 1e-12 * scaled_norm(c, c->tmp5);
+  double fl = scaled_norm(c, c->tmp5);
+  if (c->p.Q != 0.0) {   // the load of the volumetric source: |Q| h^3 per source element
+    const BoxRangeCount n = source_count(c);
+    fl += fabs(c->p.Q) * std::pow(c->lev[0].h, 3) * std::sqrt((double)n.count) * c->rows64.s[4];
+  }
+  return 1e-12 * fl;
 }
 
 // NC_DEBUG=1 prints the Newton and adjoint iterations to stderr (tracing aid)
@@ -855,7 +949,10 @@ int newton(nc_ctx* c, double* s, nc_info* info) {
     if (debug_on())
       std::fprintf(stderr, "nc newton %d: krylov %d relres %.2e lam %g step %.2e step_pt %.2e merit %.3e -> %.3e floor %.2e\n",
                    it, its, relres, lam, step, step_pt, rn_prev, rn, floor);
-    if (lam == 1.0 && (step <= p.newton_step_rtol || rn <= floor || predicted || (tiny && rn > 0.5 * rn_prev))) {
+    // (a small step from a linear solve that missed its tolerance says nothing about the
+    // root: the step tests need the solve to have reached it)
+    const bool solved = relres <= 10.0 * eta;
+    if (lam == 1.0 && ((solved && step <= p.newton_step_rtol) || rn <= floor || predicted || (tiny && rn > 0.5 * rn_prev))) {
       status = NC_OK;
       ++it;
       break;
@@ -1042,9 +1139,12 @@ void nc_problem_default(nc_problem* p, int nx, int ny, int nz) {
   p->smooth_pre = 2;
   p->smooth_post = 2;
   p->smooth_omega = 1.0;
+  p->smooth_omega_fallback = 0.7;
   p->smooth_pre_coarse = 1;
   p->smooth_post_coarse = 1;
   p->filter_kind = NC_FILTER_CONE;
+  p->sym_x = p->sym_y = 0;
+  for (int d = 0; d < 6; ++d) p->q_box[d] = p->solid_box[d] = p->design_box[d] = 0.0;
 }
 
 size_t nc_workspace_bytes(const nc_problem* p) {
@@ -1094,6 +1194,7 @@ int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stre
     c->patch = Patch{c->p.q_h, c->p.patch_x0, c->p.patch_x1, c->p.patch_y0, c->p.patch_y1, c->p.h};
     c->design_set = false;
     c->hier_valid = false;
+    c->omega = c->p.smooth_omega;
     c->timing = false;
     c->ev_used = 0;
     c->join_pending = c->join2_pending = false;
@@ -1155,6 +1256,7 @@ int nc_set_design(nc_ctx* c, const double* x) {
     join_coarse(c);
     join_levels(c);
     apply_filter(c, x, c->gamma, false);
+    if (c->regions) launch_passive(st, L0.g, c->reg, c->gamma);
     launch_ramp(st, c->E, c->gamma, p.k_f, p.k_s, p.q_c, p.kappa_f, p.kappa_s, p.q_p, L0.coef64, L0.coef32, c->dk,
                 c->dkap);
     for (int l = 1; l < c->L; ++l) {
@@ -1242,18 +1344,60 @@ int nc_solve_state(nc_ctx* c, double* s, nc_info* info) {
 }
 
 int nc_objective(nc_ctx* c, const double* s, double* f) {
-  if (!c || !s || !f) return NC_EINVAL;
+  if (!c || !s || !f || !c->design_set) return NC_EINVAL;
   return guarded([&]() {
-    launch_objective(c->stream, c->lev[0].g, c->patch, s, c->part, c->dres);
+    launch_objective(c->stream, c->lev[0].g, c->patch, c->lev[0].c64, c->lev[0].coef64, s, c->part, c->dres);
     fetch(c, c->dres, 1);
     *f = c->hbuf[0];
     return NC_OK;
   });
 }
 
-int nc_objective_grad(nc_ctx* c, double* g) {
+int nc_objective_grad(nc_ctx* c, const double* s, double* g) {
   if (!c || !g) return NC_EINVAL;
-  return guarded([&]() { launch_objective_grad(c->stream, c->lev[0].g, c->patch, g); ck(hipGetLastError()); return NC_OK; });
+  if (c->p.Q != 0.0 && !s) return NC_EINVAL;   // the volumetric part depends on the state
+  return guarded([&]() {
+    const Level& L0 = c->lev[0];
+    launch_objective_grad(c->stream, L0.g, c->patch, g);
+    if (c->p.Q != 0.0) {
+      launch_objective_grad_q(c->stream, L0.g, L0.c64, L0.coef64, s, g);
+      launch_mask_state(c->stream, L0.g, g);
+    }
+    ck(hipGetLastError());
+    return NC_OK;
+  });
+}
+
+int nc_objective_sensitivity(nc_ctx* c, const double* s, const double* lam, double* dfdx, double* dfdgamma) {
+  if (!c || !s || !lam || !dfdx || !c->design_set) return NC_EINVAL;
+  return guarded([&]() {
+    hipStream_t st = c->stream;
+    const Level& L0 = c->lev[0];
+    double* g = dfdgamma ? dfdgamma : c->sens;
+    launch_sensitivity(st, L0.g, L0.c64, L0.coef64, c->dk, c->dkap, s, lam, g);
+    if (c->p.Q != 0.0) launch_objective_dgamma(st, L0.g, L0.c64, L0.coef64, c->dkap, s, g);
+    pull_back(c, g, dfdx);
+    ck(hipGetLastError());
+    return NC_OK;
+  });
+}
+
+int nc_volume(nc_ctx* c, double* frac, double* dgdx) {
+  if (!c || !frac || !c->design_set) return NC_EINVAL;
+  if (c->n_design == 0) return NC_EINVAL;
+  return guarded([&]() {
+    hipStream_t st = c->stream;
+    const Grid& g = c->lev[0].g;
+    if (dgdx) {
+      launch_design_mask(st, g, c->reg, c->sens, true, 1.0 / (double)c->n_design);
+      apply_filter(c, c->sens, dgdx, true);
+      launch_design_mask(st, g, c->reg, dgdx, false, 0.0);
+    }
+    launch_design_sum(st, g, c->reg, c->gamma, c->part, c->dres);
+    fetch(c, c->dres, 1);
+    *frac = c->hbuf[0] / (double)c->n_design;
+    return NC_OK;
+  });
 }
 
 int nc_solve_adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info* info) {
@@ -1282,7 +1426,7 @@ int nc_sensitivity(nc_ctx* c, const double* s, const double* lam, double* dfdx, 
     const Level& L0 = c->lev[0];
     double* g = dfdgamma ? dfdgamma : c->sens;
     launch_sensitivity(st, L0.g, L0.c64, L0.coef64, c->dk, c->dkap, s, lam, g);
-    apply_filter(c, g, dfdx, true);
+    pull_back(c, g, dfdx);
     ck(hipGetLastError());
     return NC_OK;
   });

@@ -23,7 +23,7 @@ EXPORTED = [
     "nc_problem_default", "nc_workspace_bytes", "nc_create", "nc_destroy", "nc_status_string",
     "nc_set_design", "nc_get_gamma", "nc_filter_apply", "nc_residual", "nc_linearize", "nc_jac_apply", "nc_jacT_apply",
     "nc_jac_apply_f32", "nc_jacT_apply_f32", "nc_solve_state", "nc_objective", "nc_objective_grad",
-    "nc_solve_adjoint", "nc_sensitivity", "nc_precondition", "nc_cone_filter", "nc_dense_inverse",
+    "nc_solve_adjoint", "nc_sensitivity", "nc_objective_sensitivity", "nc_volume", "nc_precondition", "nc_cone_filter", "nc_dense_inverse",
     "nc_dense_inverse_noalloc", "nc_set_timing", "nc_get_timing",
 ]
 
@@ -54,6 +54,9 @@ class NCProblem(ctypes.Structure):
         ("krylov_rtol_mixed", ctypes.c_double), ("gs_passes", ctypes.c_int),
         ("coarse_tail", ctypes.c_int), ("newton_eta0", ctypes.c_double),
         ("filter_kind", ctypes.c_int),
+        ("sym_x", ctypes.c_int), ("sym_y", ctypes.c_int),
+        ("q_box", ctypes.c_double * 6), ("solid_box", ctypes.c_double * 6), ("design_box", ctypes.c_double * 6),
+        ("smooth_omega_fallback", ctypes.c_double),
     ]
 
 
@@ -105,7 +108,9 @@ def load():
             "nc_jacT_apply_f32": (I, [V, V, V]),
             "nc_solve_state": (I, [V, V, ctypes.POINTER(NCInfo)]),
             "nc_objective": (I, [V, V, ctypes.POINTER(D)]),
-            "nc_objective_grad": (I, [V, V]),
+            "nc_objective_grad": (I, [V, V, V]),
+            "nc_objective_sensitivity": (I, [V, V, V, V, V]),
+            "nc_volume": (I, [V, ctypes.POINTER(D), V]),
             "nc_solve_adjoint": (I, [V, V, V, V, ctypes.POINTER(NCInfo)]),
             "nc_sensitivity": (I, [V, V, V, V, V]),
             "nc_cone_filter": (I, [I, I, I, D, V, V, I, V]),
@@ -128,6 +133,8 @@ def default_problem(nx, ny, nz, **overrides):
     for k, v in overrides.items():
         if not hasattr(p, k):
             raise KeyError(k)
+        if k in ("q_box", "solid_box", "design_box"):
+            v = (ctypes.c_double * 6)(*v)
         setattr(p, k, v)
     return p
 
@@ -263,10 +270,30 @@ class Solver:
         _check(self.lib.nc_objective(self.ctx, _ptr(s), ctypes.byref(f)), "nc_objective")
         return f.value
 
-    def objective_grad(self):
+    def objective_grad(self, s=None):
+        """d f / d s of the compliance; s is required when the problem has a volumetric
+        source (its SUPG-weighted load depends on the state)."""
         g = self._vec()
-        _check(self.lib.nc_objective_grad(self.ctx, _ptr(g)), "nc_objective_grad")
+        sp = _ptr(self._in(s, (self.N, 5))) if s is not None else None
+        _check(self.lib.nc_objective_grad(self.ctx, sp, _ptr(g)), "nc_objective_grad")
         return g
+
+    def objective_sensitivity(self, s, lam, with_gamma=False):
+        """d f / d x of nc_objective (adjoint term plus the explicit design term)."""
+        s = self._in(s, (self.N, 5))
+        lam = self._in(lam, (self.N, 5))
+        dfdx = torch.empty(self.E, dtype=torch.float64, device=self.device)
+        dfdg = torch.empty(self.E, dtype=torch.float64, device=self.device) if with_gamma else None
+        _check(self.lib.nc_objective_sensitivity(self.ctx, _ptr(s), _ptr(lam), _ptr(dfdx),
+                                                 _ptr(dfdg) if dfdg is not None else None), "nc_objective_sensitivity")
+        return (dfdx, dfdg) if with_gamma else dfdx
+
+    def volume(self, with_grad=True):
+        """(solid fraction of the design domain, its gradient w.r.t. x or None)."""
+        frac = ctypes.c_double()
+        dg = torch.empty(self.E, dtype=torch.float64, device=self.device) if with_grad else None
+        _check(self.lib.nc_volume(self.ctx, ctypes.byref(frac), _ptr(dg) if dg is not None else None), "nc_volume")
+        return frac.value, dg
 
     def solve_adjoint(self, s, rhs, out=None):
         s = self._in(s, (self.N, 5))

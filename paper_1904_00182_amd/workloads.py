@@ -64,3 +64,24 @@ def config(name, device="cuda:0", **over):
     p = problem(c["grid"], c["gr"], c["precision"], c["radius"], filter_kind=fk)
     x = design(c["grid"], c["design"], c["seed"], device)
     return p, x, c
+
+
+# The benchmark of Sec. 6.1 on a quarter of the 1 m cavity with symmetry planes at x = y =
+# 0.5: heat-source block 0.1 x 0.1 x 0.05 m (Q = 1e4, passive solid) on the floor at the
+# centre, design domain 0.75 x 0.75 x 0.75 m on top of it, fluid elsewhere.
+BENCH_Q = 1e4
+BENCH_SOURCE = (0.45, 0.5, 0.45, 0.5, 0.0, 0.05)
+BENCH_DESIGN = (0.125, 0.5, 0.125, 0.5, 0.05, 0.8)
+
+
+def benchmark_problem(n, alpha=1e3, precision=nc.NC_FP64, kappa_s=1e-5, q_c=8.81, q_p=8.0, filter_radius=2.5,
+                      **over):
+    """Quarter cavity of Sec. 6.1 with n x n x 2n elements (h = 0.5 / n), the Table tab:2
+    permeability for alpha, the PDE filter of radius 2.5 elements and the penalties of the
+    performance study (q_c = 8.81, q_p = 8)."""
+    fields = dict(h=0.5 / n, alpha=float(alpha), kappa_f=KAPPA_F[float(alpha)], kappa_s=kappa_s, q_c=q_c, q_p=q_p,
+                  q_h=0.0, Q=BENCH_Q, precision=precision, filter_radius=float(filter_radius),
+                  filter_kind=nc.NC_FILTER_PDE, sym_x=1, sym_y=1, q_box=BENCH_SOURCE, solid_box=BENCH_SOURCE,
+                  design_box=BENCH_DESIGN)
+    fields.update(over)
+    return nc.default_problem(n, n, 2 * n, **fields)

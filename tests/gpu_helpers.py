@@ -10,12 +10,19 @@ from paper_1904_00182_amd import nc, inputs
 DEV = "cuda:0"
 
 
+def _box(b):
+    b = tuple(float(v) for v in b)
+    return b if (b[1] > b[0] and b[3] > b[2] and b[5] > b[4]) else None
+
+
 def oracle_params(p):
     """oracle.Params mirroring an NCProblem."""
     return oracle.Params(p.nx, p.ny, p.nz, h=p.h, rho0=p.rho0, mu=p.mu, cp=p.cp, g0=p.g0, alpha=p.alpha,
                          k_f=p.k_f, k_s=p.k_s, kappa_f=p.kappa_f, kappa_s=p.kappa_s, q_c=p.q_c, q_p=p.q_p,
                          q_h=p.q_h, patch=(p.patch_x0, p.patch_x1, p.patch_y0, p.patch_y1), Q=p.Q,
-                         filter_radius=p.filter_radius, filter_kind="pde" if p.filter_kind == nc.NC_FILTER_PDE else "cone")
+                         filter_radius=p.filter_radius, filter_kind="pde" if p.filter_kind == nc.NC_FILTER_PDE else "cone",
+                         q_box=_box(p.q_box), solid_box=_box(p.solid_box), design_box=_box(p.design_box),
+                         sym_x=bool(p.sym_x), sym_y=bool(p.sym_y))
 
 
 def oracle_blob_design(grid, seed):
@@ -83,7 +90,7 @@ def local_rows(p, s, k, kap, nodes, v=None, transpose_w=None):
     """
     prm = oracle_params(p)
     mesh = oracle.Mesh(prm)
-    mask, _ = oracle.default_constraints(mesh)
+    mask, _ = oracle.default_constraints(mesh, prm)
     out = np.zeros((len(nodes), NFIELD))
     h = 1e-30
     for r, (i, j, kk) in enumerate(nodes):

@@ -64,7 +64,7 @@ def test_ctypes_struct_matches_header_fields():
     text = open(os.path.join(ROOT, "include", "nc.h")).read()
     body = text[text.index("typedef struct nc_problem {"):text.index("} nc_problem;")]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    names = re.findall(r"\b([a-zA-Z_][a-zA-Z0-9_]*)\s*[,;]", body)
+    names = re.findall(r"\b([a-zA-Z_][a-zA-Z0-9_]*)\s*(?:\[[^\]]*\])?\s*[,;]", body)
     assert names == [f[0] for f in nc.NCProblem._fields_]
 
 
