@@ -18,7 +18,8 @@ What it computes (all in float64, plain and unblocked):
   with SuperLU;
 * the adjoint solve with the transposed factorisation and the design
   sensitivities -lambda^T dR/dgamma (Sec. 5.1, adjoint sensitivity analysis);
-* the closed-form permeability tuning of Sec. 3 (eqs. nusselt1-nusselt5).
+* the closed-form permeability tuning of Sec. 3 (eqs. nusselt1-nusselt5);
+* the Method of Moving Asymptotes for the volume-constrained design update (Sec. 5.1).
 
 Parity status: every function is pinned by tests under tests/ (closed forms,
 invariants, brute-force finite differences, the paper's Table tab:2); the SUPG
@@ -32,9 +33,10 @@ from .material import ramp_k, ramp_kappa, ramp_k_deriv, ramp_kappa_deriv, cone_f
 from .element import element_residual, reference_element
 from .pde_filter import PDEFilter, pde_length_scale
 from .fem import Model
+from .mma import MMA
 
 __all__ = [
     "Params", "Mesh", "default_constraints", "patch_flux",
     "ramp_k", "ramp_kappa", "ramp_k_deriv", "ramp_kappa_deriv", "cone_filter_matrix", "kappa_f_tuning",
-    "element_residual", "reference_element", "Model", "PDEFilter", "pde_length_scale",
+    "element_residual", "reference_element", "Model", "PDEFilter", "pde_length_scale", "MMA",
 ]

@@ -745,3 +745,76 @@ def test_source_objective_uses_the_residual_source_load():
     N, _, _, _, detJ, _ = reference_element(kw["h"])
     galerkin = np.sum(mQ.Qe[:, None] * detJ * N.sum(axis=0)[None, :] * s[:, FIELD_T][mQ.mesh.conn])
     assert abs(f - galerkin) > 1e-6 * abs(f)
+
+
+# --------------------------------------------------------------------------- P17
+def test_mma_converges_to_the_closed_form_optimum():
+    """MMA (Sec. 5.1) on a convex problem with a known optimum: minimise sum_j c_j / x_j
+    subject to mean(x) <= V, 0 <= x <= 1.  KKT: c_j / x_j^2 = lambda / n with the constraint
+    active, so x_j = n V sqrt(c_j) / sum_k sqrt(c_k)."""
+    from oracle import MMA
+    n, V = 50, 0.3
+    c = 1.0 + rng(51).uniform(size=n)
+    xstar = n * V * np.sqrt(c) / np.sqrt(c).sum()
+    assert 0.0 < xstar.min() and xstar.max() < 1.0
+    opt = MMA(n, move=0.2)
+    x = np.full(n, V)
+    for _ in range(200):
+        x, lam = opt.update(x, -c / x ** 2, x.mean() - V, np.full(n, 1.0 / n))
+    assert np.abs(x - xstar).max() < 1e-8, np.abs(x - xstar).max()
+    assert abs(x.mean() - V) < 1e-10
+    # the multiplier of the last subproblem is the true one: -c_j / x_j^2 + lambda / n = 0
+    assert abs(lam - n * c[0] / xstar[0] ** 2) < 1e-6 * lam
+
+
+def test_mma_subproblem_kkt_and_move_limit():
+    """One MMA update from random data: the new x is within the move limit and [0, 1], and it
+    satisfies the KKT conditions of the subproblem, checked with the derivative of the
+    Lagrangian P/(U - x) + Q/(x - L) (not with its closed-form minimiser): zero inside
+    (alpha, beta), pointing outwards at an active bound; the constraint approximation holds,
+    with equality when lambda > 0."""
+    from oracle import MMA
+    n = 400
+    r = rng(52)
+    opt = MMA(n, move=0.2)
+    x = r.uniform(0.1, 0.9, n)
+    for it in range(4):
+        df = r.standard_normal(n)
+        dg = np.abs(r.standard_normal(n)) / n
+        g = 0.01 * (it - 1)
+        xn, lam = opt.update(x, df, g, dg)
+        assert np.isfinite(lam)
+        d = opt.last
+        assert np.all(np.abs(xn - x) <= 0.2 + 1e-15) and xn.min() >= 0.0 and xn.max() <= 1.0
+        P, Q = d["p0"] + lam * d["p1"], d["q0"] + lam * d["q1"]
+        dL = P / (opt.upp - xn) ** 2 - Q / (xn - opt.low) ** 2
+        scale = P / (opt.upp - xn) ** 2 + Q / (xn - opt.low) ** 2
+        inside = (xn > d["alpha"] + 1e-12) & (xn < d["beta"] - 1e-12)
+        assert np.all(np.abs(dL[inside]) <= 1e-10 * scale[inside])
+        assert np.all(dL[xn <= d["alpha"] + 1e-12] >= -1e-10 * scale[xn <= d["alpha"] + 1e-12])
+        assert np.all(dL[xn >= d["beta"] - 1e-12] <= 1e-10 * scale[xn >= d["beta"] - 1e-12])
+        con = np.sum(d["p1"] / (opt.upp - xn) + d["q1"] / (xn - opt.low)) - d["b"]
+        assert con <= 1e-10 * d["b"]
+        if lam > 0:
+            assert abs(con) <= 1e-10 * abs(d["b"])
+        x = xn
+
+
+def test_mma_infeasible_subproblem_reduces_the_constraint_most():
+    """A constraint violation that the move limit cannot remove in one step: the update is
+    the minimiser of the constraint's approximation alone over the subproblem's box (the
+    lambda -> infinity limit), which no other point of the box improves on."""
+    from oracle import MMA
+    n = 300
+    r = rng(53)
+    opt = MMA(n, move=0.05)
+    x = r.uniform(0.2, 0.8, n)
+    dg = np.abs(r.standard_normal(n)) / n
+    xn, lam = opt.update(x, r.standard_normal(n), 1.0, dg)
+    assert lam == np.inf
+    d = opt.last
+    best = opt.constraint(xn, d["p1"], d["q1"], d["b"])
+    assert best > 0.0
+    for trial in range(20):
+        y = np.clip(xn + 1e-3 * r.standard_normal(n), d["alpha"], d["beta"])
+        assert opt.constraint(y, d["p1"], d["q1"], d["b"]) >= best - 1e-15
