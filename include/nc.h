@@ -241,6 +241,30 @@ int    nc_objective_sensitivity(nc_ctx* ctx, const double* s_dev, const double* 
  * for an empty design domain.  Synchronises. */
 int    nc_volume(nc_ctx* ctx, double* frac_host, double* dgdx_dev);
 
+/* Changes the parameters of a context in place (continuation of the penalties and of the
+ * solid permeability, Sec. 5.3 eq. contsch1; a ramp of the heat source, Sec. 5.4; or a new
+ * request on a pooled context).  The new problem must give the same workspace layout:
+ * the same grid, multigrid levels, precision, Krylov restart and filter work; NC_EINVAL
+ * otherwise.  The design must be set again (nc_set_design) before the next solve.  Host
+ * only (waits for the context's setup streams). */
+int    nc_set_problem(nc_ctx* ctx, const nc_problem* p);
+
+/* One iteration of the Method of Moving Asymptotes (Sec. 5.1, Svanberg's method; the move
+ * limit of Sec. 6.1) for min f subject to g <= 0 and 0 <= x <= 1, over the design elements
+ * of the context (the raw design of passive elements is left as it is).  iter: 1 for the
+ * first update of a run, then 2, 3, ... (the asymptotes start from x in the first two
+ * iterations and then widen or narrow with the sign pattern of the last two steps);
+ * x_dev [E]: in the current design, out the update; dfdx_dev, dgdx_dev [E]: derivatives of
+ * the objective and of the constraint; g: the constraint value (e.g. volume fraction -
+ * g*); state_dev: caller-owned NC_MMA_ROWS x E doubles kept between iterations (the last
+ * two iterates and the asymptotes; the rest is scratch).  The subproblem is solved
+ * through its dual (one multiplier, written to *lambda_host when not NULL; infinite when
+ * no point within the move limit satisfies the constraint's approximation, and the update
+ * then reduces it most).  Synchronises. */
+#define NC_MMA_ROWS 10
+int    nc_mma_update(nc_ctx* ctx, int iter, double* x_dev, const double* dfdx_dev, double g, const double* dgdx_dev,
+                     double move, double* state_dev, double* lambda_host);
+
 /* Optional per-context timing of the solver's kernels with HIP events on the context's
  * stream (a tracing aid; adds one event pair per timed launch).  nc_set_timing(ctx, 1)
  * creates the events (once) and zeroes the counters; 0 turns timing off.

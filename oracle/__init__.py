@@ -19,7 +19,8 @@ What it computes (all in float64, plain and unblocked):
 * the adjoint solve with the transposed factorisation and the design
   sensitivities -lambda^T dR/dgamma (Sec. 5.1, adjoint sensitivity analysis);
 * the closed-form permeability tuning of Sec. 3 (eqs. nusselt1-nusselt5);
-* the Method of Moving Asymptotes for the volume-constrained design update (Sec. 5.1).
+* the Method of Moving Asymptotes for the volume-constrained design update (Sec. 5.1),
+  and the design loop of Sec. 5 around it (continuation, warm starts, Q ramping).
 
 Parity status: every function is pinned by tests under tests/ (closed forms,
 invariants, brute-force finite differences, the paper's Table tab:2); the SUPG
@@ -34,6 +35,7 @@ from .element import element_residual, reference_element
 from .pde_filter import PDEFilter, pde_length_scale
 from .fem import Model
 from .mma import MMA
+from . import design
 
 __all__ = [
     "Params", "Mesh", "default_constraints", "patch_flux",

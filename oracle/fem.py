@@ -169,8 +169,10 @@ class Model:
             if verbose:
                 print(f"newton {it}: |R|={hist['res'][-1]:.3e} lam={lam} step={max(rel):.3e}")
             if lam == 1.0 and max(rel) <= step_rtol:
+                hist["converged"] = True
                 break
         hist["its"] = it + 1
+        hist.setdefault("converged", False)
         self.timing.update(state_assembly=t_asm, state_factor=t_fac, state_solve=t_sol)
         return s, hist
 

@@ -170,6 +170,21 @@ struct Regions {
 void launch_passive(hipStream_t st, const Grid& g, const Regions& rg, double* gamma);
 // a = 0 off the design domain (set: a = fill on it, 0 off it)
 void launch_design_mask(hipStream_t st, const Grid& g, const Regions& rg, double* a, bool set, double fill);
+// ---- MMA design update (k_mma.hip); the caller's state holds NC_MMA_ROWS rows of E:
+// previous two iterates, asymptotes, subproblem bounds, approximation coefficients
+constexpr int MMA_CAND = 32;
+struct MmaCand {
+  double v[MMA_CAND];   // multipliers evaluated by one pass (inf: the limit lambda -> inf)
+};
+// coefficients of the subproblem at x; out[0] = sum of the constraint approximation at x
+void launch_mma_prepare(hipStream_t st, const Grid& g, const Regions& rg, int iter, double move, double xmin,
+                        double xmax, const double* x, const double* df, const double* dg, double* state, double* part,
+                        double* out);
+// out[c] = constraint approximation at x(lambda_c) (without its right-hand side)
+void launch_mma_dual(hipStream_t st, const Grid& g, const Regions& rg, const MmaCand& lam, const double* state,
+                     double* part, double* out);
+void launch_mma_apply(hipStream_t st, const Grid& g, const Regions& rg, int iter, double lam, double* x, double* state);
+
 // out[0] = sum of gamma over the design domain
 void launch_design_sum(hipStream_t st, const Grid& g, const Regions& rg, const double* gamma, double* part,
                        double* out);

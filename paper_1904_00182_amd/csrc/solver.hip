@@ -70,6 +70,8 @@ inline void ck(hipError_t e) {
 struct nc_ctx {
   nc_problem p;
   hipStream_t stream;
+  char* ws_base;         // the caller's workspace (aligned) and the bytes the layout uses
+  size_t ws_need;
   bool mixed;
   int L;
   Level lev[MAXLEV];
@@ -1190,6 +1192,8 @@ int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stre
     const size_t mis = (size_t)((uintptr_t)base % ALIGN);
     if (mis) base += ALIGN - mis;
     carve(c, base);
+    c->ws_base = base;
+    c->ws_need = need;
     c->stream = (hipStream_t)stream;
     c->patch = Patch{c->p.q_h, c->p.patch_x0, c->p.patch_x1, c->p.patch_y0, c->p.patch_y1, c->p.h};
     c->design_set = false;
@@ -1223,6 +1227,93 @@ int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stre
       return NC_EHIP;
     }
     *out = c;
+    return NC_OK;
+  });
+}
+
+int nc_set_problem(nc_ctx* c, const nc_problem* p) {
+  if (!c || !valid_problem(p)) return NC_EINVAL;
+  return guarded([&]() {
+    nc_ctx tmp;
+    tmp.p = *p;
+    if (tmp.p.h <= 0) tmp.p.h = 1.0 / p->nx;
+    const size_t need = carve(&tmp, nullptr);
+    bool same = need == c->ws_need && tmp.L == c->L && tmp.pde == c->pde && tmp.mixed == c->mixed && tmp.m == c->m &&
+                tmp.dense == c->dense;
+    for (int l = 0; same && l < c->L; ++l)
+      same = tmp.lev[l].g.nx == c->lev[l].g.nx && tmp.lev[l].g.ny == c->lev[l].g.ny && tmp.lev[l].g.nz == c->lev[l].g.nz;
+    if (!same) return NC_EINVAL;
+    // the setup streams may still read what the new parameters replace
+    join_coarse(c);
+    join_levels(c);
+    c->p = tmp.p;
+    carve(c, c->ws_base);   // the same layout: recomputes the level constants and regions only
+    c->patch = Patch{c->p.q_h, c->p.patch_x0, c->p.patch_x1, c->p.patch_y0, c->p.patch_y1, c->p.h};
+    c->omega = c->p.smooth_omega;
+    c->design_set = false;
+    c->hier_valid = false;
+    c->rows_valid = false;
+    return NC_OK;
+  });
+}
+
+int nc_mma_update(nc_ctx* c, int iter, double* x, const double* dfdx, double g, const double* dgdx, double move,
+                  double* state, double* lambda) {
+  if (!c || !x || !dfdx || !dgdx || !state || iter < 1 || !(move > 0.0) || !std::isfinite(g)) return NC_EINVAL;
+  if (c->n_design == 0) return NC_EINVAL;
+  return guarded([&]() {
+    hipStream_t st = c->stream;
+    const Grid& gr = c->lev[0].g;
+    launch_mma_prepare(st, gr, c->reg, iter, move, 0.0, 1.0, x, dfdx, dgdx, state, c->part, c->dres);
+    fetch(c, c->dres, 1);
+    const double b = c->hbuf[0] - g;   // the approximation at x equals g there
+    // constraint approximation minus b at MMA_CAND multipliers
+    auto eval = [&](const MmaCand& cand, double* con) {
+      launch_mma_dual(st, gr, c->reg, cand, state, c->part, c->dres);
+      fetch(c, c->dres, MMA_CAND);
+      for (int k = 0; k < MMA_CAND; ++k) con[k] = c->hbuf[k] - b;
+    };
+    double con[MMA_CAND];
+    MmaCand cand;
+    // first pass: 0, a geometric grid over 1e-30 .. 1e30, and the limit lambda -> inf
+    cand.v[0] = 0.0;
+    for (int k = 1; k < MMA_CAND - 1; ++k) cand.v[k] = std::pow(10.0, -30.0 + 60.0 * (k - 1) / (MMA_CAND - 3));
+    cand.v[MMA_CAND - 1] = INFINITY;
+    eval(cand, con);
+    double lam;
+    if (!std::isfinite(con[0]) || !std::isfinite(con[MMA_CAND - 1])) throw HipError{hipErrorUnknown};
+    if (con[0] <= 0.0) {
+      lam = 0.0;
+    } else if (con[MMA_CAND - 1] > 0.0) {
+      lam = INFINITY;   // no point of the box satisfies the approximation: reduce it most
+    } else {
+      // bracket [lo, hi]: con(lo) > 0 >= con(hi); narrowed geometrically while it spans
+      // more than a factor 2, then linearly, to a relative width of 1e-15
+      int k = 1;
+      while (con[k] > 0.0) ++k;
+      double lo = cand.v[k - 1], hi = cand.v[k];
+      for (int pass = 0; pass < 60 && hi - lo > 1e-15 * hi; ++pass) {
+        const bool geo = lo > 0.0 && hi > 2.0 * lo;
+        const double l0 = lo > 0.0 ? lo : hi * 1e-30;
+        for (int m = 0; m < MMA_CAND; ++m) {
+          const double t = (m + 1.0) / (MMA_CAND + 1.0);
+          cand.v[m] = geo || lo == 0.0 ? l0 * std::pow(hi / l0, t) : lo + (hi - lo) * t;
+        }
+        eval(cand, con);
+        double nlo = lo, nhi = hi;
+        for (int m = 0; m < MMA_CAND; ++m) {
+          if (con[m] > 0.0) nlo = cand.v[m];
+          else { nhi = cand.v[m]; break; }
+        }
+        lo = nlo;
+        hi = nhi;
+      }
+      lam = hi;
+    }
+    launch_mma_apply(st, gr, c->reg, iter, lam, x, state);
+    ck(hipGetLastError());
+    sync(c);
+    if (lambda) *lambda = lam;
     return NC_OK;
   });
 }

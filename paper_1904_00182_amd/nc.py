@@ -18,12 +18,13 @@ NC_FP64, NC_MIXED = 0, 1
 NC_DENSE_MAX = 2000   # largest coarsest-grid system inverted densely
 NC_HIST_MAX = 32      # Newton steps / refinement sweeps recorded per solve
 NC_FILTER_CONE, NC_FILTER_PDE = 0, 1
+NC_MMA_ROWS = 10
 
 EXPORTED = [
     "nc_problem_default", "nc_workspace_bytes", "nc_create", "nc_destroy", "nc_status_string",
     "nc_set_design", "nc_get_gamma", "nc_filter_apply", "nc_residual", "nc_linearize", "nc_jac_apply", "nc_jacT_apply",
     "nc_jac_apply_f32", "nc_jacT_apply_f32", "nc_solve_state", "nc_objective", "nc_objective_grad",
-    "nc_solve_adjoint", "nc_sensitivity", "nc_objective_sensitivity", "nc_volume", "nc_precondition", "nc_cone_filter", "nc_dense_inverse",
+    "nc_solve_adjoint", "nc_sensitivity", "nc_objective_sensitivity", "nc_volume", "nc_set_problem", "nc_mma_update", "nc_precondition", "nc_cone_filter", "nc_dense_inverse",
     "nc_dense_inverse_noalloc", "nc_set_timing", "nc_get_timing",
 ]
 
@@ -111,6 +112,8 @@ def load():
             "nc_objective_grad": (I, [V, V, V]),
             "nc_objective_sensitivity": (I, [V, V, V, V, V]),
             "nc_volume": (I, [V, ctypes.POINTER(D), V]),
+            "nc_set_problem": (I, [V, P]),
+            "nc_mma_update": (I, [V, I, V, V, D, V, D, V, ctypes.POINTER(D)]),
             "nc_solve_adjoint": (I, [V, V, V, V, ctypes.POINTER(NCInfo)]),
             "nc_sensitivity": (I, [V, V, V, V, V]),
             "nc_cone_filter": (I, [I, I, I, D, V, V, I, V]),
@@ -130,6 +133,19 @@ def load():
 def default_problem(nx, ny, nz, **overrides):
     p = NCProblem()
     load().nc_problem_default(ctypes.byref(p), nx, ny, nz)
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        if k in ("q_box", "solid_box", "design_box"):
+            v = (ctypes.c_double * 6)(*v)
+        setattr(p, k, v)
+    return p
+
+
+def copy_problem(problem, **overrides):
+    """A copy of an NCProblem with some fields replaced."""
+    p = NCProblem()
+    ctypes.memmove(ctypes.byref(p), ctypes.byref(problem), ctypes.sizeof(NCProblem))
     for k, v in overrides.items():
         if not hasattr(p, k):
             raise KeyError(k)
@@ -305,6 +321,26 @@ class Solver:
         self.last_info = info.as_dict()
         self.last_info["status"] = st
         return lam
+
+    def set_problem(self, problem):
+        """Replace the context's parameters (same grid and layout) via nc_set_problem; the
+        design must be set again afterwards."""
+        _check(self.lib.nc_set_problem(self.ctx, ctypes.byref(problem)), "nc_set_problem")
+        self.p = problem
+
+    def mma_state(self):
+        """A zeroed MMA state array (NC_MMA_ROWS x E) for mma_update."""
+        return torch.zeros((NC_MMA_ROWS, self.E), dtype=torch.float64, device=self.device)
+
+    def mma_update(self, it, x, dfdx, g, dgdx, move, state):
+        """One MMA iteration on the design elements (x updated in place); returns lambda."""
+        lam = ctypes.c_double()
+        for t in (x, dfdx, dgdx, state):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("mma_update needs contiguous float64 tensors on the solver's device")
+        _check(self.lib.nc_mma_update(self.ctx, int(it), _ptr(x), _ptr(dfdx), float(g), _ptr(dgdx), float(move),
+                                      _ptr(state), ctypes.byref(lam)), "nc_mma_update")
+        return lam.value
 
     def set_timing(self, enable=True):
         _check(self.lib.nc_set_timing(self.ctx, 1 if enable else 0), "nc_set_timing")
