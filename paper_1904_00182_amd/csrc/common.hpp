@@ -56,6 +56,8 @@ struct LayerRef {
 struct Grid {
   int nx, ny, nz;
   int sym = 0;   // bit 0: the wall x = Lx is a symmetry plane, bit 1: the wall y = Ly
+  // the index of the x (y) wall where T is held, -1 when that wall is a symmetry plane
+  int tx = (sym & 1) ? -1 : nx, ty = (sym & 2) ? -1 : ny;
   __host__ __device__ long nodes() const { return (long)(nx + 1) * (ny + 1) * (nz + 1); }
   __host__ __device__ long elems() const { return (long)nx * ny * nz; }
   // 32-bit indices: grids are limited to fewer than 2^31 / 5 nodes (checked at context creation)
@@ -80,11 +82,9 @@ struct Grid {
   // Dirichlet sets of the cavity: T on the vertical walls and the top (a symmetry plane is
   // insulated instead), P at (0, 0, nz), and the normal velocity on a symmetry plane (its
   // projection there is the mean over both sides of an odd field).
-  __host__ __device__ bool tfix(int i, int j, int k) const {
-    return i == 0 || (i == nx && !(sym & 1)) || j == 0 || (j == ny && !(sym & 2)) || k == nz;
-  }
+  __host__ __device__ bool tfix(int i, int j, int k) const { return i == 0 || i == tx || j == 0 || j == ty || k == nz; }
   __host__ __device__ bool ufix(int i, int j, int d) const {
-    return (d == 0 && (sym & 1) && i == nx) || (d == 1 && (sym & 2) && j == ny);
+    return (d == 0 && tx < 0 && i == nx) || (d == 1 && ty < 0 && j == ny);
   }
   __host__ __device__ bool pfix(int i, int j, int k) const { return i == 0 && j == 0 && k == nz; }
   // number of elements sharing node (i, j, k)

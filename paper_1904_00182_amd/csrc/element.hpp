@@ -43,6 +43,7 @@ struct ElemConst {
   int qi0, qi1, qj0, qj1, qk0, qk1;   // element index ranges (inclusive) carrying Q
   // the volumetric source of element (i, j, k)
   NC_HD T source(int i, int j, int k) const {
+    if (Q == (T)0) return (T)0;   // uniform: no source, no per-element test
     return (i >= qi0 && i <= qi1 && j >= qj0 && j <= qj1 && k >= qk0 && k <= qk1) ? Q : (T)0;
   }
 };

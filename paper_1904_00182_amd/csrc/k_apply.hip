@@ -421,8 +421,10 @@ void launch_residual(hipStream_t st, const Grid& g, const ElemConst<double>& c, 
 
 // ------------------------------------------------------------------ Jacobian applies
 // NF: fields per node of the direction/output arrays (5 on the fine level, 2 in the
-// (P, T) multigrid hierarchy).
-template <typename T, int NF, int MODE>
+// (P, T) multigrid hierarchy).  XP: the level has a volumetric source or symmetry planes
+// (per-element source, symmetry-plane velocity rows); without them the element code is the
+// plain cavity's, with no per-element tests in the loop.
+template <typename T, int NF, int MODE, bool XP = false>
 struct JvOp {
   using real = T;
   static constexpr int MIN_WAVES = 2;   // two waves per SIMD also for the float64 five-field applies
@@ -465,7 +467,7 @@ struct JvOp {
     for (int a = 0; a < 8; ++a) { P[a] = nd[a][0]; Tn[a] = nd[a][1]; p[a] = nd[a][2]; t[a] = nd[a][3]; }
     const auto kc = g.elayer(coef, 2, k).template ld<typename Pair<T>::type>(2 * g.ecol(i, j));
     LinM<T> L;
-    lin_modal_q(P, Tn, kc.x, kc.y, c.source(i, j, k), c, L);
+    lin_modal_q(P, Tn, kc.x, kc.y, XP ? c.source(i, j, k) : (T)0, c, L);
     T yP[8] = {0}, yT[8] = {0}, yU[3][8] = {{0}};
     elem_jv_m<T, NF == 5>(L, p, t, c, yP, yT, yU);
 #pragma unroll
@@ -505,7 +507,7 @@ struct JvOp {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const T xd = xk.template ld<T>(5 * n + d);
-        yk.template st<T>(5 * n + d, rs.s[d] * (g.ufix(i, j, d) ? xd : v[d] + M * xd));
+        yk.template st<T>(5 * n + d, rs.s[d] * (XP && g.ufix(i, j, d) ? xd : v[d] + M * xd));
       }
       const T ap = pf ? xk.template ld<T>(5 * n + 3) : v[3];
       const T at = tf ? xk.template ld<T>(5 * n + 4) : v[4];
@@ -532,7 +534,7 @@ struct JvOp {
   }
 };
 
-template <typename T, int NF, int MODE>
+template <typename T, int NF, int MODE, bool XP = false>
 struct JtwOp {
   using real = T;
   static constexpr int MIN_WAVES = 2;   // two waves per SIMD also for the float64 five-field applies
@@ -562,7 +564,7 @@ struct JtwOp {
       p = xk.template ld<T>(NF * n + NF - 2);
       t = xk.template ld<T>(NF * n + NF - 1);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) in[4 + d] = g.ufix(i, j, d) ? (T)0 : xk.template ld<T>(5 * n + d);
+      for (int d = 0; d < 3; ++d) in[4 + d] = XP && g.ufix(i, j, d) ? (T)0 : xk.template ld<T>(5 * n + d);
     }
     if (g.pfix(i, j, k)) p = (T)0;
     if (g.tfix(i, j, k)) t = (T)0;
@@ -580,7 +582,7 @@ struct JtwOp {
     }
     const auto kc = g.elayer(coef, 2, k).template ld<typename Pair<T>::type>(2 * g.ecol(i, j));
     LinM<T> L;
-    lin_modal_q(P, Tn, kc.x, kc.y, c.source(i, j, k), c, L);
+    lin_modal_q(P, Tn, kc.x, kc.y, XP ? c.source(i, j, k) : (T)0, c, L);
     T yP[8] = {0}, yT[8] = {0};
     elem_jtw_m<T, NF == 5>(L, wP, wT, wU, c, yP, yT);
 #pragma unroll
@@ -616,7 +618,7 @@ struct JtwOp {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const T xd = xk.template ld<T>(5 * n + d);
-        yk.template st<T>(5 * n + d, rs.s[d] * (g.ufix(i, j, d) ? xd : M * xd));
+        yk.template st<T>(5 * n + d, rs.s[d] * (XP && g.ufix(i, j, d) ? xd : M * xd));
       }
       const T ap = pf ? xk.template ld<T>(5 * n + 3) : v[0];
       const T at = tf ? xk.template ld<T>(5 * n + 4) : v[1];
@@ -648,38 +650,63 @@ static Scale5<T> ones_or(const Scale5<T>* s) {
   return s ? *s : Scale5<T>{{(T)1, (T)1, (T)1, (T)1, (T)1}};
 }
 
+// whether a level needs the extended element code (source or symmetry planes)
+template <typename T>
+static bool extended(const LevelView<T>& L) { return L.c.Q != (T)0 || L.g.sym != 0; }
+
 template <typename T>
 void launch_jv5(hipStream_t st, const LevelView<T>& L, const T* x, T* y, const Scale5<T>* rows) {
-  JvOp<T, 5, MODE_STORE> op{L.g, L.c, L.coef, L.st, x, nullptr, nullptr, y, (T)0, ones_or(rows)};
-  run_zmarch(st, op);
+  if (extended(L)) {
+    JvOp<T, 5, MODE_STORE, true> op{L.g, L.c, L.coef, L.st, x, nullptr, nullptr, y, (T)0, ones_or(rows)};
+    run_zmarch(st, op);
+  } else {
+    JvOp<T, 5, MODE_STORE> op{L.g, L.c, L.coef, L.st, x, nullptr, nullptr, y, (T)0, ones_or(rows)};
+    run_zmarch(st, op);
+  }
 }
 template <typename T>
 void launch_jtw5(hipStream_t st, const LevelView<T>& L, const T* w, T* y, const Scale5<T>* rows) {
-  JtwOp<T, 5, MODE_STORE> op{L.g, L.c, L.coef, L.st, w, nullptr, nullptr, y, (T)0, ones_or(rows)};
-  run_zmarch(st, op);
+  if (extended(L)) {
+    JtwOp<T, 5, MODE_STORE, true> op{L.g, L.c, L.coef, L.st, w, nullptr, nullptr, y, (T)0, ones_or(rows)};
+    run_zmarch(st, op);
+  } else {
+    JtwOp<T, 5, MODE_STORE> op{L.g, L.c, L.coef, L.st, w, nullptr, nullptr, y, (T)0, ones_or(rows)};
+    run_zmarch(st, op);
+  }
 }
 
 // y = D J_PT x (J_PT^T when transposed) on the finest grid: the (P, T) block of the
 // Jacobian, constrained rows and columns the identity, rows scaled by rows->s[3], s[4]
 template <typename T>
 void launch_pt_store(hipStream_t st, const LevelView<T>& L, bool transpose, const T* x, T* y, const Scale5<T>* rows) {
-  if (!transpose) {
-    JvOp<T, 2, MODE_STORE> op{L.g, L.c, L.coef, L.st, x, nullptr, nullptr, y, (T)0, ones_or(rows)};
-    run_zmarch<JvOp<T, 2, MODE_STORE>, 1>(st, op);
-  } else {
-    JtwOp<T, 2, MODE_STORE> op{L.g, L.c, L.coef, L.st, x, nullptr, nullptr, y, (T)0, ones_or(rows)};
-    run_zmarch<JtwOp<T, 2, MODE_STORE>, 1>(st, op);
+#define NC_STORE(OP, X)                                                                     \
+  {                                                                                         \
+    OP<T, 2, MODE_STORE, X> op{L.g, L.c, L.coef, L.st, x, nullptr, nullptr, y, (T)0, ones_or(rows)}; \
+    run_zmarch<OP<T, 2, MODE_STORE, X>, 1>(st, op);                                          \
   }
+  const bool xp = extended(L);
+  if (!transpose) {
+    if (xp) NC_STORE(JvOp, true) else NC_STORE(JvOp, false)
+  } else {
+    if (xp) NC_STORE(JtwOp, true) else NC_STORE(JtwOp, false)
+  }
+#undef NC_STORE
 }
 
 template <typename T>
 void launch_pt_apply(hipStream_t st, const LevelView<T>& L, bool transpose, int mode, const T* x, const T* b, T* y,
                      T omega, bool fine) {
-#define NC_PT(OP, M)                                                              \
-  {                                                                             \
-    OP<T, 2, M> op{L.g, L.c, L.coef, L.st, x, b, L.dinv, y, omega, ones_or<T>(nullptr)}; \
-    if (fine) run_zmarch<OP<T, 2, M>, 1>(st, op); else run_zmarch<OP<T, 2, M>, 0>(st, op); \
+#define NC_PTX(OP, M, X)                                                                     \
+  {                                                                                         \
+    OP<T, 2, M, X> op{L.g, L.c, L.coef, L.st, x, b, L.dinv, y, omega, ones_or<T>(nullptr)};  \
+    if (fine) run_zmarch<OP<T, 2, M, X>, 1>(st, op); else run_zmarch<OP<T, 2, M, X>, 0>(st, op); \
   }
+#define NC_PT(OP, M)                      \
+  {                                       \
+    if (xp) NC_PTX(OP, M, true)           \
+    else NC_PTX(OP, M, false)             \
+  }
+  const bool xp = extended(L);
   if (!transpose) {
     if (mode == MODE_STORE) NC_PT(JvOp, MODE_STORE)
     else if (mode == MODE_RESID) NC_PT(JvOp, MODE_RESID)
@@ -690,6 +717,7 @@ void launch_pt_apply(hipStream_t st, const LevelView<T>& L, bool transpose, int 
     else NC_PT(JtwOp, MODE_SMOOTH)
   }
 #undef NC_PT
+#undef NC_PTX
 }
 
 // ------------------------------------------------------------------ bottom of the V-cycle
@@ -753,7 +781,7 @@ struct TailIdx {
   }
 };
 
-template <typename T, bool TR, bool PF>
+template <typename T, bool TR, bool PF, bool XP>
 __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs<T> a) {
   extern __shared__ __align__(16) unsigned char tail_smem[];
   const Grid g = a.lv.g, gc = a.gc, gu = a.gu;
@@ -812,7 +840,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void tail_cycle_kernel(const TailArgs
         w[c8] = g.tfix(ni, nj, nk) ? (T)0 : x[2 * n + 1];
       }
       LinM<T> L;
-      lin_modal_q(P, Tn, CO[2 * e], CO[2 * e + 1], a.lv.c.source(i, j, k), a.lv.c, L);
+      lin_modal_q(P, Tn, CO[2 * e], CO[2 * e + 1], XP ? a.lv.c.source(i, j, k) : (T)0, a.lv.c, L);
       T yP[8] = {0}, yT[8] = {0}, yU[3][8] = {{0}};
       if constexpr (TR) elem_jtw_m<T, false>(L, p, w, yU, a.lv.c, yP, yT);
       else elem_jv_m<T, false>(L, p, w, a.lv.c, yP, yT, yU);
@@ -937,12 +965,25 @@ void launch_tail_cycle(hipStream_t st, const Grid& gu, const T* ru, T* xu, const
   const bool pf = tail_lds_bytes<T>(L.g, gc, true) <= TAIL_LDS_MAX;
   const size_t lds = tail_lds_bytes<T>(L.g, gc, pf);
   const dim3 grid(1), block(TAIL_THREADS);
+  // XP: the level carries a volumetric source (symmetry planes change only the constraint
+  // sets of the (P, T) system, which the grid's predicates cover)
+  const bool xp = L.c.Q != (T)0;
   if (transpose) {
-    if (pf) launch(tail_cycle_kernel<T, true, true>, grid, block, lds, st, a);
-    else launch(tail_cycle_kernel<T, true, false>, grid, block, lds, st, a);
+    if (pf) {
+      if (xp) launch(tail_cycle_kernel<T, true, true, true>, grid, block, lds, st, a);
+      else launch(tail_cycle_kernel<T, true, true, false>, grid, block, lds, st, a);
+    } else {
+      if (xp) launch(tail_cycle_kernel<T, true, false, true>, grid, block, lds, st, a);
+      else launch(tail_cycle_kernel<T, true, false, false>, grid, block, lds, st, a);
+    }
   } else {
-    if (pf) launch(tail_cycle_kernel<T, false, true>, grid, block, lds, st, a);
-    else launch(tail_cycle_kernel<T, false, false>, grid, block, lds, st, a);
+    if (pf) {
+      if (xp) launch(tail_cycle_kernel<T, false, true, true>, grid, block, lds, st, a);
+      else launch(tail_cycle_kernel<T, false, true, false>, grid, block, lds, st, a);
+    } else {
+      if (xp) launch(tail_cycle_kernel<T, false, false, true>, grid, block, lds, st, a);
+      else launch(tail_cycle_kernel<T, false, false, false>, grid, block, lds, st, a);
+    }
   }
 }
 

@@ -80,8 +80,8 @@ def optimize(problem, x0, iterations, g_star=0.05, move=0.2, every=100, continua
         mult = sol.mma_update(it + 1, x, dfdx / f0, frac - g_star, dv, move, state)
         torch.cuda.synchronize(sol.device)
         h = dict(it=it, f=f, frac=frac, lam=mult, ramped=ramped, newton=info["newton_its"],
-                 state_krylov=info["krylov_its"], adjoint_krylov=ainfo["krylov_its"],
-                 seconds=time.perf_counter() - t0)
+                 state_krylov=info["krylov_its"], adjoint_krylov=ainfo["krylov_its"], state_s=info["t_total"],
+                 adjoint_s=ainfo["t_total"], seconds=time.perf_counter() - t0)
         if keep_designs:
             h["x"] = x.cpu().numpy().copy()
         hist.append(h)

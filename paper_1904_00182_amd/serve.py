@@ -7,7 +7,14 @@ state, adjoint, design and gradient arrays) fits under the memory cap; admitted
 requests run concurrently, each on its own HIP stream and host worker thread, so their
 kernels overlap on the device, and their state stays resident in HBM between the state
 solve and the adjoint solve.  Requests that do not fit wait in arrival order; a request
-that can never fit is rejected.  Latency is measured from arrival to completion.
+that can never fit is rejected.  Latency is measured from arrival to completion (the
+moment its results are on the device and its stream has drained).
+
+Each slot keeps its solver contexts, one per (grid, precision), and serves a new
+request on a kept context through nc_set_problem: no context is created or destroyed
+per request (destroying one frees pinned host memory, which waits for the whole
+device).  A request whose state or adjoint solve does not converge is recorded as
+such and counted neither as completed nor in the latency percentiles.
 
 The scheduling core (`Scheduler`) is independent of the GPU: it drives any backend with
 `footprint(req)` and `run(req, slot)` methods, which lets the CPU test-suite exercise it
@@ -61,7 +68,7 @@ class Scheduler:
     def _worker(self, req, slot, fp):
         try:
             req.result = self.backend.run(req, slot) or {}
-            req.status = "done"
+            req.status = req.result.pop("status", "done")
         except Exception as e:  # the failure is recorded on the request
             req.status = f"failed: {e}"
         with self.lock:
@@ -124,6 +131,7 @@ def summarize(requests, wall):
         "completed": len(done),
         "rejected": sum(1 for r in requests if r.status.startswith("rejected")),
         "failed": sum(1 for r in requests if r.status.startswith("failed")),
+        "not_converged": sum(1 for r in requests if r.status == "not converged"),
         "p50_s": float(np.percentile(lat, 50)),
         "p99_s": float(np.percentile(lat, 99)),
         "mean_s": float(lat.mean()),
@@ -134,9 +142,10 @@ def summarize(requests, wall):
 
 class GPUBackend:
     """Runs one request as: design generation, state solve, adjoint solve and
-    sensitivities on its own stream, keeping the arrays resident until done."""
+    sensitivities on its slot's stream, keeping the arrays resident until done.
+    force_precision overrides every request's precision (the plain float64 baseline)."""
 
-    def __init__(self, device="cuda:0", slots=4, keep_results=False):
+    def __init__(self, device="cuda:0", slots=4, keep_results=False, force_precision=None):
         import torch
         from . import nc
         self.torch = torch
@@ -144,10 +153,27 @@ class GPUBackend:
         self.device = device
         self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
         self.keep = keep_results
+        self.force = force_precision
+        self.pools = [dict() for _ in range(slots)]   # per slot: (grid, precision) -> Solver
+
+    def precision(self, req):
+        return req.precision if self.force is None else self.force
 
     def problem(self, req):
         from . import workloads
-        return workloads.problem(req.grid, req.gr, precision=req.precision, q_h=req.q_h)
+        return workloads.problem(req.grid, req.gr, precision=self.precision(req), q_h=req.q_h)
+
+    def solver(self, req, slot):
+        """The slot's kept context for the request's layout, set to its parameters."""
+        p = self.problem(req)
+        key = (tuple(req.grid), self.precision(req))
+        sol = self.pools[slot].get(key)
+        if sol is None:
+            sol = self.nc.Solver(p, self.device, stream=self.streams[slot])
+            self.pools[slot][key] = sol
+        else:
+            sol.set_problem(p)
+        return sol
 
     def footprint(self, req):
         nx, ny, nz = req.grid
@@ -160,9 +186,8 @@ class GPUBackend:
         from . import workloads
         st = self.streams[slot]
         with torch.cuda.stream(st):
-            p = self.problem(req)
             x = workloads.design(req.grid, "blobs", req.design_seed, self.device)
-            sol = nc.Solver(p, self.device, stream=st)
+            sol = self.solver(req, slot)
             sol.set_design(x)
             s = sol.solve_state()
             i_state = dict(sol.last_info)
@@ -172,11 +197,17 @@ class GPUBackend:
             dfdx = sol.sensitivity(s, lam)
             f = sol.objective(s)
             st.synchronize()
-            out = {"f": f, "state": i_state, "adjoint": i_adj}
+            ok = i_state["status"] == nc.NC_OK and i_adj["status"] == nc.NC_OK
+            out = {"f": f, "state": i_state, "adjoint": i_adj, "status": "done" if ok else "not converged"}
             if self.keep:
                 out.update(s=s.cpu(), lam=lam.cpu(), dfdx=dfdx.cpu())
-            sol.close()
             return out
+
+    def close(self):
+        for pool in self.pools:
+            for sol in pool.values():
+                sol.close()
+            pool.clear()
 
 
 def make_requests(n, rate, seed=4, grids=((16, 8, 16), (32, 16, 32), (64, 32, 64), (96, 48, 96)),
@@ -193,39 +224,55 @@ def make_requests(n, rate, seed=4, grids=((16, 8, 16), (32, 16, 32), (64, 32, 64
     return out
 
 
-def run(n=256, rate=None, slots=4, mem_cap=16 << 30, seed=4, device="cuda:0", log=print):
-    """Serve n requests with continuous batching (slots concurrent) and, for reference, the
-    same trace FIFO one at a time.  With rate=None the arrival rate is set to 0.8 x the
-    measured one-at-a-time capacity for the mix.  Returns a dict of both summaries."""
+def _warm(be, slots):
+    """Creates every slot's contexts for the mix's grids and precisions (one small solve
+    each), so that measured requests find them kept."""
+    for slot in range(slots):
+        for i, gsz in enumerate(((16, 8, 16), (32, 16, 32), (64, 32, 64), (96, 48, 96))):
+            for prec in (0, 1):
+                be.run(Request(-1 - i, 0.0, gsz, 1e3, 1.0, 999, prec), slot)
+
+
+def run(n=256, rate=None, load=1.5, slots=4, mem_cap=16 << 30, seed=4, device="cuda:0", log=print):
+    """Serve n requests of the mixed-size, mixed-precision trace with continuous batching
+    (`slots` concurrent requests, each on its own stream) and, as the baseline, the same
+    trace served FIFO one at a time with the plain float64 solve.  With rate=None the
+    arrival rate is `load` x the measured one-at-a-time capacity of the mix (load > 1:
+    saturation, where throughput can differ).  Returns both summaries."""
     import torch
     be = GPUBackend(device, slots)
-    # warm-up: one request of each grid (compiles nothing, but pages in kernels and pools)
-    for i, gsz in enumerate(((16, 8, 16), (32, 16, 32), (64, 32, 64), (96, 48, 96))):
-        be.run(Request(-1 - i, 0.0, gsz, 1e3, 1.0, 999, 0), 0)
+    base = GPUBackend(device, 1, force_precision=0)
+    _warm(be, slots)
+    _warm(base, 1)
     torch.cuda.synchronize()
+    probe = make_requests(24, 1e9, seed + 7)
+    t0 = time.perf_counter()
+    for r in probe:
+        be.run(r, 0)
+    cap = len(probe) / (time.perf_counter() - t0)
     if rate is None:
-        probe = make_requests(16, 1e9, seed + 7)
-        t0 = time.perf_counter()
-        for r in probe:
-            be.run(r, 0)
-        cap = len(probe) / (time.perf_counter() - t0)
-        rate = 0.8 * cap
-        log(f"one-at-a-time capacity {cap:.1f} solves/s -> arrival rate {rate:.1f}/s")
-    res = {"arrival_rate_per_s": rate, "requests": n, "slots": slots, "mem_cap_bytes": mem_cap}
-    for label, sl in (("continuous", slots), ("fifo_serial", 1)):
+        rate = load * cap
+    log(f"one-at-a-time capacity {cap:.1f} solves/s -> arrival rate {rate:.1f}/s")
+    res = {"arrival_rate_per_s": round(rate, 2), "one_at_a_time_capacity_per_s": round(cap, 2), "requests": n,
+           "slots": slots, "mem_cap_bytes": mem_cap,
+           "trace": "Poisson arrivals; grids 16x8x16 .. 96x48x96, Gr 1e3 / 1e4, q_h ~ U(0.5, 2), blob design "
+                    "seed 1000 + r, float64 or mixed with probability 1/2 (the baseline solves all in float64)"}
+    for label, backend, sl in (("continuous", be, slots), ("fifo_serial_fp64", base, 1)):
         reqs = make_requests(n, rate, seed)
-        sch = Scheduler(be, slots=sl, mem_cap=mem_cap)
+        sch = Scheduler(backend, slots=sl, mem_cap=mem_cap)
         t0 = time.perf_counter()
         sch.serve(reqs)
         wall = time.perf_counter() - t0
         s = summarize(reqs, wall)
         for prec, nm in ((0, "fp64"), (1, "mixed")):
             lat = [r.latency for r in reqs if r.status == "done" and r.precision == prec]
-            if lat:
+            if lat and label == "continuous":
                 s[f"p50_s_{nm}"] = float(np.percentile(lat, 50))
                 s[f"p99_s_{nm}"] = float(np.percentile(lat, 99))
-        res[label] = s
-        log(label, s)
+        res[label] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+        log(label, res[label])
+    be.close()
+    base.close()
     return res
 
 

@@ -85,3 +85,22 @@ def benchmark_problem(n, alpha=1e3, precision=nc.NC_FP64, kappa_s=1e-5, q_c=8.81
                   design_box=BENCH_DESIGN)
     fields.update(over)
     return nc.default_problem(n, n, 2 * n, **fields)
+
+
+def benchmark_start_design(p, device="cuda:0"):
+    """The paper's initial design for the benchmark (Sec. 6.1): 0.05 on the design elements,
+    1 on the passive solid block, 0 on the passive fluid (membership by element centre)."""
+    import numpy as np
+    nx, ny, nz, h = p.nx, p.ny, p.nz, p.h
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    c = np.stack([(i.ravel() + 0.5) * h, (j.ravel() + 0.5) * h, (k.ravel() + 0.5) * h], axis=1)
+
+    def inside(box):
+        b = [float(v) for v in box]
+        return ((c[:, 0] >= b[0]) & (c[:, 0] <= b[1]) & (c[:, 1] >= b[2]) & (c[:, 1] <= b[3])
+                & (c[:, 2] >= b[4]) & (c[:, 2] <= b[5]))
+
+    solid = inside(p.solid_box)
+    des = inside(p.design_box) & ~solid
+    x = np.where(solid, 1.0, np.where(des, 0.05, 0.0))
+    return torch.as_tensor(x, device=device)

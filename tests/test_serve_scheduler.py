@@ -10,10 +10,11 @@ from paper_1904_00182_amd.serve import Request, Scheduler, summarize
 
 
 class FakeBackend:
-    def __init__(self, cost, footprint, fail_ids=()):
+    def __init__(self, cost, footprint, fail_ids=(), unconverged_ids=()):
         self.cost = cost
         self.fp = footprint
         self.fail = set(fail_ids)
+        self.unconverged = set(unconverged_ids)
         self.lock = threading.Lock()
         self.running = 0
         self.max_running = 0
@@ -37,6 +38,8 @@ class FakeBackend:
             self.mem -= self.fp(r)
         if r.id in self.fail:
             raise RuntimeError("forced failure")
+        if r.id in self.unconverged:
+            return {"slot": slot, "status": "not converged"}
         return {"slot": slot}
 
 
@@ -84,3 +87,14 @@ def test_single_slot_is_serial():
     assert be.max_running == 1
     fin = sorted(r.finish for r in out)
     assert fin == [r.finish for r in out]
+
+
+def test_unconverged_requests_are_not_counted_as_completed():
+    """A request whose solve did not converge finishes (its slot and memory are released)
+    but counts neither as a completed solve nor in the latency percentiles."""
+    be = FakeBackend(cost=lambda r: 0.01 if r.id != 2 else 0.2, footprint=lambda r: 1, unconverged_ids={2})
+    out = Scheduler(be, slots=2, mem_cap=100).serve(reqs(6, 0.0))
+    assert out[2].status == "not converged" and out[2].finish is not None
+    s = summarize(out, max(r.finish for r in out))
+    assert s["completed"] == 5 and s["not_converged"] == 1
+    assert s["p99_s"] < 0.2          # the slow unconverged request is not in the percentiles
