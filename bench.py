@@ -49,14 +49,43 @@ KERNEL_NAMES = {
     "maxpy": "maxpy_kernel<{t}> (FGMRES multi-axpy)",
 }
 PROFILE_NAMES = {
-    "jv": r"zmarch_kernel<JvOp<{t}, 2, 0>, \d+, 1>", "jtw": r"zmarch_kernel<JtwOp<{t}, 2, 0>, \d+, 1>",
-    "smooth": r"zmarch_kernel<JvOp<{t}, 2, 2>, \d+, 1>", "smooth_T": r"zmarch_kernel<JtwOp<{t}, 2, 2>, \d+, 1>",
-    "pt_residual": r"zmarch_kernel<JvOp<{t}, 2, 1>, \d+, 1>", "mdot": r"mdot_kernel<{t}>", "maxpy": r"maxpy_kernel<{t}>",
+    "jv": r"zmarch_kernel<JvOp<{t}, 2, 0, false>, \d+, 1>", "jtw": r"zmarch_kernel<JtwOp<{t}, 2, 0, false>, \d+, 1>",
+    "smooth": r"zmarch_kernel<JvOp<{t}, 2, 2, false>, \d+, 1>", "smooth_T": r"zmarch_kernel<JtwOp<{t}, 2, 2, false>, \d+, 1>",
+    "pt_residual": r"zmarch_kernel<JvOp<{t}, 2, 1, false>, \d+, 1>", "mdot": r"mdot_kernel<{t}>", "maxpy": r"maxpy_kernel<{t}>",
 }
-# kernel sources whose hash must match the one recorded with the counter runs
-KERNEL_SOURCES = ["paper_1904_00182_amd/csrc/k_misc.hip", "paper_1904_00182_amd/csrc/k_apply.hip",
-                  "paper_1904_00182_amd/csrc/element.hpp", "paper_1904_00182_amd/csrc/common.hpp",
-                  "paper_1904_00182_amd/csrc/kernels.hpp", "paper_1904_00182_amd/csrc/transfer.hpp"]
+# kernel sources whose hash must match the one recorded with the counter runs: every
+# source of the library
+KERNEL_SOURCES = sorted("paper_1904_00182_amd/csrc/" + f for f in os.listdir(os.path.join(ROOT, "paper_1904_00182_amd", "csrc"))
+                        if f.endswith((".hip", ".hpp")))
+
+
+def measured_counters(cls, tname):
+    """(HBM bytes, VALU instructions) per launch of the class's kernel from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE calibrated; SQ_INSTS_VALU), or (None, None)
+    when there is none or the kernel sources have changed since the counters were taken."""
+    rec = _counter_record()
+    if rec is None:
+        return None, None
+    import re
+    pat = re.compile(PROFILE_NAMES[cls].format(t=tname) + "$")
+    for name, v in rec["kernels"].items():
+        if pat.match(name):
+            return round(v["fetch_bytes"] + v["write_bytes"]), v.get("valu_insts")
+    return None, None
+
+
+def _counter_record():
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_cavity128x64x128_mixed.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest() or rec.get("source_files", KERNEL_SOURCES) != KERNEL_SOURCES:
+        return None
+    return rec
 
 
 def measured_traffic(cls, tname):
@@ -75,6 +104,8 @@ def measured_traffic(cls, tname):
     if rec.get("source_sha256") != h.hexdigest():
         return None
     pat = re.compile(PROFILE_NAMES[cls].format(t=tname) + "$")
+    if rec.get("source_files") and rec["source_files"] != KERNEL_SOURCES:
+        return None
     for name, v in rec["kernels"].items():
         if pat.match(name):
             return round(v["fetch_bytes"] + v["write_bytes"])
@@ -648,7 +679,7 @@ def main():
     gbs = dom_bytes / (dom_ms * 1e-3) / 1e9
     hbm = {"achieved_gbs": round(gbs, 1), "peak_gbs": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
            "bytes_per_launch": round(dom_bytes / max(dom_n, 1))}
-    traffic = measured_traffic(dom, tname)
+    traffic, valu_insts = measured_counters(dom, tname)
     if dom in FLOPS_PER_ELEM:
         # operator kernels are bound by vector ALU issue: exact flops of the
         # element and node arithmetic, counted on the element code, against the vector peak
@@ -659,6 +690,12 @@ def main():
                 "frac": round(ach / peak, 4), "traffic": traffic,
                 "peak_without_packed_fp32": VALU_PEAK_TFLOPS[8], "frac_without_packed_fp32": round(ach / VALU_PEAK_TFLOPS[8], 4),
                 "flops_per_launch": fl, "hbm": hbm}
+        if valu_insts:
+            # VALU issue: one wave64 instruction per SIMD every 4 cycles (1024 SIMDs, 2.4 GHz);
+            # the counted instructions of one launch against its live duration
+            floor = valu_insts * 4 / (1024 * 2.4e9)
+            roof["valu_issue"] = {"instructions_per_launch": round(valu_insts), "floor_us": round(floor * 1e6, 2),
+                                  "frac": round(floor / t_dom, 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "bytes_per_launch": hbm["bytes_per_launch"]}
