@@ -18,6 +18,8 @@ What it computes (all in float64, plain and unblocked):
   with SuperLU;
 * the adjoint solve with the transposed factorisation and the design
   sensitivities -lambda^T dR/dgamma (Sec. 5.1, adjoint sensitivity analysis);
+* the Navier-Stokes / Brinkman flow model of the hybrid strategy (Sec. 6.4) on the
+  same machinery, with equal-order SUPG / PSPG stabilisation;
 * the closed-form permeability tuning of Sec. 3 (eqs. nusselt1-nusselt5);
 * the Method of Moving Asymptotes for the volume-constrained design update (Sec. 5.1),
   and the design loop of Sec. 5 around it (continuation, warm starts, Q ramping).
@@ -35,10 +37,12 @@ from .element import element_residual, reference_element
 from .pde_filter import PDEFilter, pde_length_scale
 from .fem import Model
 from .mma import MMA
+from .navier_stokes import NSModel, ns_element_residual, ns_constraints, brinkman
 from . import design
 
 __all__ = [
     "Params", "Mesh", "default_constraints", "patch_flux",
     "ramp_k", "ramp_kappa", "ramp_k_deriv", "ramp_kappa_deriv", "cone_filter_matrix", "kappa_f_tuning",
     "element_residual", "reference_element", "Model", "PDEFilter", "pde_length_scale", "MMA",
+    "NSModel", "ns_element_residual", "ns_constraints", "brinkman",
 ]

@@ -26,6 +26,10 @@ CSTEP = 1.0e-30     # complex-step size: derivative exact to round-off
 
 
 class Model:
+    # fields through which the volumetric objective depends on the state (the SUPG
+    # weight's velocity is the Darcy velocity of P and T)
+    objective_fields = (FIELD_P, FIELD_T)
+
     def __init__(self, prm, x, constraints=None, flux=None, src_P=None, src_T=None, gamma=None):
         """prm: Params; x: raw design per element (E,) in [0, 1].  The filtered density
         gamma = F x feeds RAMP (if `gamma` is given it is used as is, without a filter)."""
@@ -206,7 +210,7 @@ class Model:
                 raise ValueError("the volumetric objective's gradient depends on the state")
             s = np.asarray(s, dtype=float).reshape(-1, NFIELD)
             nodes = np.unique(self.mesh.conn[src])
-            for f in (FIELD_P, FIELD_T):
+            for f in self.objective_fields:
                 for n in nodes:
                     sc = s.astype(complex)
                     sc[n, f] += 1j * CSTEP
