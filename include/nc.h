@@ -321,6 +321,74 @@ int    nc_dense_inverse(double* a_dev, int n, int* iwork_dev, double* dwork_dev,
 #define NC_DENSE_NOALLOC_SCRATCH 49152
 int    nc_dense_inverse_noalloc(double* a_dev, int n, void* stream);
 
+/* ---------------------------------------------------------------------------------
+ * Navier-Stokes / Brinkman flow model: the full-flow model of the paper's hybrid
+ * strategy (Sec. 6.4), for the same five unknowns per node and the same design chain,
+ * objective and adjoint machinery.  Governing equations: the steady incompressible
+ * momentum equation of Sec. 2.1 (eq. app_NS) with the modified pressure and Boussinesq
+ * buoyancy of Sec. 2.1, a Brinkman friction a(gamma) u with a = mu (1/kappa(gamma) -
+ * 1/kappa_f) from the permeability RAMP of eq. permRAMP (zero in the fluid), the
+ * incompressibility condition and the energy equation of eq. goveq.  Equal-order
+ * trilinear elements with SUPG and PSPG stabilisation: streamline weight W = N + tau_m
+ * u0 . grad N on the momentum rows, tau_m / rho0 grad N . r_m added to the continuity
+ * rows, tau_m = (4|u0|^2/h_e^2 + 16 nu^2/h_e^4 + (a/rho0)^2)^(-1/2), the energy rows as in
+ * App. A.  Boundary conditions: no slip on the walls (only u.n = 0 on a symmetry plane), T
+ * and the pressure level as in the Darcy model.
+ *
+ * The fields of nc_problem keep their meaning; the solver uses precision (NC_MIXED: a
+ * float32 multigrid preconditioner inside float64 Krylov solves), levels, the Newton and
+ * Krylov controls (newton_step_rtol, newton_eta0, krylov_rtol as the smallest linear
+ * tolerance, krylov_restart, krylov_maxit, adjoint_rtol) and the smoother's sweeps and
+ * damping.  The Krylov residuals are those of the row-equilibrated system (each field's
+ * rows divided by the root mean square of its diagonal entries); the adjoint pressure
+ * then carries about 100 times the adjoint's relative residual, so an adjoint_rtol of
+ * 1e-12 gives multipliers accurate to about 1e-10; krylov_rtol_mixed, gs_passes, coarse_tail and smooth_omega_fallback are
+ * ignored.  The Jacobian is assembled (27 neighbours x 5 x 5 per node) by forward-mode
+ * differentiation of the element rows; the workspace holds it on every multigrid level
+ * (about 5.4 KB per node in float64, plus 2.7 KB per node in float32 with NC_MIXED).
+ * Errors, ownership and synchronisation as for the Darcy model's entry points.
+ * --------------------------------------------------------------------------------- */
+typedef struct nc_ns_ctx nc_ns_ctx;
+
+/* Workspace bytes of a Navier-Stokes context for *p (0 for an invalid problem). */
+size_t nc_ns_workspace_bytes(const nc_problem* p);
+int    nc_ns_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stream, nc_ns_ctx** out);
+int    nc_ns_destroy(nc_ns_ctx* ctx);
+/* The design chain of nc_set_design (filter, passive regions, RAMP of Sec. 5.2), with the
+ * permeability turned into the Brinkman coefficient.  Enqueue only. */
+int    nc_ns_set_design(nc_ns_ctx* ctx, const double* x_dev);
+int    nc_ns_get_gamma(nc_ns_ctx* ctx, double* gamma_dev);
+/* Residual R~(s) of the model above, [N][5] -> [N][5] (s_dev and r_dev distinct);
+ * constrained rows hold s.  Enqueue only. */
+int    nc_ns_residual(nc_ns_ctx* ctx, const double* s_dev, double* r_dev);
+/* Assemble the Jacobian J~ = dR~/ds at s (exact, including the derivatives of tau_m and
+ * of the streamline weights) on every multigrid level.  Synchronises. */
+int    nc_ns_linearize(nc_ns_ctx* ctx, const double* s_dev);
+/* y = J~ v, y = J~^T w with the float64 Jacobian of the last nc_ns_linearize (or solve);
+ * NC_EINVAL before any.  Enqueue only. */
+int    nc_ns_jac_apply(nc_ns_ctx* ctx, const double* v_dev, double* y_dev);
+int    nc_ns_jacT_apply(nc_ns_ctx* ctx, const double* w_dev, double* y_dev);
+/* One V-cycle of the preconditioner at the last linearisation: z = M^-1 v (M^-T v when
+ * transpose != 0), [N][5] float64.  Enqueue only. */
+int    nc_ns_precondition(nc_ns_ctx* ctx, int transpose, const double* v_dev, double* z_dev);
+/* Damped Newton (Sec. 5.4) with FGMRES on the assembled Jacobian: s_dev in = initial
+ * guess, out = solution, as nc_solve_state.  Synchronises. */
+int    nc_ns_solve_state(nc_ns_ctx* ctx, double* s_dev, nc_info* info);
+/* The compliance of nc_objective (Sec. 5.1 eq. objdiscr, the volumetric load weighted by
+ * the energy rows' streamline weight at the element's centroid velocity) and its state
+ * derivative (patch load on T; the volumetric part on T and on the velocity unknowns of
+ * the source elements' nodes; 0 on constrained entries). */
+int    nc_ns_objective(nc_ns_ctx* ctx, const double* s_dev, double* f_host);
+int    nc_ns_objective_grad(nc_ns_ctx* ctx, const double* s_dev, double* g_dev);
+/* J~^T lambda = rhs at s (rhs zeroed on constrained dofs), to adjoint_rtol.  Synchronises. */
+int    nc_ns_solve_adjoint(nc_ns_ctx* ctx, const double* s_dev, const double* rhs_dev, double* lam_dev, nc_info* info);
+/* dfdgamma_e = -lambda_e^T dR_e/dgamma_e through the conductivity and the Brinkman
+ * coefficient (zero on passive elements), dfdx = F_R^T dfdgamma (zero off the design
+ * domain).  The compliance has no explicit dependence on gamma in this model, so this is
+ * its full gradient.  Enqueue only. */
+int    nc_ns_sensitivity(nc_ns_ctx* ctx, const double* s_dev, const double* lam_dev, double* dfdx_dev,
+                         double* dfdgamma_dev);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,6 +26,9 @@ EXPORTED = [
     "nc_jac_apply_f32", "nc_jacT_apply_f32", "nc_solve_state", "nc_objective", "nc_objective_grad",
     "nc_solve_adjoint", "nc_sensitivity", "nc_objective_sensitivity", "nc_volume", "nc_set_problem", "nc_mma_update", "nc_precondition", "nc_cone_filter", "nc_dense_inverse",
     "nc_dense_inverse_noalloc", "nc_set_timing", "nc_get_timing",
+    "nc_ns_workspace_bytes", "nc_ns_create", "nc_ns_destroy", "nc_ns_set_design", "nc_ns_get_gamma", "nc_ns_residual",
+    "nc_ns_linearize", "nc_ns_jac_apply", "nc_ns_jacT_apply", "nc_ns_precondition", "nc_ns_solve_state",
+    "nc_ns_objective", "nc_ns_objective_grad", "nc_ns_solve_adjoint", "nc_ns_sensitivity",
 ]
 
 TIMER_CLASSES = ["residual", "jv", "jtw", "smooth", "smooth_T", "pt_residual", "diag", "uproj", "transfer",
@@ -121,6 +124,21 @@ def load():
             "nc_dense_inverse_noalloc": (I, [V, I, V]),
             "nc_set_timing": (I, [V, I]),
             "nc_get_timing": (I, [V, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D), I]),
+            "nc_ns_workspace_bytes": (S, [P]),
+            "nc_ns_create": (I, [P, V, S, V, ctypes.POINTER(V)]),
+            "nc_ns_destroy": (I, [V]),
+            "nc_ns_set_design": (I, [V, V]),
+            "nc_ns_get_gamma": (I, [V, V]),
+            "nc_ns_residual": (I, [V, V, V]),
+            "nc_ns_linearize": (I, [V, V]),
+            "nc_ns_jac_apply": (I, [V, V, V]),
+            "nc_ns_jacT_apply": (I, [V, V, V]),
+            "nc_ns_precondition": (I, [V, I, V, V]),
+            "nc_ns_solve_state": (I, [V, V, ctypes.POINTER(NCInfo)]),
+            "nc_ns_objective": (I, [V, V, ctypes.POINTER(D)]),
+            "nc_ns_objective_grad": (I, [V, V, V]),
+            "nc_ns_solve_adjoint": (I, [V, V, V, V, ctypes.POINTER(NCInfo)]),
+            "nc_ns_sensitivity": (I, [V, V, V, V, V]),
         }
         for name, (res, argt) in sig.items():
             f = getattr(lib, name)
@@ -366,6 +384,124 @@ class Solver:
         dfdg = torch.empty(self.E, dtype=torch.float64, device=self.device) if with_gamma else None
         _check(self.lib.nc_sensitivity(self.ctx, _ptr(s), _ptr(lam), _ptr(dfdx),
                                        _ptr(dfdg) if dfdg is not None else None), "nc_sensitivity")
+        return (dfdx, dfdg) if with_gamma else dfdx
+
+
+def ns_workspace_bytes(problem):
+    return int(load().nc_ns_workspace_bytes(ctypes.byref(problem)))
+
+
+class NSSolver:
+    """One context of the Navier-Stokes / Brinkman flow model (nc_ns_* entry points): a
+    caller-owned workspace tensor on `device` and one stream."""
+
+    def __init__(self, problem, device="cuda:0", stream=None):
+        self.lib = load()
+        self.p = problem
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.nbytes = ns_workspace_bytes(problem)
+        if self.nbytes == 0:
+            raise NCError(NC_EINVAL, "nc_ns_workspace_bytes")
+        self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.ctx = ctypes.c_void_p()
+        _check(self.lib.nc_ns_create(ctypes.byref(problem), _ptr(self.workspace), self.nbytes + 256,
+                                     _stream_handle(self.stream), ctypes.byref(self.ctx)), "nc_ns_create")
+        self.N = (problem.nx + 1) * (problem.ny + 1) * (problem.nz + 1)
+        self.E = problem.nx * problem.ny * problem.nz
+        self.last_info = None
+
+    def close(self):
+        if self.ctx:
+            self.lib.nc_ns_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self):
+        return torch.zeros((self.N, 5), dtype=torch.float64, device=self.device)
+
+    _in = Solver._in
+
+    def set_design(self, x):
+        self._x = self._in(x, (self.E,))
+        _check(self.lib.nc_ns_set_design(self.ctx, _ptr(self._x)), "nc_ns_set_design")
+
+    def gamma(self):
+        g = torch.empty(self.E, dtype=torch.float64, device=self.device)
+        _check(self.lib.nc_ns_get_gamma(self.ctx, _ptr(g)), "nc_ns_get_gamma")
+        return g
+
+    def residual(self, s):
+        s = self._in(s, (self.N, 5))
+        r = self._vec()
+        _check(self.lib.nc_ns_residual(self.ctx, _ptr(s), _ptr(r)), "nc_ns_residual")
+        return r
+
+    def linearize(self, s):
+        self._lin = self._in(s, (self.N, 5))
+        _check(self.lib.nc_ns_linearize(self.ctx, _ptr(self._lin)), "nc_ns_linearize")
+
+    def jac_apply(self, v, transpose=False):
+        v = self._in(v, (self.N, 5))
+        y = self._vec()
+        f = self.lib.nc_ns_jacT_apply if transpose else self.lib.nc_ns_jac_apply
+        _check(f(self.ctx, _ptr(v), _ptr(y)), "nc_ns_jac_apply")
+        return y
+
+    def precondition(self, v, transpose=False):
+        v = self._in(v, (self.N, 5))
+        z = self._vec()
+        _check(self.lib.nc_ns_precondition(self.ctx, 1 if transpose else 0, _ptr(v), _ptr(z)), "nc_ns_precondition")
+        return z
+
+    def solve_state(self, s0=None, out=None):
+        s = out if out is not None else self._vec()
+        if s0 is not None:
+            s.copy_(self._in(s0, (self.N, 5)))
+        elif out is None:
+            s.zero_()
+        info = NCInfo()
+        st = _check(self.lib.nc_ns_solve_state(self.ctx, _ptr(s), ctypes.byref(info)), "nc_ns_solve_state",
+                    allow_not_converged=True)
+        self.last_info = info.as_dict()
+        self.last_info["status"] = st
+        return s
+
+    def objective(self, s):
+        s = self._in(s, (self.N, 5))
+        f = ctypes.c_double()
+        _check(self.lib.nc_ns_objective(self.ctx, _ptr(s), ctypes.byref(f)), "nc_ns_objective")
+        return f.value
+
+    def objective_grad(self, s):
+        s = self._in(s, (self.N, 5))
+        g = self._vec()
+        _check(self.lib.nc_ns_objective_grad(self.ctx, _ptr(s), _ptr(g)), "nc_ns_objective_grad")
+        return g
+
+    def solve_adjoint(self, s, rhs, out=None):
+        s = self._in(s, (self.N, 5))
+        rhs = self._in(rhs, (self.N, 5))
+        lam = out if out is not None else self._vec()
+        info = NCInfo()
+        st = _check(self.lib.nc_ns_solve_adjoint(self.ctx, _ptr(s), _ptr(rhs), _ptr(lam), ctypes.byref(info)),
+                    "nc_ns_solve_adjoint", allow_not_converged=True)
+        self.last_info = info.as_dict()
+        self.last_info["status"] = st
+        return lam
+
+    def sensitivity(self, s, lam, with_gamma=False):
+        s = self._in(s, (self.N, 5))
+        lam = self._in(lam, (self.N, 5))
+        dfdx = torch.empty(self.E, dtype=torch.float64, device=self.device)
+        dfdg = torch.empty(self.E, dtype=torch.float64, device=self.device) if with_gamma else None
+        _check(self.lib.nc_ns_sensitivity(self.ctx, _ptr(s), _ptr(lam), _ptr(dfdx),
+                                          _ptr(dfdg) if dfdg is not None else None), "nc_ns_sensitivity")
         return (dfdx, dfdg) if with_gamma else dfdx
 
 
