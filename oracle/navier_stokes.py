@@ -29,9 +29,12 @@ and
     tau_m = (4 |u0|^2 / h_e^2 + 16 nu^2 / h_e^4 + (a / rho0)^2)^(-1/2),   nu = mu / rho0,
 the momentum counterpart of the energy equation's parameter of App. A, which is kept:
 N*_a = N_a + tau u0 . grad N_a with tau = (4 |u0|^2 / h_e^2 + 16 / h_e^4)^(-1/2).
-The Brinkman coefficient reuses the permeability RAMP of eq. permRAMP,
-    a(gamma) = mu (1 / kappa(gamma) - 1 / kappa_f),
-zero in the fluid and mu (1/kappa_s - 1/kappa_f) in the solid.
+The Brinkman coefficient interpolates the solid's impermeability: in the Navier-Stokes
+stage of the hybrid strategy (the discussion of eq. contsch2) q_p interpolates the
+impermeability of the solid and kappa_s is that impermeability (1e5), with the
+interpolation of the cited Navier-Stokes work, written here for gamma = 1 solid:
+    a(gamma) = kappa_s q_p gamma / (1 + q_p - gamma),
+zero in the fluid (gamma = 0) and kappa_s in the solid.
 
 Boundary conditions: no slip (u = 0) on every wall; on a symmetry plane of the quarter
 domain only the normal velocity is held (the tangential rows keep their natural
@@ -43,13 +46,14 @@ import numpy as np
 
 from .problem import NFIELD, FIELD_P, FIELD_T
 from .element import reference_element
-from .material import ramp_kappa
+from .material import ramp_k
 from .fem import Model
 
 
-def brinkman(kap, prm):
-    """Brinkman coefficient a = mu (1/kappa - 1/kappa_f) from the RAMP permeability."""
-    return prm.mu * (1.0 / kap - 1.0 / prm.kappa_f)
+def brinkman(gamma, prm):
+    """Brinkman coefficient a(gamma) = kappa_s q_p gamma / (1 + q_p - gamma): kappa_s is the
+    solid's impermeability in this model (complex-safe)."""
+    return prm.kappa_s * prm.q_p * gamma / (1.0 + prm.q_p - gamma)
 
 
 def _tau(u0, prm, a=None):
@@ -145,12 +149,12 @@ class NSModel(Model):
         if constraints is None:
             self.mask, self.sbar = ns_constraints(self.mesh, prm)
         self.src_U, self.src_T_ns = src_U, src_T
-        self.a = brinkman(self.kap, prm)
+        self.a = brinkman(self.gamma, prm)
 
-    def _elem_rows(self, se, k=None, kap=None):
+    def _elem_rows(self, se, k=None, a=None):
         v = se.reshape(se.shape[0], 8, NFIELD)
         k = self.k if k is None else k
-        a = self.a if kap is None else brinkman(kap, self.prm)
+        a = self.a if a is None else a
         RU, RP, RT = ns_element_residual(v[:, :, 0:3], v[:, :, FIELD_P], v[:, :, FIELD_T], k, a, self.prm,
                                          self.Qe, self.src_U, self.src_T_ns, self.x0)
         out = np.empty(v.shape, dtype=np.result_type(se, k, a))
@@ -158,6 +162,19 @@ class NSModel(Model):
         out[:, :, FIELD_P] = RP
         out[:, :, FIELD_T] = RT
         return out.reshape(se.shape[0], 8 * NFIELD)
+
+    def elem_dR_dgamma(self, s):
+        """d R_e / d gamma_e through the conductivity RAMP and the Brinkman coefficient, by
+        the complex step, (E, 40)."""
+        s = np.asarray(s, dtype=float).reshape(-1)
+        g = self.gamma.astype(complex) + 1j * 1e-30
+        p = self.prm
+        k = ramp_k(g, p.k_f, p.k_s, p.q_c)
+        return self._elem_rows(s[self.ldof].astype(complex), k, brinkman(g, p)).imag / 1e-30
+
+    def dfdgamma_explicit(self, s):
+        """The compliance's weight does not depend on the design in this model."""
+        return np.zeros(self.mesh.n_elems)
 
     def _objective_q(self, s, kap=None):
         """Volumetric compliance sum_e Q_e int_e N*^T t_e with the weight at the element's

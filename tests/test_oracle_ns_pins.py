@@ -7,7 +7,6 @@ import numpy as np
 import pytest
 
 from oracle import Params, Mesh, NSModel, ns_element_residual, ns_constraints, brinkman
-from oracle import ramp_kappa, reference_element
 from oracle.problem import FIELD_P, FIELD_T, NFIELD
 from paper_1904_00182_amd.inputs import noise_design, rng
 
@@ -71,16 +70,16 @@ def test_exact_shear_flow_with_convection():
 
 
 def test_exact_brinkman_flow_with_buoyancy():
-    """A uniform velocity b through a uniform porous medium (Brinkman coefficient a from
-    the permeability RAMP) under uniform temperature t0: grad P = -a b - rho0 alpha g t0
+    """A uniform velocity b through a uniform porous medium (Brinkman coefficient a of the
+    impermeability interpolation) under uniform temperature t0: grad P = -a b - rho0 alpha g t0
     (P linear), no convection or viscous stress, T rows trivially exact.  Interior rows
     vanish; Newton returns the fields.  Checks the Brinkman and buoyancy signs against the
     pressure gradient."""
-    p = Params(3, 4, 3, h=0.25, alpha=300.0, q_h=0.0)
+    p = Params(3, 4, 3, h=0.25, alpha=300.0, q_h=0.0, kappa_s=1e3)
     m = Mesh(p)
     gam = 0.3
-    a = brinkman(ramp_kappa(np.array([gam]), p.kappa_f, p.kappa_s, p.q_p), p)[0]
-    assert a > 10.0
+    a = brinkman(np.array([gam]), p)[0]
+    assert abs(a - 1e3 * 8.0 * 0.3 / 8.7) <= 1e-12 * a
     b, t0 = np.array([0.02, -0.03, 0.05]), 0.7
     X = m.node_xyz
     s = np.zeros((m.n_nodes, NFIELD))
@@ -214,7 +213,7 @@ def test_quarter_domain_with_symmetry_planes_equals_full_domain():
     sensitivities included."""
     L, n = 1.0, 8
     src, des = _benchmark_boxes(L)
-    kw = dict(alpha=1e3, q_h=0.0, Q=40.0)
+    kw = dict(alpha=1e4, q_h=0.0, Q=40.0, kappa_s=1e5)
     pf = Params(n, n, n, q_box=src, solid_box=src, design_box=des, **kw)
     x = noise_design(n ** 3, 41).reshape(n, n, n)
     x = 0.25 * (x + x[:, :, ::-1] + x[:, ::-1, :] + x[:, ::-1, ::-1])
@@ -275,7 +274,7 @@ def test_adjoint_gradient_vs_brute_force_fd(filt):
     differences of f(x) over full Newton solves."""
     n = 4
     src = (0.25, 0.75, 0.25, 0.75, 0.0, 0.25)
-    p = Params(n, n, n, alpha=1e3, q_h=5.0, Q=40.0, q_box=src, filter_radius=filt)
+    p = Params(n, n, n, alpha=1e3, q_h=5.0, Q=40.0, q_box=src, filter_radius=filt, kappa_s=1e4)
     m = Mesh(p)
     x = noise_design(m.n_elems, 51)
     model = NSModel(p, x)
