@@ -326,24 +326,29 @@ int    nc_dense_inverse_noalloc(double* a_dev, int n, void* stream);
  * strategy (Sec. 6.4), for the same five unknowns per node and the same design chain,
  * objective and adjoint machinery.  Governing equations: the steady incompressible
  * momentum equation of Sec. 2.1 (eq. app_NS) with the modified pressure and Boussinesq
- * buoyancy of Sec. 2.1, a Brinkman friction a(gamma) u with a = mu (1/kappa(gamma) -
- * 1/kappa_f) from the permeability RAMP of eq. permRAMP (zero in the fluid), the
- * incompressibility condition and the energy equation of eq. goveq.  Equal-order
+ * buoyancy of Sec. 2.1, a Brinkman friction a(gamma) u, the incompressibility condition and the energy equation of eq. goveq.  Equal-order
  * trilinear elements with SUPG and PSPG stabilisation: streamline weight W = N + tau_m
  * u0 . grad N on the momentum rows, tau_m / rho0 grad N . r_m added to the continuity
  * rows, tau_m = (4|u0|^2/h_e^2 + 16 nu^2/h_e^4 + (a/rho0)^2)^(-1/2), the energy rows as in
  * App. A.  Boundary conditions: no slip on the walls (only u.n = 0 on a symmetry plane), T
  * and the pressure level as in the Darcy model.
  *
- * The fields of nc_problem keep their meaning; the solver uses precision (NC_MIXED: a
+ * Brinkman coefficient: in this model kappa_s is the solid's impermeability and q_p its
+ * RAMP penalty, a(gamma) = kappa_s q_p gamma / (1 + q_p - gamma), zero in the fluid (the
+ * roles the paper gives them in the Navier-Stokes stage of its hybrid continuation,
+ * eq. contsch2: kappa_s = 1e5, q_p = 8); kappa_f is unused.
+ *
+ * The other fields of nc_problem keep their meaning; the solver uses precision (NC_MIXED: a
  * float32 multigrid preconditioner inside float64 Krylov solves), levels, the Newton and
  * Krylov controls (newton_step_rtol, newton_eta0, krylov_rtol as the smallest linear
  * tolerance, krylov_restart, krylov_maxit, adjoint_rtol) and the smoother's sweeps and
  * damping.  The Krylov residuals are those of the row-equilibrated system (each field's
  * rows divided by the root mean square of its diagonal entries); the adjoint pressure
  * then carries about 100 times the adjoint's relative residual, so an adjoint_rtol of
- * 1e-12 gives multipliers accurate to about 1e-10; krylov_rtol_mixed, gs_passes, coarse_tail and smooth_omega_fallback are
- * ignored.  The Jacobian is assembled (27 neighbours x 5 x 5 per node) by forward-mode
+ * 1e-12 gives multipliers accurate to about 1e-10.  Undamped node-block Jacobi
+ * (smooth_omega 1) diverges on these saddle-point blocks beyond small grids; 0.7 suits
+ * them, and smooth_omega_fallback takes over as in the Darcy model when a first restart
+ * cycle stalls.  krylov_rtol_mixed, gs_passes and coarse_tail are ignored.  The Jacobian is assembled (27 neighbours x 5 x 5 per node) by forward-mode
  * differentiation of the element rows; the workspace holds it on every multigrid level
  * (about 5.4 KB per node in float64, plus 2.7 KB per node in float32 with NC_MIXED).
  * Errors, ownership and synchronisation as for the Darcy model's entry points.

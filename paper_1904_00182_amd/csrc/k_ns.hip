@@ -367,13 +367,15 @@ __global__ void dense_kernel(Grid g, const T* __restrict__ A, double* __restrict
     for (int gg = 0; gg < 5; ++gg) D[(5 * n + f) * nd + 5 * (long)m + gg] = (double)A[(size_t)(o * 25 + f * 5 + gg) * N + n];
 }
 
-// (k, kappa) -> (k, a), d kappa / d gamma -> d a / d gamma, a = mu (1/kappa - 1/kappa_f)
-__global__ void brinkman_kernel(long E, double mu, double kap_f, double* __restrict__ coef, double* __restrict__ dkap) {
+// coef[e][1] = a(gamma_e) = abar q gamma / (1 + q - gamma) (the solid's impermeability abar
+// interpolated with penalty q), da[e] = abar q (1 + q) / (1 + q - gamma)^2
+__global__ void brinkman_kernel(long E, double abar, double q, const double* __restrict__ gamma,
+                                double* __restrict__ coef, double* __restrict__ da) {
   const long e = (long)blockIdx.x * BS + threadIdx.x;
   if (e >= E) return;
-  const double kap = coef[2 * e + 1];
-  coef[2 * e + 1] = mu * (1.0 / kap - 1.0 / kap_f);
-  dkap[e] = -mu * dkap[e] / (kap * kap);
+  const double g = gamma[e], den = 1.0 + q - g;
+  coef[2 * e + 1] = abar * q * g / den;
+  da[e] = abar * q * (1.0 + q) / (den * den);
 }
 
 __device__ inline double block_sum(double v, double* red) {
@@ -588,8 +590,8 @@ void launch_dense(hipStream_t st, const Grid& g, const T* A, double* D) {
   launch(dense_kernel<T>, dim3(blocks(27 * N)), dim3(BS), 0, st, g, A, D, N);
 }
 
-void launch_brinkman(hipStream_t st, long E, double mu, double kap_f, double* coef, double* dkap) {
-  launch(brinkman_kernel, dim3(blocks(E)), dim3(BS), 0, st, E, mu, kap_f, coef, dkap);
+void launch_brinkman(hipStream_t st, long E, double abar, double q, const double* gamma, double* coef, double* da) {
+  launch(brinkman_kernel, dim3(blocks(E)), dim3(BS), 0, st, E, abar, q, gamma, coef, da);
 }
 
 void launch_objective(hipStream_t st, const Grid& g, const NsConst& c, const Patch& patch, const double* s, double* part,

@@ -101,6 +101,7 @@ struct nc_ns_ctx {
   // than the momentum rows by about h^2); the preconditioner sees S v
   Field5 rs, rs_inv;
   long nfree[5];
+  double omega;          // block-Jacobi damping in use: smooth_omega, or the fallback after a stall
   bool design_set;
   bool lin_valid;        // Jacobian hierarchy assembled at lin_s
   const double* lin_s;
@@ -336,7 +337,7 @@ template <typename T>
 T* vcycle(nc_ns_ctx* c, int l, bool tr) {
   hipStream_t st = c->stream;
   NsLevel& L = c->lev[l];
-  const T om = (T)c->p.smooth_omega;
+  const T om = (T)c->omega;
   T* cur = (T*)L.x;
   T* nxt = (T*)L.x2;
   const T* A = (const T*)L.A;
@@ -405,7 +406,8 @@ void apply_scaled(nc_ns_ctx* c, bool tr, const double* x, double* y) {
 // from x = 0, classical Gram-Schmidt with one reorthogonalisation; restarts from the true
 // residual.  Returns the iterations (or -1 on a non-finite value); *relres the final
 // relative residual of the equilibrated system.
-int fgmres(nc_ns_ctx* c, bool tr, const double* b_in, double* x, double rtol, int maxit, double* relres) {
+int fgmres(nc_ns_ctx* c, bool tr, const double* b_in, double* x, double rtol, int maxit, double* relres,
+           bool* stalled = nullptr) {
   hipStream_t st = c->stream;
   const long n = c->n5, ld = c->ld;
   const int m = c->m;
@@ -478,9 +480,27 @@ int fgmres(nc_ns_ctx* c, bool tr, const double* b_in, double* x, double rtol, in
     *relres = beta / bnorm;
     if (!std::isfinite(beta)) return -1;
     if (*relres <= rtol || total >= maxit) break;
+    // a first cycle that has not halved the residual: the smoother's damping does not suit
+    // this system (undamped node-block Jacobi diverges on the saddle-point blocks)
+    if (stalled && total == jend && *relres > 0.5) {
+      *stalled = true;
+      return total;
+    }
     launch_convert<double, double>(st, V, V, n, 1.0 / beta);
   }
   return total;
+}
+
+// fgmres, switching the context to the fallback damping for good (and solving again from
+// zero) when the first restart cycle stalls
+int krylov(nc_ns_ctx* c, bool tr, const double* b, double* x, double rtol, double* relres) {
+  const double fb = c->p.smooth_omega_fallback;
+  bool stalled = false;
+  int its = fgmres(c, tr, b, x, rtol, c->p.krylov_maxit, relres, fb > 0.0 && c->omega != fb ? &stalled : nullptr);
+  if (its < 0 || !stalled) return its;
+  c->omega = fb;
+  const int more = fgmres(c, tr, b, x, rtol, c->p.krylov_maxit, relres);
+  return more < 0 ? more : its + more;
 }
 
 // max over fields of |a_f| / |b_f| (0 where both vanish)
@@ -514,7 +534,7 @@ int newton(nc_ns_ctx* c, double* s, nc_info* info) {
       const double ratio = nrm / prev;
       eta = std::min(p.newton_eta0, std::max(p.krylov_rtol, 0.9 * ratio * ratio));
     }
-    const int its = fgmres(c, false, c->R, c->d, eta, p.krylov_maxit, &relres);
+    const int its = krylov(c, false, c->R, c->d, eta, &relres);
     if (its < 0) return NC_ENAN;
     ktot += its;
     // full step s - d; a full step already below the tolerance in every field is taken
@@ -575,7 +595,7 @@ int adjoint(nc_ns_ctx* c, const double* s, const double* rhs, double* lam, nc_in
   ck(hipMemcpyAsync(c->tmp5, rhs, sizeof(double) * c->n5, hipMemcpyDeviceToDevice, st));
   nc::ns::launch_mask(st, c->lev[0].g, c->tmp5);
   double relres = 0.0;
-  const int its = fgmres(c, true, c->tmp5, lam, c->p.adjoint_rtol, c->p.krylov_maxit, &relres);
+  const int its = krylov(c, true, c->tmp5, lam, c->p.adjoint_rtol, &relres);
   if (its < 0) return NC_ENAN;
   nc::ns::launch_mask(st, c->lev[0].g, lam);
   if (info) {
@@ -643,6 +663,7 @@ int nc_ns_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* s
     c->design_set = false;
     c->lin_valid = false;
     c->lin_s = nullptr;
+    c->omega = c->p.smooth_omega;
     c->t_setup = 0.0;
     c->hbuf = nullptr;
     if (hipHostMalloc((void**)&c->hbuf, sizeof(double) * 4 * MAXC, hipHostMallocDefault) != hipSuccess) {
@@ -670,8 +691,10 @@ int nc_ns_set_design(nc_ns_ctx* c, const double* x) {
     NsLevel& L0 = c->lev[0];
     apply_filter(c, x, c->gamma, false);
     if (c->regions) launch_passive(st, L0.g, c->reg, c->gamma);
-    launch_ramp(st, c->E, c->gamma, p.k_f, p.k_s, p.q_c, p.kappa_f, p.kappa_s, p.q_p, L0.coef, c->coef32, c->dk, c->da);
-    nc::ns::launch_brinkman(st, c->E, p.mu, p.kappa_f, L0.coef, c->da);
+    // conductivity RAMP (and a permeability that the next kernel overwrites)
+    launch_ramp(st, c->E, c->gamma, p.k_f, p.k_s, p.q_c, p.kappa_f, 0.5 * p.kappa_f, p.q_p, L0.coef, c->coef32, c->dk,
+                c->da);
+    nc::ns::launch_brinkman(st, c->E, p.kappa_s, p.q_p, c->gamma, L0.coef, c->da);
     for (int l = 1; l < c->L; ++l)
       launch_average_coef<double>(st, c->lev[l - 1].g, c->lev[l].g, c->lev[l - 1].coef, c->lev[l].coef);
     ck(hipGetLastError());

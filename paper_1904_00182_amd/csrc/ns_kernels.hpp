@@ -65,7 +65,9 @@ void launch_inject(hipStream_t st, const Grid& gf, const Grid& gc, const double*
 // D (5N x 5N, row-major) = A
 template <typename T>
 void launch_dense(hipStream_t st, const Grid& g, const T* A, double* D);
-void launch_brinkman(hipStream_t st, long E, double mu, double kap_f, double* coef, double* dkap);
+// Brinkman coefficient a(gamma) = abar q gamma / (1 + q - gamma) into coef[e][1] and its
+// derivative into da (abar: the solid's impermeability, q: its RAMP penalty)
+void launch_brinkman(hipStream_t st, long E, double abar, double q, const double* gamma, double* coef, double* da);
 void launch_objective(hipStream_t st, const Grid& g, const NsConst& c, const Patch& patch, const double* s, double* part,
                       double* out);
 void launch_objective_grad(hipStream_t st, const Grid& g, const NsConst& c, const Patch& patch, const double* s,

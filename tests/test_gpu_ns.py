@@ -38,7 +38,8 @@ ADJ_RTOL = 1e-12
 
 
 def _pair(grid, kw, seed, precision=nc.NC_FP64, **extra):
-    p = nc.default_problem(*grid, precision=precision, adjoint_rtol=ADJ_RTOL, **kw, **extra)
+    p = nc.default_problem(*grid, precision=precision, adjoint_rtol=ADJ_RTOL, kappa_s=1e5, smooth_omega=0.7, **kw,
+                           **extra)
     x = inputs.noise_design(grid[0] * grid[1] * grid[2], seed)
     model = oracle.NSModel(oracle_params(p), x)
     sol = nc.NSSolver(p, DEV)
