@@ -359,6 +359,11 @@ typedef struct nc_ns_ctx nc_ns_ctx;
 size_t nc_ns_workspace_bytes(const nc_problem* p);
 int    nc_ns_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stream, nc_ns_ctx** out);
 int    nc_ns_destroy(nc_ns_ctx* ctx);
+/* Parameters changed in place (the continuation of eq. contsch2, a ramp of the heat
+ * source), under the conditions of nc_set_problem: same grid, levels, precision, Krylov
+ * restart and filter work, NC_EINVAL otherwise; the design must be set again.  Host only
+ * (synchronises). */
+int    nc_ns_set_problem(nc_ns_ctx* ctx, const nc_problem* p);
 /* The design chain of nc_set_design (filter, passive regions, RAMP of Sec. 5.2), with the
  * permeability turned into the Brinkman coefficient.  Enqueue only. */
 int    nc_ns_set_design(nc_ns_ctx* ctx, const double* x_dev);

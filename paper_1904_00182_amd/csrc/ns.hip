@@ -71,6 +71,7 @@ double now() {
 struct nc_ns_ctx {
   nc_problem p;
   hipStream_t stream;
+  char* ws_base;         // the caller's workspace (aligned) and the bytes the layout uses
   size_t ws_need;
   bool mixed;
   int L;
@@ -657,6 +658,7 @@ int nc_ns_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* s
     const size_t mis = (size_t)((uintptr_t)base % NS_ALIGN);
     if (mis) base += NS_ALIGN - mis;
     carve(c, base);
+    c->ws_base = base;
     c->ws_need = need;
     c->stream = (hipStream_t)stream;
     c->patch = Patch{c->p.q_h, c->p.patch_x0, c->p.patch_x1, c->p.patch_y0, c->p.patch_y1, c->p.h};
@@ -671,6 +673,29 @@ int nc_ns_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* s
       return NC_EHIP;
     }
     *out = c;
+    return NC_OK;
+  });
+}
+
+int nc_ns_set_problem(nc_ns_ctx* c, const nc_problem* p) {
+  if (!c || !valid(p)) return NC_EINVAL;
+  return guarded([&]() {
+    nc_ns_ctx tmp;
+    tmp.p = *p;
+    if (tmp.p.h <= 0) tmp.p.h = 1.0 / p->nx;
+    const size_t need = carve(&tmp, nullptr);
+    bool same = need == c->ws_need && tmp.L == c->L && tmp.mixed == c->mixed && tmp.m == c->m &&
+                tmp.dense == c->dense && tmp.pde == c->pde;
+    for (int l = 0; same && l < c->L; ++l)
+      same = tmp.lev[l].g.nx == c->lev[l].g.nx && tmp.lev[l].g.ny == c->lev[l].g.ny && tmp.lev[l].g.nz == c->lev[l].g.nz;
+    if (!same) return NC_EINVAL;
+    sync(c);
+    c->p = tmp.p;
+    carve(c, c->ws_base);   // the same layout: recomputes the level constants and regions only
+    c->patch = Patch{c->p.q_h, c->p.patch_x0, c->p.patch_x1, c->p.patch_y0, c->p.patch_y1, c->p.h};
+    c->omega = c->p.smooth_omega;
+    c->design_set = false;
+    c->lin_valid = false;
     return NC_OK;
   });
 }

@@ -26,7 +26,7 @@ EXPORTED = [
     "nc_jac_apply_f32", "nc_jacT_apply_f32", "nc_solve_state", "nc_objective", "nc_objective_grad",
     "nc_solve_adjoint", "nc_sensitivity", "nc_objective_sensitivity", "nc_volume", "nc_set_problem", "nc_mma_update", "nc_precondition", "nc_cone_filter", "nc_dense_inverse",
     "nc_dense_inverse_noalloc", "nc_set_timing", "nc_get_timing",
-    "nc_ns_workspace_bytes", "nc_ns_create", "nc_ns_destroy", "nc_ns_set_design", "nc_ns_get_gamma", "nc_ns_residual",
+    "nc_ns_workspace_bytes", "nc_ns_create", "nc_ns_destroy", "nc_ns_set_problem", "nc_ns_set_design", "nc_ns_get_gamma", "nc_ns_residual",
     "nc_ns_linearize", "nc_ns_jac_apply", "nc_ns_jacT_apply", "nc_ns_precondition", "nc_ns_solve_state",
     "nc_ns_objective", "nc_ns_objective_grad", "nc_ns_solve_adjoint", "nc_ns_sensitivity",
 ]
@@ -127,6 +127,7 @@ def load():
             "nc_ns_workspace_bytes": (S, [P]),
             "nc_ns_create": (I, [P, V, S, V, ctypes.POINTER(V)]),
             "nc_ns_destroy": (I, [V]),
+            "nc_ns_set_problem": (I, [V, P]),
             "nc_ns_set_design": (I, [V, V]),
             "nc_ns_get_gamma": (I, [V, V]),
             "nc_ns_residual": (I, [V, V, V]),
@@ -426,6 +427,12 @@ class NSSolver:
         return torch.zeros((self.N, 5), dtype=torch.float64, device=self.device)
 
     _in = Solver._in
+
+    def set_problem(self, problem):
+        """Replace the context's parameters (same grid and layout) via nc_ns_set_problem; the
+        design must be set again afterwards."""
+        _check(self.lib.nc_ns_set_problem(self.ctx, ctypes.byref(problem)), "nc_ns_set_problem")
+        self.p = problem
 
     def set_design(self, x):
         self._x = self._in(x, (self.E,))

@@ -89,3 +89,26 @@ def test_q_ramp_reaches_the_direct_root():
     info, ramped = design.solve_with_ramp(sol, p, x, s2, force_ramp=True)
     assert ramped and info["status"] == nc.NC_OK
     check_fields(s2.cpu().numpy(), s1.cpu().numpy(), 1e-10, "ramped vs direct")
+
+
+def test_hybrid_ns_then_darcy_loop_matches_oracle():
+    """The hybrid strategy of Sec. 6.4 (NS-D, the continuation of eq. contsch2) with its
+    stages shortened to two iterations each: two Navier-Stokes / Brinkman stages (the
+    solid's impermeability 1e5 interpolated with q_p), then the first Darcy stage, on the
+    8x8x16 quarter cavity; per iteration the flow model, the compliance, the volume fraction
+    and the designs equal the oracle's loop within 1e-8."""
+    p = workloads.benchmark_problem(8, 1e3)
+    op = oracle_params(p)
+    m = oracle.Model(op, np.zeros(p.nx * p.ny * p.nz))
+    x0 = _start(m)
+    xo, so, ho = odesign.optimize(op, x0, 6, every=2, continuation=odesign.HYBRID_NS_D)
+    xg, sg, hg = design.optimize(p, x0, 6, every=2, continuation=design.HYBRID_NS_D, keep_designs=True)
+    for it, (a, b) in enumerate(zip(hg, ho)):
+        print(it, a["model"], "gpu f", a["f"], "oracle f", b["f"], "frac", a["frac"], b["frac"],
+              "krylov", a["state_krylov"], a["adjoint_krylov"], flush=True)
+        assert a["model"] == b["model"]
+        assert abs(a["f"] - b["f"]) <= 1e-8 * abs(b["f"]), it
+        assert abs(a["frac"] - b["frac"]) <= 1e-10, it
+        assert np.abs(a["x"] - b["x"]).max() <= 1e-8, (it, np.abs(a["x"] - b["x"]).max())
+    assert [h["model"] for h in hg] == ["ns"] * 4 + ["darcy"] * 2
+    check_fields(sg.cpu().numpy(), so, 1e-8, "final state")
