@@ -131,6 +131,8 @@ def parse():
     ap.add_argument("--serving-load", type=float, default=1.5,
                     help="arrival rate as a multiple of the measured one-at-a-time capacity")
     ap.add_argument("--design-iters", type=int, default=10)
+    ap.add_argument("--no-ns", action="store_true", help="skip the Navier-Stokes / Brinkman model's timings")
+    ap.add_argument("--hybrid-iters", type=int, default=4, help="design iterations per stage of the hybrid NS-D run")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--report", default=None,
                     help="also write extended measurements (operator sweep, float64 baseline, warm re-solve, "
@@ -330,6 +332,91 @@ def design_loop_timing(args):
     out["paper_context"] = ("state-solver time per optimisation iteration at 80x80x160, warm-started, 250 iterations: "
                             "Gr 1e3 37.29 s on 16 and 1.25 s on 640 Xeon E5-2680v2 cores; Gr 1e6 44.77 s and 1.65 s "
                             "(Table tab:jessperformance1); other hardware and 1e-4 / 1e-5 tolerances, context only")
+    return out
+
+
+def ns_timing(args):
+    """The Navier-Stokes / Brinkman flow model (the full-flow model of the hybrid strategy,
+    Sec. 6.4) on the bench workload's grid and design: cold and warm state solves, the
+    adjoint, the float64 operator apply (its assembled node-block Jacobian is HBM-bound),
+    and design iterations of the hybrid NS-D continuation (eq. contsch2) on the paper's
+    80x80x160 quarter cavity, Navier-Stokes stage against Darcy stage."""
+    import torch
+    from paper_1904_00182_amd import design, nc, workloads
+    dev = "cuda:0"
+    p, x, _ = workloads.config(args.workload)
+    pn = nc.copy_problem(p, kappa_s=1e5, q_p=8.0, **design.NS_SETTINGS)
+    sol = nc.NSSolver(pn, dev)
+    sol.set_design(x)
+    out = {"workload": f"{args.workload} grid and design with the Navier-Stokes / Brinkman model (solid impermeability "
+                       f"1e5, q_p 8), Gr {p.alpha:g}, float64 Krylov with a "
+                       + ("float32" if p.precision == nc.NC_MIXED else "float64") + " multigrid preconditioner"}
+    s = sol.solve_state()
+    torch.cuda.synchronize()
+    for rep in range(2):
+        t0 = time.perf_counter()
+        s = sol.solve_state()
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        i_s = dict(sol.last_info)
+        g = sol.objective_grad(s)
+        t0 = time.perf_counter()
+        lam = sol.solve_adjoint(s, g)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t0
+        i_a = dict(sol.last_info)
+    out.update({"state_status": nc_status(i_s["status"]), "adjoint_status": nc_status(i_a["status"]),
+                "state_s": round(ts, 4), "adjoint_s": round(ta, 4), "newton_its": i_s["newton_its"],
+                "state_krylov_per_newton_step": i_s["hist_krylov"], "adjoint_krylov_its": i_a["krylov_its"],
+                "adjoint_rel_res": i_a["rel_res"], "assembly_and_setup_s": round(i_s["t_setup"], 4),
+                "levels": i_s["levels"], "objective": sol.objective(s)})
+    # float64 operator apply y = J~ v on the assembled Jacobian (27 x 25 entries per node)
+    N = sol.N
+    v = torch.randn((N, 5), dtype=torch.float64, device=dev)
+    y = torch.empty_like(v)
+    lib = nc.load()
+    ptr = lambda t: nc.ctypes.c_void_p(t.data_ptr())
+    for _ in range(3):
+        lib.nc_ns_jac_apply(sol.ctx, ptr(v), ptr(y))
+    iters = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        lib.nc_ns_jac_apply(sol.ctx, ptr(v), ptr(y))
+    e1.record()
+    torch.cuda.synchronize()
+    t_apply = e0.elapsed_time(e1) / iters * 1e-3
+    nbytes = (27 * 25 * 8 + 2 * 5 * 8) * N
+    out["operator_f64"] = {"us": round(t_apply * 1e6, 1), "gdof_s": round(5 * N / t_apply / 1e9, 2),
+                           "algorithmic_bytes": nbytes, "gb_s": round(nbytes / t_apply / 1e9, 1),
+                           "hbm_frac": round(nbytes / t_apply / 8e12, 3),
+                           "bytes_per_node": "27 x 25 float64 matrix entries + 5 read + 5 written"}
+    log(args, "navier-stokes", out)
+    sol.close()
+    del sol
+    torch.cuda.empty_cache()
+    # hybrid NS-D design iterations on the 80x80x160 quarter cavity
+    pb = workloads.benchmark_problem(80, 1e3, nc.NC_MIXED, kappa_s=1e-5, q_c=8.81, q_p=8.0)
+    x0 = workloads.benchmark_start_design(pb, dev)
+    every = max(2, args.hybrid_iters)
+    cont = (("ns", 8.81, 8.0, 1e5), ("darcy", 88.1, 8.0, 1e-5))
+    torch.cuda.synchronize()
+    _, _, hist = design.optimize(pb, x0, 2 * every, every=every, continuation=cont, device=dev)
+    hy = {"workload": "quarter cavity 80x80x160 (Sec. 6.1), Gr 1e3, PDE filter R = 2.5, Q = 1e4 block; stages of "
+                      f"{every} iterations: Navier-Stokes (q_c 8.81, q_p 8, impermeability 1e5), then Darcy "
+                      "(q_c 88.1, q_p 8, kappa_s 1e-5); each stage's first iteration starts cold and is excluded"}
+    for kind in ("ns", "darcy"):
+        hs = [h for h in hist if h["model"] == kind][1:]
+        hy[kind] = {"s_per_iteration": round(sum(h["seconds"] for h in hs) / len(hs), 4),
+                    "state_s": round(sum(h["state_s"] for h in hs) / len(hs), 4),
+                    "adjoint_s": round(sum(h["adjoint_s"] for h in hs) / len(hs), 4),
+                    "newton_per_iteration": round(sum(h["newton"] for h in hs) / len(hs), 2),
+                    "fgmres_per_newton_step": round(sum(h["state_krylov"] for h in hs) / max(1, sum(h["newton"] for h in hs)), 2)}
+    hy["ns_over_darcy"] = round(hy["ns"]["s_per_iteration"] / hy["darcy"]["s_per_iteration"], 2)
+    hy["paper_context"] = ("hybrid NS-D at alpha 1e3 (Table tab:topoptperformancehybrid, other hardware): Navier-Stokes "
+                           "200 iterations 20.0 h, Darcy 300 iterations 1.5 h, i.e. 360 s and 18 s per iteration")
+    out["hybrid_design"] = hy
+    log(args, "hybrid design", hy)
     return out
 
 
@@ -756,6 +843,8 @@ def main():
     result["pde_filter"] = pde_filter_timing(args)
     if not args.no_design_loop:
         result["design_loop"] = design_loop_timing(args)
+    if not args.no_ns:
+        result["navier_stokes"] = ns_timing(args)
     if mixed and not args.no_fp64_leg:
         result["fp64_baseline"] = fp64_leg(args, mixed_result)
         result["fp64_baseline"]["mixed_speedup"] = round(result["fp64_baseline"]["ms_per_step"] / (t_step * 1e3), 3)
