@@ -339,7 +339,8 @@ int    nc_dense_inverse_noalloc(double* a_dev, int n, void* stream);
  * eq. contsch2: kappa_s = 1e5, q_p = 8); kappa_f is unused.
  *
  * The other fields of nc_problem keep their meaning; the solver uses precision (NC_MIXED: a
- * float32 multigrid preconditioner inside float64 Krylov solves), levels, the Newton and
+ * float32 multigrid preconditioner inside float64 Krylov solves on the float64 Jacobian),
+ * levels, the Newton and
  * Krylov controls (newton_step_rtol, newton_eta0, krylov_rtol as the smallest linear
  * tolerance, krylov_restart, krylov_maxit, adjoint_rtol) and the smoother's sweeps and
  * damping.  The Krylov residuals are those of the row-equilibrated system (each field's

@@ -98,37 +98,193 @@ __global__ void residual_finish_kernel(Grid g, Patch patch, const double* __rest
     if (fixed(g, i, j, k, f)) r[5 * n + f] = s[5 * n + f];
 }
 
-// Jacobian columns of one colour: thread (d, element), d = 5 b + field the column's local
-// dof, added into the node-block matrix of precision T.
+// Jacobian columns of one colour, added into the node-block matrix of precision T, by
+// forward-mode differentiation of the element rows with the work shared: a block holds AS_E elements of one colour
+// and five waves, wave g the columns of field g (uniform across the wave), lane b * AS_E + le
+// the column of node b of element le.  The primal quantities of each element and Gauss
+// point (interpolated fields, strong momentum residual, divergence, energy residual,
+// symmetric stress) are computed once into LDS; each column then needs only its tangents,
+// which for the unit direction of (b, g) follow from N_b and grad N_b at the point:
+//   g < 3:  u' = N_b e_g, (grad u)' = e_g grad N_b^T, u0' = e_g / 8
+//   g = 3:  (grad P)' = grad N_b
+//   g = 4:  T' = N_b, (grad T)' = grad N_b
+// differentiating every product of the element rows (including tau_m and tau through u0).
+constexpr int AS_E = 8;            // elements per block
+constexpr int AS_Q = 26;           // primal doubles per Gauss point
+constexpr int AS_X = 11;           // per-element doubles: u0, tau_m, tau, d tau_m / d u0, d tau / d u0
+
+__device__ inline void shape_at(int q, int n, double ih, double& N, double D[3]) {
+  const double gx = (q & 1) ? G1 : G0, gy = (q & 2) ? G1 : G0, gz = (q & 4) ? G1 : G0;
+  const double lx = (n & 1) ? gx : 1.0 - gx, ly = (n & 2) ? gy : 1.0 - gy, lz = (n & 4) ? gz : 1.0 - gz;
+  N = lx * ly * lz;
+  D[0] = ((n & 1) ? ih : -ih) * ly * lz;
+  D[1] = lx * ((n & 2) ? ih : -ih) * lz;
+  D[2] = lx * ly * ((n & 4) ? ih : -ih);
+}
+
 template <typename T>
-__global__ __launch_bounds__(BS) void assemble_kernel(Grid g, NsConst c, ColourGrid cg, const double* __restrict__ coef,
-                                                      const double* __restrict__ s, T* __restrict__ A, long N) {
-  const long t = (long)blockIdx.x * BS + threadIdx.x;
-  if (t >= cg.count * 40) return;
-  const int d = (int)(t / cg.count);
-  const long te = t - (long)d * cg.count;
-  const int b = d / 5, gg = d - 5 * b;
-  int i, j, k, nid[8];
-  elem_ijk(cg, te, i, j, k);
-  elem_nodes(g, i, j, k, nid);
-  const long e = g.elem(i, j, k);
+__global__ __launch_bounds__(5 * 64) void assemble_shared_kernel(Grid g, NsConst c, ColourGrid cg,
+                                                                 const double* __restrict__ coef,
+                                                                 const double* __restrict__ s, T* __restrict__ A,
+                                                                 long N) {
+  __shared__ double vals[AS_E][40];
+  __shared__ double pq[AS_E][8][AS_Q];
+  __shared__ double pe[AS_E][AS_X];
+  __shared__ int nodes[AS_E][8];
+  __shared__ double kc[AS_E], ac[AS_E];
+  const int tid = threadIdx.x;
+  const int fg = tid >> 6, lane = tid & 63;        // field of the columns, lane
+  const int b = lane / AS_E, le = lane % AS_E;     // column node, element in the block
+  const long e0 = (long)blockIdx.x * AS_E;
+  const double h = c.h, ih = 1.0 / h, detJ = h * h * h * 0.125;
+  // nodal values and ids
+  {
+    const int el = tid / 40, d = tid % 40;
+    if (el < AS_E && e0 + el < cg.count) {
+      int i, j, k;
+      elem_ijk(cg, e0 + el, i, j, k);
+      const int n = d / 5, f = d % 5;
+      const int id = g.node(i + (n & 1), j + ((n >> 1) & 1), k + (n >> 2));
+      vals[el][d] = s[5 * (long)id + f];
+      if (f == 0) nodes[el][n] = id;
+      if (d == 0) {
+        const long e = g.elem(i, j, k);
+        kc[el] = coef[2 * e];
+        ac[el] = coef[2 * e + 1];
+      }
+    }
+  }
+  __syncthreads();
+  // primal quantities per (element, Gauss point): the first wave
+  if (fg == 0 && e0 + (lane >> 3) < cg.count) {
+    const int el = lane >> 3, q = lane & 7;
+    const double a = ac[el];
+    double uq[3] = {0, 0, 0}, Gu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, GP[3] = {0, 0, 0}, Tq = 0,
+           GT[3] = {0, 0, 0};
+    double u0[3] = {0, 0, 0};
+    for (int n = 0; n < 8; ++n) {
+      double Nn, D[3];
+      shape_at(q, n, ih, Nn, D);
+      const double* v = vals[el] + 5 * n;
+      for (int i = 0; i < 3; ++i) {
+        uq[i] += Nn * v[i];
+        u0[i] += 0.125 * v[i];
+        GP[i] += D[i] * v[3];
+        GT[i] += D[i] * v[4];
+        for (int jj = 0; jj < 3; ++jj) Gu[i][jj] += D[jj] * v[i];
+      }
+      Tq += Nn * v[4];
+    }
+    double* P = pq[el][q];
+    double rm[3];
+    for (int i = 0; i < 3; ++i)
+      rm[i] = c.rho * (uq[0] * Gu[i][0] + uq[1] * Gu[i][1] + uq[2] * Gu[i][2]) + GP[i] + a * uq[i];
+    rm[2] += c.bz * Tq;
+    for (int i = 0; i < 3; ++i) {
+      P[i] = uq[i];
+      for (int jj = 0; jj < 3; ++jj) P[3 + 3 * i + jj] = Gu[i][jj];
+      P[12 + i] = GT[i];
+      P[15 + i] = rm[i];
+    }
+    P[18] = Gu[0][0] + Gu[1][1] + Gu[2][2];
+    P[19] = (c.rho * c.cp) * (uq[0] * GT[0] + uq[1] * GT[1] + uq[2] * GT[2]);   // the source is subtracted below
+    P[20] = c.mu * 2.0 * Gu[0][0];
+    P[21] = c.mu * 2.0 * Gu[1][1];
+    P[22] = c.mu * 2.0 * Gu[2][2];
+    P[23] = c.mu * (Gu[0][1] + Gu[1][0]);
+    P[24] = c.mu * (Gu[0][2] + Gu[2][0]);
+    P[25] = c.mu * (Gu[1][2] + Gu[2][1]);
+    if (q == 0) {
+      const double ihe2 = 1.0 / c.he2;
+      const double uu = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
+      const double tm = 1.0 / sqrt(4.0 * ihe2 * uu + 16.0 * c.nu2 * ihe2 * ihe2 + a * a / (c.rho * c.rho));
+      const double tt = 1.0 / sqrt(4.0 * ihe2 * uu + 16.0 * ihe2 * ihe2);
+      double* X = pe[el];
+      for (int i = 0; i < 3; ++i) {
+        X[i] = u0[i];
+        X[5 + i] = -4.0 * ihe2 * u0[i] * tm * tm * tm;
+        X[8 + i] = -4.0 * ihe2 * u0[i] * tt * tt * tt;
+      }
+      X[3] = tm;
+      X[4] = tt;
+    }
+  }
+  __syncthreads();
+  if (e0 + le >= cg.count) return;
+  int ei, ej, ek;
+  elem_ijk(cg, e0 + le, ei, ej, ek);
+  const double Qe = c.source(ei, ej, ek);
+  const double k = kc[le], a = ac[le];
+  const double* X = pe[le];
+  const double u0[3] = {X[0], X[1], X[2]};
+  const double tm = X[3], tt = X[4];
+  // tangents of u0, tau_m and tau for this column
+  const double du0 = fg < 3 ? 0.125 : 0.0;
+  const double dtm = fg < 3 ? 0.125 * X[5 + fg] : 0.0, dtt = fg < 3 ? 0.125 * X[8 + fg] : 0.0;
+  const double irho = 1.0 / c.rho, rcp = c.rho * c.cp;
   double col[8][5];
 #pragma unroll
   for (int n = 0; n < 8; ++n)
 #pragma unroll
     for (int f = 0; f < 5; ++f) col[n][f] = 0.0;
-  auto in = [&](int n, int f) { return Dual{s[5 * (long)nid[n] + f], (n == b && f == gg) ? 1.0 : 0.0}; };
-  auto out = [&](int n, int f, Dual v) { col[n][f] += v.d; };
-  element_rows<Dual>(c, Dual{coef[2 * e], 0.0}, Dual{coef[2 * e + 1], 0.0}, c.source(i, j, k), in, out);
+#pragma unroll 1
+  for (int q = 0; q < 8; ++q) {
+    const double* P = pq[le][q];
+    double Nb, Db[3];
+    shape_at(q, b, ih, Nb, Db);
+    const double uq[3] = {P[0], P[1], P[2]};
+    const double rm[3] = {P[15], P[16], P[17]};
+    const double cT = P[19] - Qe;
+    // tangents of the point quantities
+    double drm[3], ddiv = 0.0, dcT = 0.0, dGT[3] = {0, 0, 0};
+    const double ub = uq[0] * Db[0] + uq[1] * Db[1] + uq[2] * Db[2];
+    if (fg < 3) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) drm[i] = c.rho * Nb * P[3 + 3 * i + fg];
+      drm[fg] += c.rho * ub + a * Nb;
+      ddiv = Db[fg];
+      dcT = rcp * Nb * P[12 + fg];
+    } else if (fg == 3) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) drm[i] = Db[i];
+    } else {
+      drm[0] = drm[1] = 0.0;
+      drm[2] = c.bz * Nb;
+      dcT = rcp * ub;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dGT[i] = Db[i];
+    }
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+      double Nn, Dn[3];
+      shape_at(q, n, ih, Nn, Dn);
+      const double adv = u0[0] * Dn[0] + u0[1] * Dn[1] + u0[2] * Dn[2];
+      const double dadv = fg < 3 ? du0 * Dn[fg] : 0.0;
+      const double Wm = Nn + tm * adv, dWm = dtm * adv + tm * dadv;
+      const double Wt = Nn + tt * adv, dWt = dtt * adv + tt * dadv;
+      const double Dnrm = Dn[0] * rm[0] + Dn[1] * rm[1] + Dn[2] * rm[2];
+      const double Dndrm = Dn[0] * drm[0] + Dn[1] * drm[1] + Dn[2] * drm[2];
+      // viscous tangent: mu (delta_ig Dn . Db + Dn_g Db_i) for a velocity column
+      const double DnDb = Dn[0] * Db[0] + Dn[1] * Db[1] + Dn[2] * Db[2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        double vis = 0.0;
+        if (fg < 3) vis = c.mu * ((i == fg ? DnDb : 0.0) + Dn[fg] * Db[i]);
+        col[n][i] += detJ * (dWm * rm[i] + Wm * drm[i] + vis);
+      }
+      col[n][3] += detJ * (Nn * ddiv + irho * (dtm * Dnrm + tm * Dndrm));
+      col[n][4] += detJ * (dWt * cT + Wt * dcT + k * (Dn[0] * dGT[0] + Dn[1] * dGT[1] + Dn[2] * dGT[2]));
+    }
+  }
   const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
 #pragma unroll
   for (int n = 0; n < 8; ++n) {
     const int o = (bx - (n & 1) + 1) + 3 * (by - ((n >> 1) & 1) + 1) + 9 * (bz - (n >> 2) + 1);
+    const int id = nodes[le][n];
+    // a returnless atomic add (no round trip through the registers); within one colour no
+    // other thread touches the entry, so the additions keep their launch order
 #pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      T* p = A + (size_t)(o * 25 + f * 5 + gg) * N + nid[n];
-      *p = (T)((double)*p + col[n][f]);
-    }
+    for (int f = 0; f < 5; ++f) unsafeAtomicAdd(A + (size_t)(o * 25 + f * 5 + fg) * N + id, (T)col[n][f]);
   }
 }
 
@@ -161,8 +317,8 @@ __global__ void fix_kernel(Grid g, T* __restrict__ A, long N) {
 
 // y = A x, y = b - A x, or one damped block-Jacobi sweep y = x + omega D^-1 (b - A x)
 // (A^T and D^-T when TR); x, b, y node-interleaved [N][5].
-template <typename T, bool TR, int MODE>
-__global__ __launch_bounds__(BS) void bsr_kernel(Grid g, const T* __restrict__ A, const T* __restrict__ Dinv,
+template <typename TM, typename T, bool TR, int MODE>
+__global__ __launch_bounds__(BS) void bsr_kernel(Grid g, const TM* __restrict__ A, const TM* __restrict__ Dinv,
                                                  const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y,
                                                  T omega, long N) {
   const long n = (long)blockIdx.x * BS + threadIdx.x;
@@ -181,12 +337,12 @@ __global__ __launch_bounds__(BS) void bsr_kernel(Grid g, const T* __restrict__ A
 #pragma unroll
       for (int f = 0; f < 5; ++f)
 #pragma unroll
-        for (int gg = 0; gg < 5; ++gg) acc[f] += A[(size_t)(o * 25 + f * 5 + gg) * N + n] * xm[gg];
+        for (int gg = 0; gg < 5; ++gg) acc[f] += (T)A[(size_t)(o * 25 + f * 5 + gg) * N + n] * xm[gg];
     } else {
 #pragma unroll
       for (int f = 0; f < 5; ++f)
 #pragma unroll
-        for (int gg = 0; gg < 5; ++gg) acc[gg] += A[(size_t)((26 - o) * 25 + f * 5 + gg) * N + m] * xm[f];
+        for (int gg = 0; gg < 5; ++gg) acc[gg] += (T)A[(size_t)((26 - o) * 25 + f * 5 + gg) * N + m] * xm[f];
     }
   }
   if (MODE == 0) {
@@ -206,7 +362,7 @@ __global__ __launch_bounds__(BS) void bsr_kernel(Grid g, const T* __restrict__ A
   for (int f = 0; f < 5; ++f) {
     T z = 0;
 #pragma unroll
-    for (int gg = 0; gg < 5; ++gg) z += (TR ? Dinv[(size_t)(gg * 5 + f) * N + n] : Dinv[(size_t)(f * 5 + gg) * N + n]) * r[gg];
+    for (int gg = 0; gg < 5; ++gg) z += (T)(TR ? Dinv[(size_t)(gg * 5 + f) * N + n] : Dinv[(size_t)(f * 5 + gg) * N + n]) * r[gg];
     y[5 * n + f] = x[5 * n + f] + omega * z;
   }
 }
@@ -231,13 +387,14 @@ __global__ void scale_fields_kernel(const Ta* __restrict__ in, Tb* __restrict__ 
 }
 
 // diagonal entries of A into d [N][5] (0 on constrained dofs)
-__global__ void diagonal_kernel(Grid g, const double* __restrict__ A, double* __restrict__ d, long N) {
+template <typename TM>
+__global__ void diagonal_kernel(Grid g, const TM* __restrict__ A, double* __restrict__ d, long N) {
   const long n = (long)blockIdx.x * BS + threadIdx.x;
   if (n >= N) return;
   int i, j, k;
   node_ijk(g, n, i, j, k);
 #pragma unroll
-  for (int f = 0; f < 5; ++f) d[5 * n + f] = fixed(g, i, j, k, f) ? 0.0 : A[(size_t)(13 * 25 + f * 6) * N + n];
+  for (int f = 0; f < 5; ++f) d[5 * n + f] = fixed(g, i, j, k, f) ? 0.0 : (double)A[(size_t)(13 * 25 + f * 6) * N + n];
 }
 
 // x = omega D^-1 b (D^-T): the first sweep from a zero guess
@@ -519,17 +676,19 @@ void launch_assemble(hipStream_t st, const Grid& g, const NsConst& c, const doub
   launch_fill<T>(st, A, (long)NS_ENTRIES * N, (T)0);
   for (int col = 0; col < 8; ++col) {
     const ColourGrid cg = colour_grid(g, col);
-    if (cg.count > 0) launch(assemble_kernel<T>, dim3(blocks(cg.count * 40)), dim3(BS), 0, st, g, c, cg, coef, s, A, N);
+    if (cg.count > 0)
+      launch(assemble_shared_kernel<T>, dim3((unsigned)((cg.count + AS_E - 1) / AS_E)), dim3(5 * 64), 0, st, g, c, cg,
+             coef, s, A, N);
   }
   launch(fix_kernel<T>, dim3(blocks(N)), dim3(BS), 0, st, g, A, N);
 }
 
-template <typename T>
-void launch_bsr(hipStream_t st, const Grid& g, const T* A, const T* Dinv, bool tr, int mode, const T* x, const T* b,
+template <typename TM, typename T>
+void launch_bsr(hipStream_t st, const Grid& g, const TM* A, const TM* Dinv, bool tr, int mode, const T* x, const T* b,
                 T* y, T omega) {
   const long N = g.nodes();
   const dim3 gr(blocks(N));
-#define NS_BSR(TRV, M) launch(bsr_kernel<T, TRV, M>, gr, dim3(BS), 0, st, g, A, Dinv, x, b, y, omega, N)
+#define NS_BSR(TRV, M) launch(bsr_kernel<TM, T, TRV, M>, gr, dim3(BS), 0, st, g, A, Dinv, x, b, y, omega, N)
   if (!tr) {
     if (mode == 0) NS_BSR(false, 0);
     else if (mode == 1) NS_BSR(false, 1);
@@ -575,9 +734,12 @@ void launch_scale_fields(hipStream_t st, long N, const Ta* in, Tb* out, const Fi
 template void launch_scale_fields<double, double>(hipStream_t, long, const double*, double*, const Field5&);
 template void launch_scale_fields<double, float>(hipStream_t, long, const double*, float*, const Field5&);
 
-void launch_diagonal(hipStream_t st, const Grid& g, const double* A, double* d) {
-  launch(diagonal_kernel, dim3(blocks(g.nodes())), dim3(BS), 0, st, g, A, d, g.nodes());
+template <typename TM>
+void launch_diagonal(hipStream_t st, const Grid& g, const TM* A, double* d) {
+  launch(diagonal_kernel<TM>, dim3(blocks(g.nodes())), dim3(BS), 0, st, g, A, d, g.nodes());
 }
+template void launch_diagonal<double>(hipStream_t, const Grid&, const double*, double*);
+template void launch_diagonal<float>(hipStream_t, const Grid&, const float*, double*);
 
 void launch_inject(hipStream_t st, const Grid& gf, const Grid& gc, const double* sf, double* sc) {
   launch(inject_kernel, dim3(blocks(gc.nodes())), dim3(BS), 0, st, gf, gc, sf, sc);
@@ -614,7 +776,7 @@ void launch_sensitivity(hipStream_t st, const Grid& g, const NsConst& c, const d
 #define NS_INST(T)                                                                                                    \
   template void launch_fill<T>(hipStream_t, T*, long, T);                                                              \
   template void launch_assemble<T>(hipStream_t, const Grid&, const NsConst&, const double*, const double*, T*);        \
-  template void launch_bsr<T>(hipStream_t, const Grid&, const T*, const T*, bool, int, const T*, const T*, T*, T);     \
+  template void launch_bsr<T, T>(hipStream_t, const Grid&, const T*, const T*, bool, int, const T*, const T*, T*, T);  \
   template void launch_diag_scale<T>(hipStream_t, const Grid&, const T*, bool, T, const T*, T*);                       \
   template void launch_diag_inverse<T>(hipStream_t, const Grid&, const T*, T*);                                        \
   template void launch_restrict<T>(hipStream_t, const Grid&, const Grid&, const T*, T*);                               \
@@ -623,6 +785,7 @@ void launch_sensitivity(hipStream_t st, const Grid& g, const NsConst& c, const d
 NS_INST(float)
 NS_INST(double)
 #undef NS_INST
+
 
 }  // namespace ns
 }  // namespace nc

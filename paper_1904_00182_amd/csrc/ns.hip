@@ -294,7 +294,7 @@ void linearize_t(nc_ns_ctx* c, const double* s) {
   const double t0 = now();
   NsLevel& L0 = c->lev[0];
   nc::ns::launch_assemble<double>(st, L0.g, L0.c, L0.coef, s, c->A64);
-  launch_diagonal(st, L0.g, c->A64, c->bs);
+  launch_diagonal<double>(st, L0.g, c->A64, c->bs);
   {
     double dn[10];
     field_norms(c, c->bs, nullptr, dn);
@@ -327,6 +327,9 @@ void linearize_t(nc_ns_ctx* c, const double* s) {
   c->lin_s = s;
 }
 
+// The Krylov operator stays the float64 Jacobian in NC_MIXED as well: with a float32 one
+// the Newton steps lose their quadratic convergence on these ill-conditioned systems
+// (measured: 25 Newton steps instead of 3 on the 128x64x128 cavity).
 void linearize(nc_ns_ctx* c, const double* s) {
   if (c->mixed) linearize_t<float>(c, s);
   else linearize_t<double>(c, s);
@@ -351,7 +354,7 @@ T* vcycle(nc_ns_ctx* c, int l, bool tr) {
     }
     nc::ns::launch_diag_scale<T>(st, L.g, Di, tr, om, b, cur);
     for (int k = 1; k < COARSE_SWEEPS; ++k) {
-      nc::ns::launch_bsr<T>(st, L.g, A, Di, tr, 2, cur, b, nxt, om);
+      nc::ns::launch_bsr<T, T>(st, L.g, A, Di, tr, 2, cur, b, nxt, om);
       std::swap(cur, nxt);
     }
     return cur;
@@ -360,16 +363,16 @@ T* vcycle(nc_ns_ctx* c, int l, bool tr) {
   const int npost = l == 0 ? c->p.smooth_post : c->p.smooth_post_coarse;
   nc::ns::launch_diag_scale<T>(st, L.g, Di, tr, om, b, cur);
   for (int k = 1; k < npre; ++k) {
-    nc::ns::launch_bsr<T>(st, L.g, A, Di, tr, 2, cur, b, nxt, om);
+    nc::ns::launch_bsr<T, T>(st, L.g, A, Di, tr, 2, cur, b, nxt, om);
     std::swap(cur, nxt);
   }
-  nc::ns::launch_bsr<T>(st, L.g, A, Di, tr, 1, cur, b, (T*)L.r, om);
+  nc::ns::launch_bsr<T, T>(st, L.g, A, Di, tr, 1, cur, b, (T*)L.r, om);
   NsLevel& C = c->lev[l + 1];
   nc::ns::launch_restrict<T>(st, L.g, C.g, (const T*)L.r, (T*)C.b);
   T* xc = vcycle<T>(c, l + 1, tr);
   nc::ns::launch_prolong_add<T>(st, L.g, C.g, xc, cur);
   for (int k = 0; k < npost; ++k) {
-    nc::ns::launch_bsr<T>(st, L.g, A, Di, tr, 2, cur, b, nxt, om);
+    nc::ns::launch_bsr<T, T>(st, L.g, A, Di, tr, 2, cur, b, nxt, om);
     std::swap(cur, nxt);
   }
   return cur;
@@ -394,7 +397,7 @@ void precondition(nc_ns_ctx* c, bool tr, const double* v, double* z, const Field
 const Field5 kUnit{{1.0, 1.0, 1.0, 1.0, 1.0}};
 
 void apply(nc_ns_ctx* c, bool tr, const double* x, double* y) {
-  nc::ns::launch_bsr<double>(c->stream, c->lev[0].g, c->A64, nullptr, tr, 0, x, nullptr, y, 0.0);
+  nc::ns::launch_bsr<double, double>(c->stream, c->lev[0].g, c->A64, nullptr, tr, 0, x, nullptr, y, 0.0);
 }
 
 // y = S^-1 A x (A^T when tr): the operator of the equilibrated Krylov system

@@ -39,8 +39,8 @@ void launch_residual(hipStream_t st, const Grid& g, const NsConst& c, const Patc
 template <typename T>
 void launch_assemble(hipStream_t st, const Grid& g, const NsConst& c, const double* coef, const double* s, T* A);
 // mode 0: y = A x; 1: y = b - A x; 2: y = x + omega D^-1 (b - A x); transposes when tr
-template <typename T>
-void launch_bsr(hipStream_t st, const Grid& g, const T* A, const T* Dinv, bool tr, int mode, const T* x, const T* b,
+template <typename TM, typename T>
+void launch_bsr(hipStream_t st, const Grid& g, const TM* A, const TM* Dinv, bool tr, int mode, const T* x, const T* b,
                 T* y, T omega);
 template <typename T>
 void launch_diag_scale(hipStream_t st, const Grid& g, const T* Dinv, bool tr, T omega, const T* b, T* x);
@@ -57,8 +57,9 @@ struct Field5 {
 // out[n][f] = sc.s[f] in[n][f] for [N][5] arrays (in == out allowed)
 template <typename Ta, typename Tb>
 void launch_scale_fields(hipStream_t st, long N, const Ta* in, Tb* out, const Field5& sc);
-// d [N][5] = the diagonal of the float64 node-block matrix A (0 on constrained dofs)
-void launch_diagonal(hipStream_t st, const Grid& g, const double* A, double* d);
+// d [N][5] = the diagonal of the node-block matrix A (0 on constrained dofs)
+template <typename TM>
+void launch_diagonal(hipStream_t st, const Grid& g, const TM* A, double* d);
 // constrained dofs of s [N][5] set to 0
 void launch_mask(hipStream_t st, const Grid& g, double* s);
 void launch_inject(hipStream_t st, const Grid& gf, const Grid& gc, const double* sf, double* sc);
