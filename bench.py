@@ -55,9 +55,6 @@ PROFILE_NAMES = {
 }
 # kernel sources whose hash must match the one recorded with the counter runs: every
 # source of the library
-KERNEL_SOURCES = sorted("paper_1904_00182_amd/csrc/" + f for f in os.listdir(os.path.join(ROOT, "paper_1904_00182_amd", "csrc"))
-                        if f.endswith((".hip", ".hpp")))
-
 
 def measured_counters(cls, tname):
     """(HBM bytes, VALU instructions) per launch of the class's kernel from the committed
@@ -75,15 +72,22 @@ def measured_counters(cls, tname):
 
 
 def _counter_record():
+    """The committed counter summary, if the sources it was taken with are unchanged: the
+    record lists every kernel source file of the library at the time (all of them go into
+    the operator kernels' build) and their SHA-256; a file added later, which those kernels
+    do not include, does not invalidate it."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_cavity128x64x128_mixed.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    files = rec.get("source_files")
+    if not files or not all(os.path.exists(os.path.join(ROOT, f)) for f in files):
+        return None
     h = hashlib.sha256()
-    for s in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, s), "rb").read())
-    if rec.get("source_sha256") != h.hexdigest() or rec.get("source_files", KERNEL_SOURCES) != KERNEL_SOURCES:
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest():
         return None
     return rec
 
@@ -92,24 +96,7 @@ def measured_traffic(cls, tname):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) of the class's kernel from
     the committed counter summary, or None when there is none or the kernel sources have
     changed since the counters were taken."""
-    import hashlib
-    import re
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_cavity128x64x128_mixed.json")
-    if not os.path.exists(path):
-        return None
-    rec = json.load(open(path))
-    h = hashlib.sha256()
-    for s in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, s), "rb").read())
-    if rec.get("source_sha256") != h.hexdigest():
-        return None
-    pat = re.compile(PROFILE_NAMES[cls].format(t=tname) + "$")
-    if rec.get("source_files") and rec["source_files"] != KERNEL_SOURCES:
-        return None
-    for name, v in rec["kernels"].items():
-        if pat.match(name):
-            return round(v["fetch_bytes"] + v["write_bytes"])
-    return None
+    return measured_counters(cls, tname)[0]
 
 
 def parse():
