@@ -109,6 +109,7 @@ typedef struct nc_problem {
                                  an FGMRES solve has stalled (its first restart cycle did not
                                  halve the residual: undamped block Jacobi diverges on
                                  strongly convective blocks); the stalled solve is redone.
+                                 Only a stronger damping than the current one is taken over.
                                  0: no fallback                                          */
 } nc_problem;
 

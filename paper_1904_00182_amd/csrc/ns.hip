@@ -496,11 +496,11 @@ int fgmres(nc_ns_ctx* c, bool tr, const double* b_in, double* x, double rtol, in
 }
 
 // fgmres, switching the context to the fallback damping for good (and solving again from
-// zero) when the first restart cycle stalls
+// zero) when the first restart cycle stalls; the fallback only ever damps more
 int krylov(nc_ns_ctx* c, bool tr, const double* b, double* x, double rtol, double* relres) {
   const double fb = c->p.smooth_omega_fallback;
   bool stalled = false;
-  int its = fgmres(c, tr, b, x, rtol, c->p.krylov_maxit, relres, fb > 0.0 && c->omega != fb ? &stalled : nullptr);
+  int its = fgmres(c, tr, b, x, rtol, c->p.krylov_maxit, relres, fb > 0.0 && fb < c->omega ? &stalled : nullptr);
   if (its < 0 || !stalled) return its;
   c->omega = fb;
   const int more = fgmres(c, tr, b, x, rtol, c->p.krylov_maxit, relres);

@@ -759,7 +759,7 @@ int reduced_solve(nc_ctx* c, bool tr, const double* r, double* d, bool krylov, d
   if (krylov) {
     bool stalled = false;
     its = fgmres<T>(c, tr, kb, kx, rtol, c->p.krylov_maxit, relres,
-                    c->p.smooth_omega_fallback > 0.0 && c->omega != c->p.smooth_omega_fallback ? &stalled : nullptr);
+                    c->p.smooth_omega_fallback > 0.0 && c->p.smooth_omega_fallback < c->omega ? &stalled : nullptr);
     if (its < 0) return its;
     if (stalled) {
       // switch this context to the fallback damping for good and solve again from zero

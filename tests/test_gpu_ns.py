@@ -161,3 +161,25 @@ def test_preconditioner_transpose_pairing_and_reproducibility():
     s1 = sol.solve_state()
     s2 = sol.solve_state()
     assert torch.equal(s1, s2)
+
+
+def test_odd_grid_single_level_without_dense_coarsest():
+    """9x5x9 (odd, so no coarser level; 3,000 unknowns, above the dense limit): the
+    preconditioner is the smoother alone on that one level; state, adjoint and
+    sensitivities still match the oracle."""
+    grid = (9, 5, 9)
+    kw = dict(alpha=1e3, q_h=5.0, Q=20.0, q_box=(0.3, 0.7, 0.2, 0.8, 0.0, 0.4), krylov_maxit=2000)
+    p, x, model, sol = _pair(grid, kw, 23)
+    s = sol.solve_state()
+    info = sol.last_info
+    assert info["status"] == nc.NC_OK and info["levels"] == 1, info
+    so, _ = model.solve_state()
+    check_fields(s.cpu().numpy(), so, 1e-9, "odd-grid state")
+    g = sol.objective_grad(s)
+    lam = sol.solve_adjoint(s, g)
+    assert sol.last_info["status"] == nc.NC_OK, sol.last_info
+    lo = model.solve_adjoint(so, model.dfds(so))
+    check_fields(lam.cpu().numpy(), lo, 1e-8, "odd-grid adjoint")
+    dfdx = sol.sensitivity(s, lam).cpu().numpy()
+    _, do = model.sensitivity(so, lo, explicit=True)
+    assert np.linalg.norm(dfdx - do) <= 1e-8 * np.linalg.norm(do)
