@@ -10,6 +10,7 @@
 // every step is one fused node kernel (stencil apply, iterate and residual update, next
 // direction), the step coefficients are host constants, there is no host round trip and
 // the result is bitwise reproducible.
+#include <algorithm>
 #include <cmath>
 #include <utility>
 
@@ -41,10 +42,6 @@ void element_pattern(double h, double r, double a[8]) {
 
 struct HelmCoef {
   double a[8];   // element pattern entries
-  // interior stencil: the pattern entry depends only on how many coordinates two nodes
-  // share, and an interior node shares 8 / 4 / 2 / 1 elements with itself / a face / an
-  // edge / a corner neighbour
-  double w_centre, w_face, w_edge, w_corner;
 };
 
 // n / d for 0 <= n < 2^31 by a multiply-high and a shift (division by an invariant
@@ -68,36 +65,6 @@ struct NodeGrid {
   FastDiv nx1, nxy;   // divisions by nx + 1 and (nx + 1)(ny + 1)
 };
 
-// (K_F d)_n for node (i, j, k): neighbour n + o couples through the elements the two share;
-// each of them contributes the same pattern entry (s_d = [o_d == 0]), and their number is
-// the product over d of 2 (o_d = 0, node inside in d), 1 (o_d = 0 on a wall, or o_d = +-1
-// with the neighbour on the grid) or 0 (neighbour off the grid).
-__device__ inline double helm_apply_row(const Grid& g, const HelmCoef& c, const double* __restrict__ d, int i, int j,
-                                        int k) {
-  const int nx1 = g.nx + 1, nxy = (g.nx + 1) * (g.ny + 1);
-  const int cx0 = (i > 0 && i < g.nx) ? 2 : 1, cy0 = (j > 0 && j < g.ny) ? 2 : 1, cz0 = (k > 0 && k < g.nz) ? 2 : 1;
-  const int n = g.node(i, j, k);
-  double acc = 0.0;
-#pragma unroll
-  for (int oz = -1; oz <= 1; ++oz) {
-    const int cz = oz == 0 ? cz0 : ((k + oz >= 0 && k + oz <= g.nz) ? 1 : 0);
-    if (cz == 0) continue;
-#pragma unroll
-    for (int oy = -1; oy <= 1; ++oy) {
-      const int cy = oy == 0 ? cy0 : ((j + oy >= 0 && j + oy <= g.ny) ? 1 : 0);
-      if (cy == 0) continue;
-#pragma unroll
-      for (int ox = -1; ox <= 1; ++ox) {
-        const int cx = ox == 0 ? cx0 : ((i + ox >= 0 && i + ox <= g.nx) ? 1 : 0);
-        if (cx == 0) continue;
-        const int p = (ox == 0) + 2 * (oy == 0) + 4 * (oz == 0);
-        acc += (double)(cx * cy * cz) * c.a[p] * d[n + ox + nx1 * oy + nxy * oz];
-      }
-    }
-  }
-  return acc;
-}
-
 struct NodeIdx {
   int i, j, k, n;
   bool ok;
@@ -119,17 +86,6 @@ __device__ inline NodeIdx node_idx(const NodeGrid& ng) {
   q.j = (int)j;
   q.i = (int)(rem - j * ng.nx1.d);
   return q;
-}
-
-// (K_F d)_n of an interior node: the constant 27-point stencil
-__device__ inline double helm_apply_interior(const HelmCoef& c, const double* __restrict__ d, int n, int sy, int sz) {
-  const double face = d[n - 1] + d[n + 1] + d[n - sy] + d[n + sy] + d[n - sz] + d[n + sz];
-  const double edge = d[n - 1 - sy] + d[n + 1 - sy] + d[n - 1 + sy] + d[n + 1 + sy] + d[n - 1 - sz] +
-                      d[n + 1 - sz] + d[n - 1 + sz] + d[n + 1 + sz] + d[n - sy - sz] + d[n + sy - sz] +
-                      d[n - sy + sz] + d[n + sy + sz];
-  const double corner = d[n - 1 - sy - sz] + d[n + 1 - sy - sz] + d[n - 1 + sy - sz] + d[n + 1 + sy - sz] +
-                        d[n - 1 - sy + sz] + d[n + 1 - sy + sz] + d[n - 1 + sy + sz] + d[n + 1 + sy + sz];
-  return c.w_centre * d[n] + c.w_face * face + c.w_edge * edge + c.w_corner * corner;
 }
 
 // b = s_in * (sum of x over the elements around each node); the iteration starts from
@@ -158,23 +114,84 @@ __global__ __launch_bounds__(BS) void helm_init_kernel(NodeGrid ng, double s_in,
   d[n] = inv_theta * b / (g.valence(q.i, q.j, q.k) * a_diag);
 }
 
-// One Chebyshev step: y += d, r -= K_F d, d' = c1 d + c2 D^-1 r.
-__global__ __launch_bounds__(BS) void helm_cheb_kernel(NodeGrid ng, HelmCoef c, double c1, double c2,
-                                                       const double* __restrict__ d, double* __restrict__ d_next,
-                                                       double* __restrict__ y, double* __restrict__ r) {
-  const Grid& g = ng.g;
-  const NodeIdx q = node_idx(ng);
-  if (!q.ok) return;
-  const int n = q.n;
-  const double dn = d[n];
-  const bool inner = q.i > 0 && q.i < g.nx && q.j > 0 && q.j < g.ny && q.k > 0 && q.k < g.nz;
-  const double Ad = inner ? helm_apply_interior(c, d, n, g.nx + 1, (g.nx + 1) * (g.ny + 1))
-                          : helm_apply_row(g, c, d, q.i, q.j, q.k);
-  const double diag = inner ? c.w_centre : g.valence(q.i, q.j, q.k) * c.a[7];
-  y[n] += dn;
-  const double rn = r[n] - Ad;
-  r[n] = rn;
-  d_next[n] = c1 * dn + c2 * rn / diag;
+// One Chebyshev step, y += d, r -= K_F d, d' = c1 d + c2 D^-1 r, with the direction staged
+// in LDS: a workgroup of CT_X x CT_Y threads owns
+// a CT_X x CT_Y tile of node columns and marches up its z range, keeping three node planes
+// of d (the tile and a one-node halo, zero off the grid) in a ring of LDS buffers, so that
+// each value of d is read from memory about once instead of once per neighbour.  Row n of
+// K_F: neighbour n + o couples through the elements the two share; each of them contributes
+// the same pattern entry (s_d = [o_d == 0]), and their number is the product over d of 2
+// (o_d = 0, node inside in d), 1 (o_d = 0 on a wall, or o_d = +-1 with the neighbour on the
+// grid) or 0 (neighbour off the grid); an interior row is the constant 27-point stencil.
+// Summed in a fixed order, so results are bitwise reproducible.
+constexpr int CT_X = 32, CT_Y = 8, CT_LX = CT_X + 2, CT_LY = CT_Y + 2;
+
+__device__ inline void helm_load_plane(const Grid& g, const double* __restrict__ d, int k, int gi0, int gj0,
+                                       double* __restrict__ buf) {
+  const bool zin = k >= 0 && k <= g.nz;
+  for (int t = threadIdx.x; t < CT_LX * CT_LY; t += CT_X * CT_Y) {
+    const int li = t % CT_LX, lj = t / CT_LX;
+    const int gi = gi0 - 1 + li, gj = gj0 - 1 + lj;
+    buf[t] = (zin && gi >= 0 && gi <= g.nx && gj >= 0 && gj <= g.ny) ? d[g.node(gi, gj, k)] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(CT_X* CT_Y) void helm_cheb_tiled_kernel(Grid g, HelmCoef c, double c1, double c2,
+                                                                     int chunks, const double* __restrict__ d,
+                                                                     double* __restrict__ d_next, double* __restrict__ y,
+                                                                     double* __restrict__ r) {
+  __shared__ double ring[3][CT_LX * CT_LY];
+  const int tx = threadIdx.x % CT_X, ty = threadIdx.x / CT_X;
+  const int ntx = (g.nx + CT_X) / CT_X;                      // tiles over the nx + 1 node columns
+  const int tile = blockIdx.x % (ntx * ((g.ny + CT_Y) / CT_Y)), chunk = blockIdx.x / (ntx * ((g.ny + CT_Y) / CT_Y));
+  const int gi0 = (tile % ntx) * CT_X, gj0 = (tile / ntx) * CT_Y;
+  const int i = gi0 + tx, j = gj0 + ty;
+  const int K0 = (int)((long)chunk * (g.nz + 1) / chunks), K1 = (int)((long)(chunk + 1) * (g.nz + 1) / chunks);
+  const bool own = i <= g.nx && j <= g.ny;
+  // count factors of the element-count row in x and y (offset -1, 0, +1)
+  double cxy[3][3];
+  {
+    double cx[3], cy[3];
+    for (int o = -1; o <= 1; ++o) {
+      cx[o + 1] = o == 0 ? ((i > 0 && i < g.nx) ? 2.0 : 1.0) : ((i + o >= 0 && i + o <= g.nx) ? 1.0 : 0.0);
+      cy[o + 1] = o == 0 ? ((j > 0 && j < g.ny) ? 2.0 : 1.0) : ((j + o >= 0 && j + o <= g.ny) ? 1.0 : 0.0);
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) cxy[a][b] = cx[b] * cy[a];
+  }
+  helm_load_plane(g, d, K0 - 1, gi0, gj0, ring[(K0 + 2) % 3]);
+  helm_load_plane(g, d, K0, gi0, gj0, ring[K0 % 3]);
+  const int li = tx + 1, lj = ty + 1;
+  for (int k = K0; k < K1; ++k) {
+    helm_load_plane(g, d, k + 1, gi0, gj0, ring[(k + 1) % 3]);
+    // the node's own iterate and residual, loaded before the barrier so that their latency
+    // overlaps the wait
+    const int n = own ? g.node(i, j, k) : 0;
+    const double yn = own ? y[n] : 0.0, rn0 = own ? r[n] : 0.0;
+    __syncthreads();
+    if (own) {
+      double acc = 0.0;
+#pragma unroll
+      for (int oz = -1; oz <= 1; ++oz) {
+        const double cz = oz == 0 ? ((k > 0 && k < g.nz) ? 2.0 : 1.0) : ((k + oz >= 0 && k + oz <= g.nz) ? 1.0 : 0.0);
+        const double* pl = ring[(k + oz + 3) % 3];
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+          for (int ox = -1; ox <= 1; ++ox) {
+            const int p = (ox == 0) + 2 * (oy == 0) + 4 * (oz == 0);
+            acc += cz * cxy[oy + 1][ox + 1] * c.a[p] * pl[(li + ox) + CT_LX * (lj + oy)];
+          }
+      }
+      const double dn = ring[k % 3][li + CT_LX * lj];
+      const double diag = cxy[1][1] * ((k > 0 && k < g.nz) ? 2.0 : 1.0) * c.a[7];
+      y[n] = yn + dn;
+      const double rn = rn0 - acc;
+      r[n] = rn;
+      d_next[n] = c1 * dn + c2 * rn / diag;
+    }
+    __syncthreads();
+  }
 }
 
 // out_e = s_out * sum of (y + d) over the element's eight nodes (the last direction is
@@ -242,10 +259,6 @@ void launch_pde_filter(hipStream_t st, const Grid& g, const HelmholtzPlan& pl, c
   double* d1 = work + 3 * N;
   HelmCoef c;
   element_pattern(pl.h, pl.r, c.a);
-  c.w_centre = 8.0 * c.a[7];
-  c.w_face = 4.0 * c.a[3];     // two coordinates shared (pattern 3, 5 or 6: equal on a cube)
-  c.w_edge = 2.0 * c.a[1];     // one coordinate shared
-  c.w_corner = c.a[0];
   NodeGrid ng{g, FastDiv((unsigned)(g.nx + 1)), FastDiv((unsigned)((g.nx + 1) * (g.ny + 1)))};
   // Chebyshev acceleration (Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1)
   // with the Jacobi preconditioner on [lmin, lmax]
@@ -254,10 +267,13 @@ void launch_pde_filter(hipStream_t st, const Grid& g, const HelmholtzPlan& pl, c
   const double h3 = pl.h * pl.h * pl.h;
   launch(helm_init_kernel, dim3(blocks_for(N)), dim3(BS), 0, st, ng, h3 / 8.0, c.a[7], 1.0 / theta, x, yy, rr, d0);
   double rho = 1.0 / sigma1;
+  // tiles of CT_X x CT_Y node columns times z chunks of about 4 node planes
+  const int tiles = ((g.nx + CT_X) / CT_X) * ((g.ny + CT_Y) / CT_Y);
+  const int chunks = std::max(1, std::min(g.nz + 1, (g.nz + 1 + 3) / 4));
   for (int s = 0; s < pl.steps; ++s) {
     const double rho_next = 1.0 / (2.0 * sigma1 - rho);
-    launch(helm_cheb_kernel, dim3(blocks_for(N)), dim3(BS), 0, st, ng, c, rho_next * rho, 2.0 * rho_next / delta,
-           (const double*)d0, d1, yy, rr);
+    launch(helm_cheb_tiled_kernel, dim3((unsigned)(tiles * chunks)), dim3(CT_X * CT_Y), 0, st, g, c, rho_next * rho,
+           2.0 * rho_next / delta, chunks, (const double*)d0, d1, yy, rr);
     rho = rho_next;
     std::swap(d0, d1);
   }
