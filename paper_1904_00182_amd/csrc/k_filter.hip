@@ -115,39 +115,68 @@ __global__ __launch_bounds__(BS) void helm_init_kernel(NodeGrid ng, double s_in,
 }
 
 // One Chebyshev step, y += d, r -= K_F d, d' = c1 d + c2 D^-1 r, with the direction staged
-// in LDS: a workgroup of CT_X x CT_Y threads owns
-// a CT_X x CT_Y tile of node columns and marches up its z range, keeping three node planes
-// of d (the tile and a one-node halo, zero off the grid) in a ring of LDS buffers, so that
-// each value of d is read from memory about once instead of once per neighbour.  Row n of
-// K_F: neighbour n + o couples through the elements the two share; each of them contributes
-// the same pattern entry (s_d = [o_d == 0]), and their number is the product over d of 2
-// (o_d = 0, node inside in d), 1 (o_d = 0 on a wall, or o_d = +-1 with the neighbour on the
-// grid) or 0 (neighbour off the grid); an interior row is the constant 27-point stencil.
-// Summed in a fixed order, so results are bitwise reproducible.
-constexpr int CT_X = 32, CT_Y = 8, CT_LX = CT_X + 2, CT_LY = CT_Y + 2;
+// in LDS: a workgroup of CT_X x CT_Y threads owns a CT_X x CT_Y tile of node columns over a
+// chunk of CT_Z node planes and stages the CT_Z + 2 planes of d it touches (the tile and a
+// one-node halo, zero off the grid) in LDS, so that each value of d is read from memory
+// about once instead of once per neighbour.  Every load of the chunk (d, and the own nodes'
+// y and r) is issued before the first LDS store and the workgroup waits at one barrier, so
+// the memory latency is paid once per chunk rather than once per plane.  Row n of K_F:
+// neighbour n + o couples through the elements the two share; each of them contributes the
+// same pattern entry (s_d = [o_d == 0]), and their number is the product over d of 2 (o_d = 0,
+// node inside in d), 1 (o_d = 0 on a wall, or o_d = +-1 with the neighbour on the grid) or 0
+// (neighbour off the grid); an interior row is the constant 27-point stencil.  Summed in a
+// fixed order, so results are bitwise reproducible.
+constexpr int CT_X = 32, CT_Y = 8, CT_Z = 4, CT_LX = CT_X + 2, CT_LY = CT_Y + 2;
+constexpr int CT_THREADS = CT_X * CT_Y, CT_PLANE = CT_LX * CT_LY;
+constexpr int CT_SLOTS = (CT_PLANE + CT_THREADS - 1) / CT_THREADS;  // plane values per thread
 
-__device__ inline void helm_load_plane(const Grid& g, const double* __restrict__ d, int k, int gi0, int gj0,
-                                       double* __restrict__ buf) {
-  const bool zin = k >= 0 && k <= g.nz;
-  for (int t = threadIdx.x; t < CT_LX * CT_LY; t += CT_X * CT_Y) {
-    const int li = t % CT_LX, lj = t / CT_LX;
-    const int gi = gi0 - 1 + li, gj = gj0 - 1 + lj;
-    buf[t] = (zin && gi >= 0 && gi <= g.nx && gj >= 0 && gj <= g.ny) ? d[g.node(gi, gj, k)] : 0.0;
-  }
-}
-
-__global__ __launch_bounds__(CT_X* CT_Y) void helm_cheb_tiled_kernel(Grid g, HelmCoef c, double c1, double c2,
-                                                                     int chunks, const double* __restrict__ d,
-                                                                     double* __restrict__ d_next, double* __restrict__ y,
-                                                                     double* __restrict__ r) {
-  __shared__ double ring[3][CT_LX * CT_LY];
+__global__ __launch_bounds__(CT_THREADS) void helm_cheb_tiled_kernel(Grid g, HelmCoef c, double c1, double c2,
+                                                                    int tiles, const double* __restrict__ d,
+                                                                    double* __restrict__ d_next,
+                                                                    double* __restrict__ y, double* __restrict__ r) {
+  __shared__ double buf[CT_Z + 2][CT_PLANE];
+  // workgroups are dealt to the eight XCDs in turn; the logical block id is chosen so that
+  // each XCD runs a contiguous range of them, and tiles that share halo planes and cache
+  // lines share that XCD's L2
+  const int nb = (int)gridDim.x, xcd = (int)blockIdx.x % 8, q8 = nb / 8, rem8 = nb % 8;
+  const int lb = xcd * q8 + min(xcd, rem8) + (int)blockIdx.x / 8;
+  const int tile = lb % tiles, chunk = lb / tiles;
   const int tx = threadIdx.x % CT_X, ty = threadIdx.x / CT_X;
   const int ntx = (g.nx + CT_X) / CT_X;                      // tiles over the nx + 1 node columns
-  const int tile = blockIdx.x % (ntx * ((g.ny + CT_Y) / CT_Y)), chunk = blockIdx.x / (ntx * ((g.ny + CT_Y) / CT_Y));
   const int gi0 = (tile % ntx) * CT_X, gj0 = (tile / ntx) * CT_Y;
   const int i = gi0 + tx, j = gj0 + ty;
-  const int K0 = (int)((long)chunk * (g.nz + 1) / chunks), K1 = (int)((long)(chunk + 1) * (g.nz + 1) / chunks);
+  const int K0 = chunk * CT_Z, nk = min(CT_Z, g.nz + 1 - K0);
   const bool own = i <= g.nx && j <= g.ny;
+  // planes K0 - 1 .. K0 + CT_Z of d; a plane beyond nz (the last chunk's tail) reads as zero
+  double v[CT_Z + 2][CT_SLOTS];
+#pragma unroll
+  for (int p = 0; p < CT_Z + 2; ++p) {
+    const int k = K0 - 1 + p;
+    const bool zin = k >= 0 && k <= g.nz;
+#pragma unroll
+    for (int s = 0; s < CT_SLOTS; ++s) {
+      const int t = (int)threadIdx.x + s * CT_THREADS;
+      const int gi = gi0 - 1 + t % CT_LX, gj = gj0 - 1 + t / CT_LX;
+      v[p][s] = (t < CT_PLANE && zin && gi >= 0 && gi <= g.nx && gj >= 0 && gj <= g.ny) ? d[g.node(gi, gj, k)] : 0.0;
+    }
+  }
+  double yv[CT_Z], rv[CT_Z];
+#pragma unroll
+  for (int p = 0; p < CT_Z; ++p) {
+    const bool ok = own && p < nk;
+    const int n = ok ? g.node(i, j, K0 + p) : 0;
+    yv[p] = ok ? y[n] : 0.0;
+    rv[p] = ok ? r[n] : 0.0;
+  }
+#pragma unroll
+  for (int p = 0; p < CT_Z + 2; ++p)
+#pragma unroll
+    for (int s = 0; s < CT_SLOTS; ++s) {
+      const int t = (int)threadIdx.x + s * CT_THREADS;
+      if (t < CT_PLANE) buf[p][t] = v[p][s];
+    }
+  __syncthreads();
+  if (!own) return;
   // count factors of the element-count row in x and y (offset -1, 0, +1)
   double cxy[3][3];
   {
@@ -159,38 +188,31 @@ __global__ __launch_bounds__(CT_X* CT_Y) void helm_cheb_tiled_kernel(Grid g, Hel
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) cxy[a][b] = cx[b] * cy[a];
   }
-  helm_load_plane(g, d, K0 - 1, gi0, gj0, ring[(K0 + 2) % 3]);
-  helm_load_plane(g, d, K0, gi0, gj0, ring[K0 % 3]);
   const int li = tx + 1, lj = ty + 1;
-  for (int k = K0; k < K1; ++k) {
-    helm_load_plane(g, d, k + 1, gi0, gj0, ring[(k + 1) % 3]);
-    // the node's own iterate and residual, loaded before the barrier so that their latency
-    // overlaps the wait
-    const int n = own ? g.node(i, j, k) : 0;
-    const double yn = own ? y[n] : 0.0, rn0 = own ? r[n] : 0.0;
-    __syncthreads();
-    if (own) {
-      double acc = 0.0;
 #pragma unroll
-      for (int oz = -1; oz <= 1; ++oz) {
-        const double cz = oz == 0 ? ((k > 0 && k < g.nz) ? 2.0 : 1.0) : ((k + oz >= 0 && k + oz <= g.nz) ? 1.0 : 0.0);
-        const double* pl = ring[(k + oz + 3) % 3];
+  for (int p = 0; p < CT_Z; ++p) {
+    if (p >= nk) break;
+    const int k = K0 + p;
+    double acc = 0.0;
 #pragma unroll
-        for (int oy = -1; oy <= 1; ++oy)
+    for (int oz = -1; oz <= 1; ++oz) {
+      const double cz = oz == 0 ? ((k > 0 && k < g.nz) ? 2.0 : 1.0) : ((k + oz >= 0 && k + oz <= g.nz) ? 1.0 : 0.0);
+      const double* pl = buf[p + 1 + oz];
 #pragma unroll
-          for (int ox = -1; ox <= 1; ++ox) {
-            const int p = (ox == 0) + 2 * (oy == 0) + 4 * (oz == 0);
-            acc += cz * cxy[oy + 1][ox + 1] * c.a[p] * pl[(li + ox) + CT_LX * (lj + oy)];
-          }
-      }
-      const double dn = ring[k % 3][li + CT_LX * lj];
-      const double diag = cxy[1][1] * ((k > 0 && k < g.nz) ? 2.0 : 1.0) * c.a[7];
-      y[n] = yn + dn;
-      const double rn = rn0 - acc;
-      r[n] = rn;
-      d_next[n] = c1 * dn + c2 * rn / diag;
+      for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int e = (ox == 0) + 2 * (oy == 0) + 4 * (oz == 0);
+          acc += cz * cxy[oy + 1][ox + 1] * c.a[e] * pl[(li + ox) + CT_LX * (lj + oy)];
+        }
     }
-    __syncthreads();
+    const double dn = buf[p + 1][li + CT_LX * lj];
+    const double diag = cxy[1][1] * ((k > 0 && k < g.nz) ? 2.0 : 1.0) * c.a[7];
+    const int n = g.node(i, j, k);
+    y[n] = yv[p] + dn;
+    const double rn = rv[p] - acc;
+    r[n] = rn;
+    d_next[n] = c1 * dn + c2 * rn / diag;
   }
 }
 
@@ -267,13 +289,13 @@ void launch_pde_filter(hipStream_t st, const Grid& g, const HelmholtzPlan& pl, c
   const double h3 = pl.h * pl.h * pl.h;
   launch(helm_init_kernel, dim3(blocks_for(N)), dim3(BS), 0, st, ng, h3 / 8.0, c.a[7], 1.0 / theta, x, yy, rr, d0);
   double rho = 1.0 / sigma1;
-  // tiles of CT_X x CT_Y node columns times z chunks of about 4 node planes
+  // tiles of CT_X x CT_Y node columns times z chunks of CT_Z node planes
   const int tiles = ((g.nx + CT_X) / CT_X) * ((g.ny + CT_Y) / CT_Y);
-  const int chunks = std::max(1, std::min(g.nz + 1, (g.nz + 1 + 3) / 4));
+  const int chunks = (g.nz + CT_Z) / CT_Z;
   for (int s = 0; s < pl.steps; ++s) {
     const double rho_next = 1.0 / (2.0 * sigma1 - rho);
     launch(helm_cheb_tiled_kernel, dim3((unsigned)(tiles * chunks)), dim3(CT_X * CT_Y), 0, st, g, c, rho_next * rho,
-           2.0 * rho_next / delta, chunks, (const double*)d0, d1, yy, rr);
+           2.0 * rho_next / delta, tiles, (const double*)d0, d1, yy, rr);
     rho = rho_next;
     std::swap(d0, d1);
   }
