@@ -111,6 +111,16 @@ typedef struct nc_problem {
                                  strongly convective blocks); the stalled solve is redone.
                                  Only a stronger damping than the current one is taken over.
                                  0: no fallback                                          */
+  int    f64_krylov_fallback; /* NC_MIXED, 1: the workspace also holds a float64 Krylov basis
+                                 (krylov_restart + 1 vectors and as many preconditioned ones);
+                                 a float32 Krylov solve that ends unconverged is redone with
+                                 float64 vectors and operator, preconditioned by the float32
+                                 V-cycle, and the context keeps that for good (nc_info
+                                 krylov_f64).  Where the V-cycle amplifies a few directions by
+                                 orders of magnitude (a solid region whose permeability is far
+                                 below the fluid's, in the convective regime) float32 rounding
+                                 of the basis and of the operator reaches the size of the
+                                 residual.  0: no reserve, no fallback; ignored in NC_FP64  */
 } nc_problem;
 
 #define NC_HIST_MAX 32  /* Newton steps / refinement sweeps recorded in nc_info */
@@ -134,6 +144,10 @@ typedef struct nc_info {
   int    hist_krylov[NC_HIST_MAX];   /* FGMRES iterations of each Newton step (state) or
                                         refinement sweep (adjoint)                        */
   double hist_res[NC_HIST_MAX][5];   /* residual 2-norm per field after that step / sweep */
+  int    krylov_f64;          /* NC_MIXED with f64_krylov_fallback: 1 once a float32 Krylov
+                                 solve of this context has ended unconverged; from then on
+                                 (until nc_set_problem) its Krylov vectors and operator are
+                                 float64, preconditioned by the float32 V-cycle.  0 otherwise */
 } nc_info;
 
 typedef struct nc_ctx nc_ctx;

@@ -520,6 +520,20 @@ void launch_scale2(hipStream_t st, long nodes, const Ta* in, Tb* out, double s_p
                      s_p, s_t);
 }
 
+template <typename Ta, typename Tb>
+__global__ void normalize_copy_kernel(const double* __restrict__ nrm, Ta* v, Tb* __restrict__ out, long n) {
+  const double s = nrm ? 1.0 / nrm[0] : 1.0;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const Ta a = nrm ? (Ta)(s * (double)v[t]) : v[t];
+    if (nrm) v[t] = a;
+    out[t] = (Tb)a;
+  }
+}
+template <typename Ta, typename Tb>
+void launch_normalize_copy(hipStream_t st, const double* nrm, Ta* v, Tb* out, long n) {
+  launch((normalize_copy_kernel<Ta, Tb>), dim3(std::min(blocks_for(n), 4096)), dim3(BS), 0, st, nrm, v, out, n);
+}
+
 template <typename T>
 __global__ void unpack_pt_kernel(Grid g, const T* __restrict__ x, double* __restrict__ out5) {
   const PlaneIdx q = plane_idx(g);
@@ -1378,5 +1392,6 @@ template void launch_convert<float, float>(hipStream_t, const float*, float*, lo
 template void launch_scale2<double, float>(hipStream_t, long, const double*, float*, double, double);
 template void launch_scale2<float, double>(hipStream_t, long, const float*, double*, double, double);
 template void launch_scale2<double, double>(hipStream_t, long, const double*, double*, double, double);
+template void launch_normalize_copy<double, float>(hipStream_t, const double*, double*, float*, long);
 
 }  // namespace nc

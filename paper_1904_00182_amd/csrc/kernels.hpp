@@ -87,6 +87,9 @@ void launch_pack_pt(hipStream_t st, long nodes, const double* r5, T* out, double
 // out[n][f] = s_f * in[n][f] for two-field vectors, converting precision
 template <typename Ta, typename Tb>
 void launch_scale2(hipStream_t st, long nodes, const Ta* in, Tb* out, double s_p, double s_t);
+// v <- v / nrm[0] in place (when nrm is not null; nrm on the device) and out = v rounded to Tb
+template <typename Ta, typename Tb>
+void launch_normalize_copy(hipStream_t st, const double* nrm, Ta* v, Tb* out, long n);
 // out5[n][3 + f] = x[n][f] (free dofs) or 0 (constrained dofs); velocity entries untouched
 template <typename T>
 void launch_unpack_pt(hipStream_t st, const Grid& g, const T* x, double* out5);

@@ -584,6 +584,7 @@ int newton(nc_ns_ctx* c, double* s, nc_info* info) {
     info->newton_its = it;
     info->krylov_its = ktot;
     info->levels = c->L;
+    info->krylov_f64 = 0;
     info->rel_res = relres;
     double fr[10];
     field_norms(c, c->R, nullptr, fr);
@@ -613,6 +614,7 @@ int adjoint(nc_ns_ctx* c, const double* s, const double* rhs, double* lam, nc_in
     for (int f = 0; f < 5; ++f) info->res[f] = rr[f];
     info->krylov_its = its;
     info->levels = c->L;
+    info->krylov_f64 = 0;
     info->rel_res = relres;
     info->hist_len = 1;
     info->hist_krylov[0] = its;

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -130,6 +131,11 @@ struct nc_ctx {
   bool rows_valid;       // rows64 / rows32 and res_floor computed for this design
   double res_floor;      // round-off floor of the scaled residual
   double omega;          // block-Jacobi damping in use: smooth_omega, or the fallback after a stall
+  bool k64;              // NC_MIXED: Krylov vectors and operator in float64 (float32 V-cycle) after a
+                         // float32 Krylov solve failed to converge
+  bool reserve64;        // V64 / Z64 hold a float64 Krylov basis for that fallback
+  double* V64;
+  double* Z64;
   // optional event timing per kernel class
   bool timing;
   std::vector<hipEvent_t> ev;
@@ -313,6 +319,10 @@ size_t carve(nc_ctx* c, char* base) {
   c->ld = (2 * c->N + 63) / 64 * 64;   // Krylov vectors: the (P, T) system
   c->V = cv.take<char>((size_t)(c->m + 1) * c->ld * rs);
   c->Z = cv.take<char>((size_t)c->m * c->ld * rs);
+  const bool reserve64 = c->mixed && p.f64_krylov_fallback != 0;
+  c->V64 = cv.take<double>(reserve64 ? (size_t)(c->m + 1) * c->ld : 1);
+  c->Z64 = cv.take<double>(reserve64 ? (size_t)c->m * c->ld : 1);
+  c->reserve64 = reserve64;
   c->kx = cv.take<char>(2 * c->N * rs);
   c->kb = cv.take<char>(2 * c->N * rs);
   c->pt64 = cv.take<double>(2 * c->N);
@@ -588,14 +598,18 @@ constexpr int HSLOT = 2 * MAXC + 8;   // doubles per Hessenberg slot: h1 [MAXC],
 // discarded.
 bool debug_on();
 
-template <typename T>
+//
+// T is the precision of the Krylov vectors and of the operator, TP that of the V-cycle (a
+// float64 basis with the float32 V-cycle is the NC_MIXED fallback, in its own reserve).
+template <typename T, typename TP = T>
 int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double* relres, bool* stalled = nullptr) {
   hipStream_t st = c->stream;
   const Scale5<T>* rows = row_scales<T>(c);
   const long n = 2 * c->N, ld = c->ld;
   const int m = c->m;
-  T* V = (T*)c->V;
-  T* Z = (T*)c->Z;
+  constexpr bool split = !std::is_same<T, TP>::value;
+  T* V = split ? (T*)c->V64 : (T*)c->V;
+  T* Z = split ? (T*)c->Z64 : (T*)c->Z;
   double* dres = c->dres;
   ck(hipMemsetAsync(x, 0, sizeof(T) * n, st));
   // |b| also goes to the pinned slot after the Hessenberg slots; the host reads it with
@@ -615,7 +629,23 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
     T* w = V + (long)(j + 1) * ld;
     T* zj = Z + (long)j * ld;
     // v_j arrives unnormalised from step j-1 (its norm is still in dres); step 0's is normal
-    precondition_pt<T>(c, tr, vj, zj, rows, j > 0 ? dres + 2 * MAXC : nullptr);
+    if constexpr (std::is_same<T, TP>::value) {
+      precondition_pt<T>(c, tr, vj, zj, rows, j > 0 ? dres + 2 * MAXC : nullptr);
+    } else {
+      // normalise v_j in place and round a copy to the V-cycle's precision; the cycle's
+      // result is widened into z_j (kb and kx are free: b and x are float64 here)
+      TP* pv = (TP*)c->kb;
+      TP* pz = (TP*)c->kx;
+      {
+        Timed tm(c, TC_VECTOR, (double)(2 * sizeof(T) + sizeof(TP)) * n);
+        launch_normalize_copy<T, TP>(st, j > 0 ? dres + 2 * MAXC : nullptr, vj, pv, n);
+      }
+      precondition_pt<TP>(c, tr, pv, pz, row_scales<TP>(c), nullptr);
+      {
+        Timed tm(c, TC_VECTOR, (double)(sizeof(T) + sizeof(TP)) * n);
+        launch_scale2<TP, T>(st, c->N, pz, zj, 1.0, 1.0);
+      }
+    }
     apply_pt<T>(c, tr, zj, w, rows);
     // the reductions store the Hessenberg column into the step's pinned slot as well
     double* hs = c->hslots + (size_t)j * HSLOT;
@@ -724,6 +754,8 @@ int fgmres(nc_ctx* c, bool tr, const T* b, T* x, double rtol, int maxit, double*
     launch_norm<T>(st, V, n, c->part, dres);
     fetch(c, dres, 1);
     beta = c->hbuf[0];
+    if (debug_on())
+      std::fprintf(stderr, "nc fgmres restart after %d: recurrence %.2e true %.2e\n", total, *relres, beta / bnorm);
     *relres = beta / bnorm;
     if (beta / bnorm <= rtol) break;
     launch_scale_inv<T>(st, dres, V, V, n);
@@ -758,17 +790,54 @@ int reduced_solve(nc_ctx* c, bool tr, const double* r, double* d, bool krylov, d
   int its = 0;
   if (krylov) {
     bool stalled = false;
-    its = fgmres<T>(c, tr, kb, kx, rtol, c->p.krylov_maxit, relres,
-                    c->p.smooth_omega_fallback > 0.0 && c->p.smooth_omega_fallback < c->omega ? &stalled : nullptr);
-    if (its < 0) return its;
-    if (stalled) {
-      // switch this context to the fallback damping for good and solve again from zero
-      if (debug_on()) std::fprintf(stderr, "nc fgmres stalled (relres %.2e): block-Jacobi damping %g -> %g\n", *relres,
-                                   c->omega, c->p.smooth_omega_fallback);
-      c->omega = c->p.smooth_omega_fallback;
-      const int more = fgmres<T>(c, tr, kb, kx, rtol, c->p.krylov_maxit, relres);
-      if (more < 0) return more;
-      its += more;
+    if (!c->k64) {
+      const bool damp = c->p.smooth_omega_fallback > 0.0 && c->p.smooth_omega_fallback < c->omega;
+      its = fgmres<T>(c, tr, kb, kx, rtol, c->p.krylov_maxit, relres, damp || c->reserve64 ? &stalled : nullptr);
+      if (its < 0) return its;
+      if (stalled && damp) {
+        stalled = false;
+        // switch this context to the fallback damping for good and solve again from zero
+        if (debug_on()) std::fprintf(stderr, "nc fgmres stalled (relres %.2e): block-Jacobi damping %g -> %g\n", *relres,
+                                     c->omega, c->p.smooth_omega_fallback);
+        c->omega = c->p.smooth_omega_fallback;
+        const int more = fgmres<T>(c, tr, kb, kx, rtol, c->p.krylov_maxit, relres);
+        if (more < 0) return more;
+        its += more;
+      }
+    }
+    if constexpr (sizeof(T) < sizeof(double)) {
+      // A float32 Krylov solve that ends unconverged: where the V-cycle amplifies a few
+      // directions by orders of magnitude (the pressure inside a solid region whose
+      // permeability is 1e5 below the fluid's, which the per-field row scales do not see),
+      // the float32 rounding of the basis and of the operator is of the size of the
+      // residual itself.  With the reserve, the context then keeps float64 Krylov vectors
+      // and a float64 operator for good, with the float32 V-cycle as the preconditioner.
+      // (a first restart cycle that did not halve the residual, with no stronger damping
+      // left to try, takes the same way at once)
+      if (c->reserve64 && (c->k64 || stalled || (*relres > rtol && its >= c->p.krylov_maxit))) {
+        if (!c->k64 && debug_on())
+          std::fprintf(stderr, "nc fgmres float32 unconverged (relres %.2e): float64 Krylov from now on\n", *relres);
+        c->k64 = true;
+        double* b64 = c->tmp5;   // free during a linear solve
+        if (!tr) {
+          Timed tm(c, TC_VECTOR, vbytes);
+          launch_pack_pt<double>(st, c->N, r, b64, sp, stt);
+        } else {
+          Timed tm(c, TC_VECTOR, vbytes);
+          launch_scale2<double, double>(st, c->N, c->pt64, b64, sp, stt);
+        }
+        const int more = fgmres<double, T>(c, tr, b64, c->pt64, rtol, c->p.krylov_maxit, relres);
+        if (more < 0) return more;
+        its += more;
+        if (!tr) {
+          Timed tm(c, TC_UPROJ, ubytes);
+          launch_uproj<double>(st, v64, c->pt64, r, d, nullptr);
+        } else {
+          Timed tm(c, TC_VECTOR, vbytes);
+          launch_unpack_pt<double>(st, L0.g, c->pt64, d);
+        }
+        return its;
+      }
     }
   } else {
     precondition_pt<T>(c, tr, kb, kx, nullptr);
@@ -965,6 +1034,7 @@ int newton(nc_ctx* c, double* s, nc_info* info) {
     info->krylov_its = kits;
     info->refine_its = 0;
     info->levels = c->L;
+    info->krylov_f64 = c->k64 ? 1 : 0;
     info->rel_res = relres;
     launch_field_norms(st, c->R, nullptr, c->N, c->part, c->dres);
     fetch(c, c->dres, 5);
@@ -990,6 +1060,7 @@ int adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info*
     info->hist_len = 0;
     info->newton_its = info->krylov_its = info->refine_its = 0;
     info->levels = c->L;
+    info->krylov_f64 = c->k64 ? 1 : 0;
     info->rel_res = bn == 0.0 ? 0.0 : 1.0;
   }
   ck(hipMemsetAsync(lam, 0, sizeof(double) * c->n5, st));
@@ -1054,6 +1125,7 @@ int adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info*
     info->krylov_its = kits;
     info->refine_its = ref;
     info->levels = c->L;
+    info->krylov_f64 = c->k64 ? 1 : 0;
     info->rel_res = rel;
     launch_field_norms(st, c->R, nullptr, c->N, c->part, c->dres);
     fetch(c, c->dres, 5);
@@ -1142,6 +1214,7 @@ void nc_problem_default(nc_problem* p, int nx, int ny, int nz) {
   p->smooth_post = 2;
   p->smooth_omega = 1.0;
   p->smooth_omega_fallback = 0.7;
+  p->f64_krylov_fallback = 0;
   p->smooth_pre_coarse = 1;
   p->smooth_post_coarse = 1;
   p->filter_kind = NC_FILTER_CONE;
@@ -1199,6 +1272,7 @@ int nc_create(const nc_problem* p, void* workspace_dev, size_t bytes, void* stre
     c->design_set = false;
     c->hier_valid = false;
     c->omega = c->p.smooth_omega;
+    c->k64 = false;
     c->timing = false;
     c->ev_used = 0;
     c->join_pending = c->join2_pending = false;
@@ -1250,6 +1324,7 @@ int nc_set_problem(nc_ctx* c, const nc_problem* p) {
     carve(c, c->ws_base);   // the same layout: recomputes the level constants and regions only
     c->patch = Patch{c->p.q_h, c->p.patch_x0, c->p.patch_x1, c->p.patch_y0, c->p.patch_y1, c->p.h};
     c->omega = c->p.smooth_omega;
+    c->k64 = false;
     c->design_set = false;
     c->hier_valid = false;
     c->rows_valid = false;

@@ -60,7 +60,7 @@ class NCProblem(ctypes.Structure):
         ("filter_kind", ctypes.c_int),
         ("sym_x", ctypes.c_int), ("sym_y", ctypes.c_int),
         ("q_box", ctypes.c_double * 6), ("solid_box", ctypes.c_double * 6), ("design_box", ctypes.c_double * 6),
-        ("smooth_omega_fallback", ctypes.c_double),
+        ("smooth_omega_fallback", ctypes.c_double), ("f64_krylov_fallback", ctypes.c_int),
     ]
 
 
@@ -71,7 +71,7 @@ class NCInfo(ctypes.Structure):
         ("res0", ctypes.c_double * 5), ("res", ctypes.c_double * 5), ("rel_res", ctypes.c_double),
         ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double), ("t_total", ctypes.c_double),
         ("hist_len", ctypes.c_int), ("hist_krylov", ctypes.c_int * NC_HIST_MAX),
-        ("hist_res", (ctypes.c_double * 5) * NC_HIST_MAX),
+        ("hist_res", (ctypes.c_double * 5) * NC_HIST_MAX), ("krylov_f64", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -79,7 +79,8 @@ class NCInfo(ctypes.Structure):
         return {"newton_its": self.newton_its, "krylov_its": self.krylov_its, "refine_its": self.refine_its,
                 "levels": self.levels, "res0": list(self.res0), "res": list(self.res), "rel_res": self.rel_res,
                 "t_setup": self.t_setup, "t_solve": self.t_solve, "t_total": self.t_total,
-                "hist_krylov": list(self.hist_krylov[:n]), "hist_res": [list(self.hist_res[k]) for k in range(n)]}
+                "hist_krylov": list(self.hist_krylov[:n]), "hist_res": [list(self.hist_res[k]) for k in range(n)],
+                "krylov_f64": self.krylov_f64}
 
 
 _LIB = None

@@ -169,3 +169,38 @@ def test_cold_solves_at_gr_1e6_with_the_convective_smoothing(n, kappa_s, precisi
     assert info["newton_its"] <= 12
     r = sol.residual(s).cpu().numpy()
     assert np.linalg.norm(r[:, 4]) <= 1e-11 * info["res0"][4]
+
+
+@pytest.mark.parametrize("n,kappa_s", [(16, 1e-5), (16, 1e-7), (24, 1e-5)])
+def test_mixed_precision_at_gr_1e6_goes_on_in_float64_krylov(n, kappa_s):
+    """Mixed precision, cold, at alpha 1e6 on grids where the heat-source block is one or two
+    elements wide: the float32 Krylov solves stagnate (the V-cycle amplifies the pressure
+    inside the solid block), the context switches to float64 Krylov vectors and operator
+    with the float32 V-cycle (the reserve the benchmark problem asks for in this regime),
+    and state and adjoint match the float64 solve; without the reserve the mixed solve
+    reports that it did not converge."""
+    print("gr1e6 mixed", n, kappa_s, flush=True)
+    x = None
+    res = {}
+    for precision in (nc.NC_FP64, nc.NC_MIXED):
+        p = workloads.benchmark_problem(n, 1e6, precision, kappa_s=kappa_s)
+        sol = nc.Solver(p, DEV)
+        x = workloads.benchmark_start_design(p, DEV)
+        sol.set_design(x)
+        s = sol.solve_state()
+        info = sol.last_info
+        print(precision, "newton", info["newton_its"], "fgmres per step", info["hist_krylov"], "f64", info["krylov_f64"],
+              flush=True)
+        assert info["status"] == nc.NC_OK, info
+        assert info["krylov_f64"] == (1 if precision == nc.NC_MIXED else 0)
+        lam = sol.solve_adjoint(s, sol.objective_grad(s))
+        assert sol.last_info["status"] == nc.NC_OK, sol.last_info
+        res[precision] = (s.cpu().numpy(), lam.cpu().numpy())
+        sol.close()
+    check_fields(res[nc.NC_MIXED][0], res[nc.NC_FP64][0], 1e-9, "gr1e6 mixed state")
+    check_fields(res[nc.NC_MIXED][1], res[nc.NC_FP64][1], 1e-8, "gr1e6 mixed adjoint")
+    p = workloads.benchmark_problem(n, 1e6, nc.NC_MIXED, kappa_s=kappa_s, f64_krylov_fallback=0, newton_maxit=12)
+    sol = nc.Solver(p, DEV)
+    sol.set_design(x)
+    sol.solve_state()
+    assert sol.last_info["status"] == nc.NC_NOT_CONVERGED and sol.last_info["krylov_f64"] == 0, sol.last_info
