@@ -284,14 +284,15 @@ def design_loop_timing(args):
     passive regions, PDE filter R = 2.5, constant penalties q_c = 8.81, q_p = 8 (as in that
     study), kappa_s = 1e-5, from the paper's initial design 0.05.  Each iteration: design
     chain, warm-started Newton state solve, adjoint, sensitivities, volume constraint, MMA.
-    Gr 1e3 in mixed precision, Gr 1e6 in float64."""
+    Gr 1e3 in mixed precision, Gr 1e6 in float64 and in mixed precision (with the float64
+    Krylov reserve of that regime)."""
     import torch
     from paper_1904_00182_amd import design, nc, workloads
     dev = "cuda:0"
     out = {"workload": "quarter cavity 80x80x160 of the paper's benchmark (Sec. 6.1), Q = 1e4 block, PDE filter R = 2.5, "
                        "q_c = 8.81, q_p = 8, kappa_s = 1e-5, g* = 0.05, move 0.2, start 0.05",
            "iterations": args.design_iters}
-    for alpha, prec in ((1e3, nc.NC_MIXED), (1e6, nc.NC_FP64)):
+    for alpha, prec in ((1e3, nc.NC_MIXED), (1e6, nc.NC_FP64), (1e6, nc.NC_MIXED)):
         p = workloads.benchmark_problem(80, alpha, prec, kappa_s=1e-5, q_c=8.81, q_p=8.0)
         x0 = workloads.benchmark_start_design(p, dev)
         torch.cuda.synchronize()
@@ -301,7 +302,7 @@ def design_loop_timing(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         warm = hist[1:]
-        key = f"gr{alpha:g}"
+        key = f"gr{alpha:g}" + ("_mixed" if alpha >= 1e5 and prec == nc.NC_MIXED else "")
         out[key] = {
             "precision": "f32+f64" if prec == nc.NC_MIXED else "f64",
             "s_per_iteration": round(sum(h["seconds"] for h in warm) / len(warm), 4),
@@ -311,6 +312,7 @@ def design_loop_timing(args):
             "newton_per_iteration_warm": round(sum(h["newton"] for h in warm) / len(warm), 2),
             "fgmres_per_newton_step_warm": round(sum(h["state_krylov"] for h in warm) / max(1, sum(h["newton"] for h in warm)), 2),
             "ramped": sum(1 for h in hist if h["ramped"]),
+            "float64_krylov_from_iteration": next((h["it"] for h in hist if h["krylov_f64"]), None),
             "f_first_last": [hist[0]["f"], hist[-1]["f"]],
             "volume_last": hist[-1]["frac"],
             "wall_s": round(wall, 3),

@@ -117,7 +117,8 @@ def optimize(problem, x0, iterations, g_star=0.05, move=0.2, every=100, continua
         torch.cuda.synchronize(sol.device)
         h = dict(it=it, model=kind, f=f, frac=frac, lam=mult, ramped=ramped, newton=info["newton_its"],
                  state_krylov=info["krylov_its"], adjoint_krylov=ainfo["krylov_its"], state_s=info["t_total"],
-                 adjoint_s=ainfo["t_total"], seconds=time.perf_counter() - t0)
+                 adjoint_s=ainfo["t_total"], krylov_f64=max(info.get("krylov_f64", 0), ainfo.get("krylov_f64", 0)),
+                 seconds=time.perf_counter() - t0)
         if keep_designs:
             h["x"] = x.cpu().numpy().copy()
         hist.append(h)
