@@ -227,6 +227,7 @@ bool valid_problem(const nc_problem* p) {
   if (!(p->krylov_rtol > 0) || !(p->krylov_rtol_mixed > 0) || !(p->adjoint_rtol > 0)) return false;
   if (p->gs_passes != 1 && p->gs_passes != 2) return false;
   if (p->coarse_tail != 0 && p->coarse_tail != 1) return false;
+  if (p->f64_krylov_fallback != 0 && p->f64_krylov_fallback != 1) return false;
   if (!(p->newton_eta0 >= 0.0 && p->newton_eta0 < 1.0)) return false;
   if (p->smooth_pre < 1 || p->smooth_post < 0 || p->smooth_pre_coarse < 1 || p->smooth_post_coarse < 0) return false;
   if (!(p->smooth_omega > 0.0 && p->smooth_omega <= 2.0) || !(p->smooth_omega_fallback >= 0.0 && p->smooth_omega_fallback <= 2.0))

@@ -46,9 +46,17 @@ def test_host_only_entry_points():
     assert nc.workspace_bytes(pm) < nc.workspace_bytes(p64)
     bad = nc.default_problem(16, 8, 16, krylov_restart=0)
     assert nc.workspace_bytes(bad) == 0
-    for field, value in (("newton_eta0", 1.0), ("newton_eta0", -1e-3), ("coarse_tail", 2), ("gs_passes", 3)):
+    for field, value in (("newton_eta0", 1.0), ("newton_eta0", -1e-3), ("coarse_tail", 2), ("gs_passes", 3),
+                         ("f64_krylov_fallback", 2)):
         assert nc.workspace_bytes(nc.default_problem(16, 8, 16, **{field: value})) == 0, field
-    assert p.newton_eta0 == 3e-3 and p.coarse_tail == 1 and p.gs_passes == 1
+    assert p.newton_eta0 == 3e-3 and p.coarse_tail == 1 and p.gs_passes == 1 and p.f64_krylov_fallback == 0
+    # the float64 Krylov reserve: krylov_restart + 1 basis and krylov_restart preconditioned
+    # vectors of 2N float64 each (stride rounded to 64), in NC_MIXED only
+    pr = nc.default_problem(64, 32, 64, precision=nc.NC_MIXED, f64_krylov_fallback=1)
+    ld = (2 * 65 * 33 * 65 + 63) // 64 * 64
+    extra = nc.workspace_bytes(pr) - nc.workspace_bytes(pm)
+    assert abs(extra - 8 * (2 * pm.krylov_restart + 1) * ld) <= 1024, extra
+    assert nc.workspace_bytes(nc.default_problem(64, 32, 64, f64_krylov_fallback=1)) == nc.workspace_bytes(p64)
     # size limits: fewer than 2^31 / 5 nodes, and a z-layer of a five-field float64 array
     # below 4 GiB (the operator kernels address a layer with 32-bit byte offsets)
     assert nc.workspace_bytes(nc.default_problem(2048, 2048, 128)) == 0
