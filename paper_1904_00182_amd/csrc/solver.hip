@@ -853,6 +853,23 @@ int reduced_solve(nc_ctx* c, bool tr, const double* r, double* d, bool krylov, d
   return its;
 }
 
+// Relative residual, in float64 and with the Krylov row scales, of the (P, T) part of the
+// last linear solve J~ d = r (its (P, T) solution is still in pt64).
+double pt_true_relres(nc_ctx* c, const double* r) {
+  hipStream_t st = c->stream;
+  const long n = 2 * c->N;
+  double* b64 = c->tmp5;       // D r_PT
+  double* w64 = c->tmp5 + n;   // D A d_PT, then D (r_PT - A d_PT)
+  launch_pack_pt<double>(st, c->N, r, b64, c->krow64.s[3], c->krow64.s[4]);
+  apply_pt<double>(c, false, c->pt64, w64, &c->krow64);
+  launch_norm<double>(st, b64, n, c->part, c->dres + 3 * MAXC);
+  launch_rsub<double>(st, b64, w64, n);
+  launch_norm<double>(st, w64, n, c->part, c->dres + 3 * MAXC + 1);
+  ck(hipMemcpyAsync(c->hbuf, c->dres + 3 * MAXC, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  sync(c);
+  return c->hbuf[0] > 0.0 ? c->hbuf[1] / c->hbuf[0] : 0.0;
+}
+
 int linear_solve(nc_ctx* c, bool tr, const double* r, double* d, double rtol, double* relres) {
   return c->mixed ? reduced_solve<float>(c, tr, r, d, true, rtol, relres)
                   : reduced_solve<double>(c, tr, r, d, true, rtol, relres);
@@ -964,8 +981,22 @@ int newton(nc_ctx* c, double* s, nc_info* info) {
     // from the guess to near the root) or when the last solve needed many more iterations
     const bool rebuild = it < 2 || !c->hier_valid;
     linearize(c, s, rebuild);
-    const int its = linear_solve(c, false, c->R, c->d, eta, &relres);
+    int its = linear_solve(c, false, c->R, c->d, eta, &relres);
     if (its < 0) return NC_ENAN;
+    if (c->mixed && c->reserve64 && !c->k64) {
+      // the float32 solve's own residual can hide a float64 residual far above it (its
+      // operator's rounding, relative to a correction the V-cycle has amplified); then the
+      // step goes on in float64 Krylov, for good
+      const double rt = pt_true_relres(c, c->R);
+      if (!(rt <= 10.0 * std::max(relres, eta))) {
+        if (debug_on()) std::fprintf(stderr, "nc newton %d: float32 solve relres %.2e, float64 %.2e: float64 Krylov\n", it,
+                                     relres, rt);
+        c->k64 = true;
+        const int more = linear_solve(c, false, c->R, c->d, eta, &relres);
+        if (more < 0) return NC_ENAN;
+        its += more;
+      }
+    }
     if (it == 1) first_its = its;
     if (it >= 2 && its > 2 * first_its + 4) c->hier_valid = false;
     kits += its;
@@ -1117,7 +1148,14 @@ int adjoint(nc_ctx* c, const double* s, const double* rhs, double* lam, nc_info*
         ++ref;
         break;
       }
-      if (stalled && ref > 2) { ++ref; break; }
+      if (stalled && c->mixed && c->reserve64 && !c->k64) {
+        // float32 inner solves no longer reduce the float64 residual: float64 Krylov from here
+        if (debug_on()) std::fprintf(stderr, "nc adjoint sweep %d: refinement stalled, float64 Krylov\n", ref);
+        c->k64 = true;
+      } else if (stalled && ref > 2) {
+        ++ref;
+        break;
+      }
     }
     rel_prev = rel;
   }

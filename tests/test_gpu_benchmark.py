@@ -204,3 +204,27 @@ def test_mixed_precision_at_gr_1e6_goes_on_in_float64_krylov(n, kappa_s):
     sol.set_design(x)
     sol.solve_state()
     assert sol.last_info["status"] == nc.NC_NOT_CONVERGED and sol.last_info["krylov_f64"] == 0, sol.last_info
+
+
+@pytest.mark.parametrize("q_c", [0.881, 8.81])
+def test_mixed_cold_solve_at_gr_1e6_on_80x80x160_checks_its_float64_residual(q_c):
+    """The paper's performance-study mesh (1,024,000 elements), alpha 1e6, the first two
+    continuation stages' penalties, cold from the initial design at the full heat load: the
+    float32 Krylov solve's own residual hides a float64 residual far above it (the correction
+    carries the amplified pressure of the solid source block), the Newton step's float64
+    residual check switches the context to float64 Krylov, and the solve converges to the
+    float64 solve's root."""
+    from paper_1904_00182_amd import design
+    res = {}
+    for precision in (nc.NC_FP64, nc.NC_MIXED):
+        p = nc.copy_problem(workloads.benchmark_problem(80, 1e6, precision), q_c=q_c, q_p=8.0, kappa_s=1e-5)
+        sol = nc.Solver(p, DEV)
+        sol.set_design(workloads.benchmark_start_design(p, DEV))
+        s = sol.solve_state()
+        info = sol.last_info
+        print(precision, q_c, "newton", info["newton_its"], "fgmres", info["hist_krylov"], "f64", info["krylov_f64"],
+              flush=True)
+        assert info["status"] == nc.NC_OK and info["newton_its"] <= 10, info
+        res[precision] = s.cpu().numpy()
+        sol.close()
+    check_fields(res[nc.NC_MIXED], res[nc.NC_FP64], 1e-9, "80x80x160 gr1e6 mixed vs fp64")
