@@ -125,3 +125,34 @@ def optimize(problem, x0, iterations, g_star=0.05, move=0.2, every=100, continua
         if log:
             log(h)
     return x, s, hist
+
+
+def paper_optimisation(n, alpha, iterations=500, every=100, precision=nc.NC_MIXED, device="cuda:0", log=None):
+    """The optimisation of Sec. 6.3 on the benchmark of Sec. 6.1 with n x n x 2n elements of
+    the quarter cavity: the paper's initial design, eq. contsch1 advanced every `every`
+    iterations, g* = 0.05, move limit 0.2, the Table tab:2 permeability for alpha.  Returns
+    (final raw design, summary) with the thermal compliance of the quarter model and of the
+    full symmetric box (four quarters), the volume fraction, the share of design elements
+    with intermediate density (0.1 < gamma < 0.9), the iteration from which Krylov ran in
+    float64 (mixed precision), and the seconds taken."""
+    from . import workloads
+    p = workloads.benchmark_problem(n, alpha, precision)
+    x0 = workloads.benchmark_start_design(p, device)
+    torch.cuda.synchronize(device)
+    t0 = time.perf_counter()
+    x, _, hist = optimize(p, x0, iterations, every=every, continuation=CONTINUATION, device=device, log=log)
+    torch.cuda.synchronize(device)
+    wall = time.perf_counter() - t0
+    sol = nc.Solver(stage_problem(p, iterations - 1, every), device)
+    sol.set_design(x)
+    gam = sol.gamma()
+    _, dv = sol.volume()
+    design = dv != 0
+    gray = float(((gam > 0.1) & (gam < 0.9) & design).sum()) / max(1, int(design.sum()))
+    sol.close()
+    f = hist[-1]["f"]
+    return x, {"grid": [p.nx, p.ny, p.nz], "alpha": alpha, "iterations": iterations,
+               "precision": "f32+f64" if precision == nc.NC_MIXED else "f64",
+               "f_quarter": f, "f_full_box": 4.0 * f, "volume_fraction": hist[-1]["frac"], "gray_share": gray,
+               "float64_krylov_from_iteration": next((h["it"] for h in hist if h["krylov_f64"]), None),
+               "ramped_iterations": sum(1 for h in hist if h["ramped"]), "wall_s": wall}
