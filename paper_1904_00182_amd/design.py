@@ -156,3 +156,21 @@ def paper_optimisation(n, alpha, iterations=500, every=100, precision=nc.NC_MIXE
                "f_quarter": f, "f_full_box": 4.0 * f, "volume_fraction": hist[-1]["frac"], "gray_share": gray,
                "float64_krylov_from_iteration": next((h["it"] for h in hist if h["krylov_f64"]), None),
                "ramped_iterations": sum(1 for h in hist if h["ramped"]), "wall_s": wall}
+
+
+def paper_evaluate(n, alpha, x, precision=nc.NC_MIXED, device="cuda:0"):
+    """Compliance of the full box (four quarters) of the raw design x on the n x n x 2n
+    benchmark at alpha, with the penalties of the continuation's last stage: the cross-check
+    of optimised designs under every operating condition (Table tab:petscperformance).  The
+    state solve starts cold, with the Q ramp if Newton fails."""
+    from . import workloads
+    p = stage_problem(workloads.benchmark_problem(n, alpha, precision), len(CONTINUATION) - 1, 1)
+    sol = nc.Solver(p, device)
+    sol.set_design(x)
+    s = torch.zeros((sol.N, 5), dtype=torch.float64, device=device)
+    info, _ = solve_with_ramp(sol, p, x, s)
+    if info["status"] != nc.NC_OK:
+        raise RuntimeError(f"state solve failed evaluating a design at alpha {alpha:g}: {info}")
+    f = sol.objective(s)
+    sol.close()
+    return 4.0 * f
